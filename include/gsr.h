@@ -1,0 +1,259 @@
+/*
+ * gsr.h - 3D Gaussian Splatting render and backward pass for AMD MI355X
+ * (gfx950), with a per-wavefront choice between a register butterfly
+ * reduction plus one lane's atomics and plain per-lane global atomics.
+ *
+ * The calls follow the problem the paper (DISTWAR, arXiv 2401.05345) states
+ * for raster-based differentiable rendering: render a view of a set of
+ * learnable primitives, then propagate dL/dimage back to every parameter of
+ * every primitive that influenced the image (Background, the differentiable
+ * rendering training pipeline and the rasterisation pipeline figure; its
+ * steps 1-7). The backward accumulation is the paper's gradient-computation
+ * kernel (Motivation, outline of the gradient computation step); the
+ * per-wave reduction with a balancing threshold is its SW-B primitive
+ * (Detailed Design, "Butterfly Reduction (SW-B)", and Approach, "Scheduling
+ * Atomic Updates Between Core and L2"). The rendering math is the published
+ * 3D Gaussian Splatting method the paper instruments.
+ *
+ * Conventions
+ *  - Every array pointer is a DEVICE pointer (hipMalloc'd or a torch CUDA
+ *    tensor on the context's device) unless marked [host].
+ *  - All arrays are dense, row-major, fp32 unless stated; no strides.
+ *  - Every call that launches work enqueues it on the context's stream and
+ *    returns without waiting, except where "synchronises" is stated.
+ *  - No call throws; every call returns a gsr_status. On failure the
+ *    context's message (gsr_ctx_last_error) says why. Arguments are checked
+ *    on the host before anything is enqueued; on GSR_EINVAL nothing ran.
+ *  - A context is used by one host thread at a time.
+ */
+#ifndef GSR_H
+#define GSR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GSR_OK = 0,
+    GSR_EINVAL = -1,  /* bad argument; nothing was enqueued */
+    GSR_ENOMEM = -2,  /* device or pinned-host allocation failed */
+    GSR_EHIP = -3,    /* a HIP runtime call failed; message carries hipGetErrorString */
+    GSR_ESTATE = -4   /* object used in a wrong state (e.g. counters never collected) */
+} gsr_status;
+
+typedef enum {
+    GSR_BWD_PLAIN_ATOMIC = 0, /* every active lane issues its own 9 atomic adds */
+    GSR_BWD_WAVE_REDUCE = 1   /* butterfly + one lane's atomics when active lanes >= threshold */
+} gsr_bwd_mode;
+
+enum {
+    GSR_FLAG_DEBUG_COUNTERS = 1, /* backward counts wave-entries, active lanes and issued atomics */
+    GSR_FLAG_XCD_REMAP = 2,      /* composite kernels map consecutive blocks of one XCD to neighbouring tiles */
+    GSR_FLAG_STAGE_TIMING = 4,   /* record HIP events around each stage (gsr_ctx_stage_times) */
+    GSR_FLAG_LANE_SPLIT_ATOMICS = 8 /* reduce path: lanes 0..8 each issue one of the 9 sums in one instruction */
+};
+
+/* Number of floats reserved per Gaussian in the backward accumulators:
+ * (dL/du, dL/dv, dL/dA, dL/dB, dL/dC, dL/do, dL/dr, dL/dg, dL/db, pad...). */
+#define GSR_ACC_STRIDE 12
+
+/* Learnable scene. n >= 0; sh_degree 0..3, K = (sh_degree+1)^2 coefficients.
+ *  means3d [n,3], log_scales [n,3], quats [n,4] as (w,x,y,z) (need not be
+ *  unit length; normalised inside, gradients go through the normalisation),
+ *  opacity_logits [n], sh [n,K,3] (coefficient k = l*l + l + m, channel last). */
+typedef struct {
+    int32_t n;
+    int32_t sh_degree;
+    const float *means3d;
+    const float *log_scales;
+    const float *quats;
+    const float *opacity_logits;
+    const float *sh;
+} gsr_scene;
+
+/* Pinhole camera, OpenCV axes (+x right, +y down, +z forward). Pixel (x,y)
+ * is sampled at (x+0.5, y+0.5). world_to_cam [host] is the row-major 3x4
+ * [R|t]; R must be a rotation. Points with fp32 camera depth <= znear are
+ * culled. bg is the background colour. */
+typedef struct {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+    float world_to_cam[12];
+    float znear;
+    float bg[3];
+} gsr_camera;
+
+/* tile: 8, 16 or 32 (pixels per tile side; one workgroup of tile*tile
+ * threads per tile). lds_batch: 64, 128 or 256 Gaussian records staged in
+ * LDS per round, <= tile*tile. bwd_mode: gsr_bwd_mode. reduce_threshold
+ * 0..65: in GSR_BWD_WAVE_REDUCE a wave reduces iff its active-lane count is
+ * >= max(threshold, 1); 65 never reduces (same atomics as plain). flags:
+ * GSR_FLAG_* bits. */
+typedef struct {
+    int32_t tile;
+    int32_t lds_batch;
+    int32_t bwd_mode;
+    int32_t reduce_threshold;
+    int32_t flags;
+} gsr_config;
+
+/* Caller-owned gradient outputs, same shapes as the scene's arrays. */
+typedef struct {
+    float *means3d;
+    float *log_scales;
+    float *quats;
+    float *opacity_logits;
+    float *sh;
+} gsr_grads;
+
+typedef struct gsr_ctx gsr_ctx;
+typedef struct gsr_fwd gsr_fwd;
+
+/* Host-visible facts about a forward state (filled by a synchronising call). */
+typedef struct {
+    int64_t n;            /* Gaussians */
+    int64_t n_visible;    /* Gaussians with radius > 0 */
+    int64_t n_pairs;      /* P: (tile, Gaussian) pairs in the sorted lists */
+    int32_t grid_x, grid_y;
+    int32_t tile;
+} gsr_fwd_stats_t;
+
+/* Destinations for gsr_fwd_export; every pointer is a caller-owned device
+ * buffer or NULL to skip it. Sizes: n Gaussians, P pairs, G = grid_x*grid_y
+ * tiles, HW pixels.
+ *  mean2d [n,2], conic_opacity [n,4] (A,B,C,o), rgb [n,3], depth [n],
+ *  radius [n] int32 (0 = culled), tiles_touched [n] uint32,
+ *  clamp_mask [n] uint8 (bit c: colour channel c clamped at 0),
+ *  sorted_ids [P] uint32 (Gaussian per list entry, tile-major then depth),
+ *  ranges [G,2] uint32 half-open [start,end) into sorted_ids,
+ *  T_final [HW], n_contrib [HW] uint32 (1-based list position of the last
+ *  composited entry, 0 = none), acc [n,GSR_ACC_STRIDE] (accumulators of the
+ *  last backward). */
+typedef struct {
+    float *mean2d;
+    float *conic_opacity;
+    float *rgb;
+    float *depth;
+    int32_t *radius;
+    uint32_t *tiles_touched;
+    uint8_t *clamp_mask;
+    uint32_t *sorted_ids;
+    uint32_t *ranges;
+    float *T_final;
+    uint32_t *n_contrib;
+    float *acc;
+} gsr_fwd_export_t;
+
+/* Debug counters of the last backward run with GSR_FLAG_DEBUG_COUNTERS.
+ *  evaluated     E: (pixel, entry) pairs walked with entry <= n_contrib
+ *  active        A: pairs that contributed (the paper's participating threads)
+ *  wave_entries  (wave, entry) steps with at least one active lane
+ *  reduced       W_R: wave-entries that took the butterfly path
+ *  plain_lanes   A_<: active lanes of wave-entries that issued per-lane atomics
+ *  lane_atomics  atomic lane-operations issued (each lane of each atomic instruction)
+ *  atomic_instrs atomic instructions issued
+ *  hist[c]       wave-entries with c active lanes, c = 0..64 (c = 0 not counted) */
+typedef struct {
+    uint64_t evaluated, active, wave_entries, reduced, plain_lanes, lane_atomics, atomic_instrs;
+    uint64_t hist[65];
+} gsr_bwd_counters_t;
+
+/* Milliseconds of the stages of the last gsr_render / gsr_backward with
+ * GSR_FLAG_STAGE_TIMING (HIP events on the context stream). */
+typedef struct {
+    float preprocess, depth_sort, scan_emit, tile_sort, ranges, composite_fwd;
+    float zero_acc, composite_bwd, preprocess_bwd;
+} gsr_stage_times_t;
+
+/* Create a context on `device`. hip_stream: a hipStream_t to enqueue on, or
+ * NULL to create a stream of default priority owned by the context.
+ * Returns GSR_EINVAL for a bad device, GSR_EHIP on runtime failure. */
+gsr_status gsr_ctx_create(gsr_ctx **out, int device, void *hip_stream);
+
+/* Destroy a context and free all library-owned device memory. Waits for the
+ * stream to drain. Forward states must be released before. */
+void gsr_ctx_destroy(gsr_ctx *ctx);
+
+/* Message describing the last failure on this context ("" if none). The
+ * string is owned by the context and valid until the next call on it. */
+const char *gsr_ctx_last_error(const gsr_ctx *ctx);
+
+/* Replace the stream the context enqueues on (NULL = its own stream). */
+gsr_status gsr_ctx_set_stream(gsr_ctx *ctx, void *hip_stream);
+
+/* Forward pass (3DGS rasterisation: per-Gaussian projection, tile binning
+ * with a device radix sort on (tile, depth), front-to-back composite).
+ * image_chw [3,H,W] is written. *state_out receives a library-owned state
+ * holding the projected Gaussians, the sorted lists, per-tile ranges and
+ * per-pixel T_final / n_contrib; it borrows the scene's arrays, which must
+ * stay valid and unchanged until gsr_fwd_release. Synchronises once (the
+ * number of pairs is read back to size the sort buffers). n = 0 is valid:
+ * the image is bg. */
+gsr_status gsr_render(gsr_ctx *ctx, const gsr_scene *scene, const gsr_camera *camera,
+                      const gsr_config *config, float *image_chw, gsr_fwd **state_out);
+
+/* Backward pass for a forward state: walks every tile list in reverse,
+ * accumulates the nine per-Gaussian gradients (2D mean, conic, opacity,
+ * colour) with the configured reduction mode, then turns them into
+ * gradients of the raw parameters. dl_dimage_chw [3,H,W]. out: caller-owned
+ * gradients; accumulate = 0 overwrites, 1 adds. Culled Gaussians get 0 (or
+ * keep their value when accumulating). May be called several times per
+ * state, with any mode/threshold in `config` (NULL = the render config). */
+gsr_status gsr_backward(gsr_ctx *ctx, gsr_fwd *state, const float *dl_dimage_chw,
+                        const gsr_grads *out, int accumulate, const gsr_config *config);
+
+/* Only the composite part of the backward: fills the state's accumulators
+ * (exported as `acc`). Same arguments as gsr_backward. */
+gsr_status gsr_backward_composite(gsr_ctx *ctx, gsr_fwd *state, const float *dl_dimage_chw,
+                                  const gsr_config *config);
+
+/* Only the per-Gaussian part: raw-parameter gradients from the state's
+ * accumulators of the last gsr_backward_composite. */
+gsr_status gsr_backward_params(gsr_ctx *ctx, gsr_fwd *state, const gsr_grads *out, int accumulate);
+
+/* Release a forward state (its buffers return to the context's pool after
+ * the stream reaches this point). */
+gsr_status gsr_fwd_release(gsr_ctx *ctx, gsr_fwd *state);
+
+/* Host-side facts about a state; does not touch the device. */
+gsr_status gsr_fwd_stats(const gsr_fwd *state, gsr_fwd_stats_t *out);
+
+/* Copy intermediate results to caller buffers (device-to-device, async). */
+gsr_status gsr_fwd_export(gsr_ctx *ctx, const gsr_fwd *state, const gsr_fwd_export_t *dst);
+
+/* Read the debug counters of the last backward (synchronises). GSR_ESTATE if
+ * that backward did not run with GSR_FLAG_DEBUG_COUNTERS. */
+gsr_status gsr_bwd_counters(gsr_ctx *ctx, const gsr_fwd *state, gsr_bwd_counters_t *out);
+
+/* Stage times of the last render/backward with GSR_FLAG_STAGE_TIMING
+ * (synchronises on the events). */
+gsr_status gsr_ctx_stage_times(gsr_ctx *ctx, gsr_stage_times_t *out);
+
+/* L1 loss gradient (harness step, outside the timed backward):
+ * dl_dimage = sign(image - target) / count over `count` floats, sign(0) = 0. */
+gsr_status gsr_l1_grad(gsr_ctx *ctx, const float *image, const float *target, int64_t count, float *dl_dimage);
+
+/* Run the per-wave reduce-or-atomic primitive on synthetic data: wave w,
+ * lane l contributes vals[(w*64+l)*9 + k] to sums[k] (k < 9) when
+ * active[w*64+l] != 0. mode/threshold as in gsr_config. lane_atomics[0]
+ * receives the number of atomic lane-operations issued. sums [9] and
+ * lane_atomics [1] are zeroed by the call. */
+gsr_status gsr_wave_reduce_selftest(gsr_ctx *ctx, const float *vals, const uint8_t *active, int32_t n_waves,
+                                    int32_t mode, int32_t threshold, int32_t lane_split,
+                                    float *sums, uint64_t *lane_atomics);
+
+/* Host-only argument checks (no device needed); GSR_OK or GSR_EINVAL. */
+gsr_status gsr_validate_scene(const gsr_scene *scene);
+gsr_status gsr_validate_camera(const gsr_camera *camera);
+gsr_status gsr_validate_config(const gsr_config *config, const gsr_camera *camera);
+
+/* Library version string, e.g. "gsr 0.1 gfx950". */
+const char *gsr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSR_H */

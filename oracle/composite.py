@@ -55,7 +55,7 @@ def _raster():
     global _lib
     if _lib is None:
         lib = ctypes.CDLL(build_raster_lib())
-        lib.oracle_render.argtypes = [ctypes.POINTER(_Frame)] + [ctypes.c_void_p] * 5
+        lib.oracle_render.argtypes = [ctypes.POINTER(_Frame)] + [ctypes.c_void_p] * 6
         lib.oracle_render.restype = ctypes.c_int
         lib.oracle_backward.argtypes = [ctypes.POINTER(_Frame), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
         lib.oracle_backward.restype = ctypes.c_int
@@ -109,6 +109,7 @@ class RenderResult:
     n_contrib: np.ndarray  # int32 [H,W]
     margin: np.ndarray     # f64 [H,W] min relative distance of any per-pixel decision to its threshold
     signature: np.ndarray  # uint64 [H,W] hash of the composited entries and their clamp states
+    n_used: np.ndarray     # int32 [H,W] number of composited entries
     proj: Projected
     lists: TileLists
     cam: object
@@ -147,12 +148,13 @@ def render(scene, cam, tile: int = 16, tile_select: np.ndarray | None = None) ->
     n_contrib = np.zeros((H, W), np.int32)
     margin = np.full((H, W), np.inf)
     sig = np.zeros((H, W), np.uint64)
+    used = np.zeros((H, W), np.int32)
     keep = []
     f = _frame(proj, lists, cam, tile, tile_select, keep)
     rc = _raster().oracle_render(ctypes.byref(f), image.ctypes.data, T_final.ctypes.data,
-                                 n_contrib.ctypes.data, margin.ctypes.data, sig.ctypes.data)
+                                 n_contrib.ctypes.data, margin.ctypes.data, sig.ctypes.data, used.ctypes.data)
     assert rc == 0
-    return RenderResult(image, T_final, n_contrib, margin, sig, proj, lists, cam, tile, tile_select)
+    return RenderResult(image, T_final, n_contrib, margin, sig, used, proj, lists, cam, tile, tile_select)
 
 
 def composite_backward(rr: RenderResult, dl_dimage: np.ndarray) -> np.ndarray:

@@ -238,7 +238,9 @@ def project(scene, cam, tile: int = 16) -> Projected:
     out.tiles_touched[vis] = tiles[ok].astype(np.int64)
     raw = p["rgb_raw"].numpy()[ok]
     out.clamp_mask[vis] = ((raw[:, 0] < 0) * 1 + (raw[:, 1] < 0) * 2 + (raw[:, 2] < 0) * 4).astype(np.uint8)
-    out.geom_margin[vis] = gm[ok]
+    # Margins of every Gaussian in front of the camera, listed or not: an empty rectangle
+    # (off-screen splat) is a decision too.
+    out.geom_margin[idx] = np.where(det > 0, gm, np.inf)
     out.frustum_clamp[vis] = fcl[ok]
     return out
 

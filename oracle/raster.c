@@ -127,9 +127,9 @@ static int selected(const oracle_frame *f, int x, int y)
 
 /* image [3,H,W], T_final [H,W], n_contrib [H,W], margin [H,W], sig [H,W]
  * (may be NULL): a hash of which entries were composited and whether their
- * alpha was clamped. Pixels of unselected tiles are left untouched. */
+ * alpha was clamped; n_used [H,W] (may be NULL): number of composited entries. Pixels of unselected tiles are left untouched. */
 int oracle_render(const oracle_frame *f, double *image, double *T_final, int32_t *n_contrib, double *margin,
-                  uint64_t *sig)
+                  uint64_t *sig, int32_t *n_used)
 {
     int64_t hw = (int64_t)f->width * f->height;
     for (int y = 0; y < f->height; ++y)
@@ -137,7 +137,9 @@ int oracle_render(const oracle_frame *f, double *image, double *T_final, int32_t
             if (!selected(f, x, y)) continue;
             int64_t p = (int64_t)y * f->width + x;
             double col[3];
-            pixel_forward(f, x, y, NULL, col, &T_final[p], &n_contrib[p], &margin[p], sig ? &sig[p] : NULL);
+            int64_t used = pixel_forward(f, x, y, NULL, col, &T_final[p], &n_contrib[p], &margin[p],
+                                         sig ? &sig[p] : NULL);
+            if (n_used) n_used[p] = (int32_t)used;
             for (int c = 0; c < 3; ++c) image[c * hw + p] = col[c];
         }
     return 0;

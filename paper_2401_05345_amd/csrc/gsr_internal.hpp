@@ -1,0 +1,168 @@
+// Internal declarations shared by the HIP translation units of libgsr.
+// Device layouts (all in HBM, one allocation each, from the context pool):
+//   rec        [n][3] float4  (u, v, A, B) (C, o, r, g) (b, depth, 0, 0): the
+//              record each list entry gathers in the composite kernels
+//   radius     [n] int32, tiles_touched [n] uint32, clamp_mask [n] uint8
+//   depth_key  [n] uint32 (fp32 depth bits, 0xffffffff when culled), ids [n]
+//   offsets    [n] uint32 exclusive scan of tiles_touched in depth order
+//   pair_tile / pair_id [P] uint32 (+ alternates for the radix sort)
+//   ranges     [tiles] uint2, T_final [HW] f32, n_contrib [HW] uint32
+//   acc        [n][GSR_ACC_STRIDE] f32 backward accumulators
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "gsr.h"
+
+namespace gsr {
+
+// Camera as the kernels take it (by value).
+struct DevCamera {
+    int width, height, tile, grid_x, grid_y;
+    float fx, fy, cx, cy;
+    float R[9];        // world -> camera rotation, row-major
+    float t[3];
+    float centre[3];   // camera centre in world space, -R^T t
+    float znear;
+    float limx, limy;  // guard band of the projection Jacobian: 1.3 * half-extent / focal
+    float bg[3];
+};
+
+DevCamera make_dev_camera(const gsr_camera &c, int tile);
+
+// Caching device allocator: buffers return to per-size free lists and are
+// reused by later requests on the same (single) stream, so no hipFree or
+// hipMalloc runs in steady state.
+class Pool {
+public:
+    explicit Pool(int device) : device_(device) {}
+    ~Pool();
+    hipError_t alloc(void **p, size_t bytes);
+    void release(void *p);
+    size_t reserved() const { return reserved_; }
+private:
+    int device_;
+    std::multimap<size_t, void *> free_;
+    std::map<void *, size_t> live_;
+    size_t reserved_ = 0;
+};
+
+template <typename T>
+struct Buf {
+    T *p = nullptr;
+    size_t count = 0;
+};
+
+// Scratch for the scan / radix sort helpers.
+struct SortScratch {
+    uint32_t *hist = nullptr;     // digit histograms per block, then their exclusive scan
+    uint32_t *partials = nullptr; // per-block sums for multi-level scans
+    size_t hist_count = 0, partial_count = 0;
+};
+
+// ----- kernel launchers (defined in the .hip files) -----
+
+// a1: per-Gaussian projection (sh_degree 0..3).
+hipError_t launch_preprocess_fwd(const gsr_scene &s, const DevCamera &cam, float4 *rec, int32_t *radius,
+                                 uint32_t *tiles_touched, uint32_t *depth_key, uint32_t *ids, uint8_t *clamp_mask,
+                                 hipStream_t st);
+
+// a7: raw-parameter gradients from the accumulators.
+hipError_t launch_preprocess_bwd(const gsr_scene &s, const DevCamera &cam, const int32_t *radius, const float *acc,
+                                 const gsr_grads &out, int accumulate, hipStream_t st);
+
+// Exclusive scan of n uint32 values (in[gather[i]] when gather != nullptr).
+// total (device, may be nullptr) receives the sum. Scratch sized by scan_scratch_count.
+size_t scan_partial_count(int64_t n);
+hipError_t device_exclusive_scan(const uint32_t *in, const uint32_t *gather, uint32_t *out, int64_t n,
+                                 uint32_t *total, uint32_t *partials, hipStream_t st);
+
+// Stable LSD radix sort of (key, value) pairs on key bits [0, bits). Buffers
+// ping-pong between (k0,v0) and (k1,v1); returns the index (0/1) holding the
+// result in *which.
+size_t radix_hist_count(int64_t n);
+hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n, int bits,
+                            uint32_t *hist, uint32_t *partials, int *which, hipStream_t st);
+
+// a2: expand each depth-ordered Gaussian into its (tile, id) pairs.
+hipError_t launch_emit_pairs(int64_t n, const uint32_t *sorted_ids, const uint32_t *offsets, const float4 *rec,
+                             const int32_t *radius, const DevCamera &cam, uint32_t *pair_tile, uint32_t *pair_id,
+                             hipStream_t st);
+
+// a4: per-tile [start, end) ranges from tile-sorted pairs (ranges zero-filled first).
+hipError_t launch_tile_ranges(int64_t P, const uint32_t *sorted_tile, uint2 *ranges, int64_t n_tiles, hipStream_t st);
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream_t st);
+
+// out[0] = number of r[i] > 0.
+hipError_t launch_count_positive(const int32_t *r, int64_t n, uint32_t *out, hipStream_t st);
+
+// a5: forward composite.
+hipError_t launch_composite_fwd(const DevCamera &cam, int lds_batch, int remap, const uint2 *ranges,
+                                const uint32_t *sorted_ids, const float4 *rec, float *image, float *T_final,
+                                uint32_t *n_contrib, hipStream_t st);
+
+// a6: backward composite.
+struct BwdArgs {
+    const uint2 *ranges;
+    const uint32_t *sorted_ids;
+    const float4 *rec;
+    const float *dl_dimage;
+    const float *T_final;
+    const uint32_t *n_contrib;
+    float *acc;
+    unsigned long long *counters; // [7 + 65] when counting
+    int threshold;                // effective: reduce iff active >= threshold (>= 1)
+};
+hipError_t launch_composite_bwd(const DevCamera &cam, int lds_batch, int remap, int mode, bool count,
+                                bool lane_split, const BwdArgs &a, hipStream_t st);
+
+hipError_t launch_l1_grad(const float *image, const float *target, int64_t count, float *out, hipStream_t st);
+hipError_t launch_wave_reduce_selftest(const float *vals, const uint8_t *active, int n_waves, int mode,
+                                       int threshold, int lane_split, float *sums, unsigned long long *lane_atomics,
+                                       hipStream_t st);
+
+} // namespace gsr
+
+// ----- opaque API objects -----
+
+struct gsr_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+    gsr::Pool *pool = nullptr;
+    uint32_t *host_pinned = nullptr; // small readback area
+    hipEvent_t ev[12] = {};
+    bool timing_render = false, timing_bwd = false;
+};
+
+struct gsr_fwd {
+    gsr_scene scene{};
+    gsr_camera camera{};
+    gsr_config config{};
+    gsr::DevCamera dcam{};
+    int64_t n = 0, n_visible = -1, P = 0, n_tiles = 0;
+    float4 *rec = nullptr;
+    int32_t *radius = nullptr;
+    uint32_t *tiles_touched = nullptr;
+    uint8_t *clamp_mask = nullptr;
+    uint32_t *depth_key = nullptr, *ids = nullptr, *key_alt = nullptr, *ids_alt = nullptr;
+    uint32_t *sorted_ids_by_depth = nullptr; // points into ids or ids_alt
+    uint32_t *offsets = nullptr;
+    uint32_t *pair_tile = nullptr, *pair_id = nullptr, *pair_tile_alt = nullptr, *pair_id_alt = nullptr;
+    uint32_t *sorted_pair_id = nullptr; // points into pair_id or pair_id_alt
+    uint2 *ranges = nullptr;
+    float *T_final = nullptr;
+    uint32_t *n_contrib = nullptr;
+    float *acc = nullptr;
+    unsigned long long *counters = nullptr;
+    bool counters_valid = false;
+    std::vector<void *> owned; // every pool buffer of this state
+};

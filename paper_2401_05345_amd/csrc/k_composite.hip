@@ -1,0 +1,374 @@
+// Composite kernels of the 3DGS pipeline on gfx950 (fp32), one workgroup of
+// TILE*TILE threads per screen tile, one thread per pixel, each 64-lane
+// wavefront covering an 8x8 pixel block.
+//   a5 composite_fwd: front-to-back blending over the tile's depth-ordered
+//      list, Gaussian records staged through LDS in batches; stores
+//      T_final and n_contrib so the backward can recompute instead of store.
+//   a6 composite_bwd: the paper's gradient-computation kernel (Motivation,
+//      outline of the gradient computation step): each pixel walks the same
+//      list in reverse and adds its contribution to nine per-Gaussian
+//      gradients. All lanes of a wave walk the same entry in lockstep, so the
+//      address is wave-uniform by construction (the paper's observation that
+//      almost every warp updates a single primitive), and lanes that skip an
+//      entry carry zeros instead of leaving the loop (the SW-B kernel
+//      transformation of Detailed Design, "Butterfly Reduction"). The update
+//      is either nine plain atomic adds per active lane, or - when the
+//      wave's active-lane count reaches the balancing threshold (Approach,
+//      "Scheduling Atomic Updates Between Core and L2") - a DPP butterfly
+//      over the 64 lanes and one lane's (or nine lanes') atomics.
+#include "device_common.hpp"
+
+namespace gsr {
+namespace {
+
+__device__ __forceinline__ int tile_for_block(int b, int n_tiles, int remap) {
+    if (!remap) return b;
+    // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a
+    // contiguous band of tiles so neighbouring tiles (which share Gaussians)
+    // update accumulator lines through the same L2.
+    const int per = (n_tiles + 7) / 8;
+    return (b & 7) * per + (b >> 3);
+}
+
+__host__ __device__ __forceinline__ int grid_for_tiles(int n_tiles, int remap) {
+    return remap ? ((n_tiles + 7) / 8) * 8 : n_tiles;
+}
+
+__device__ __forceinline__ void atomic_add_f32(float *p, float v) { unsafeAtomicAdd(p, v); }
+
+// Per-wave update of the nine values of one Gaussian. Every lane of the wave
+// must call it (uniform control flow). Returns the atomic lane-operations
+// this lane issued.
+template <int MODE, bool SPLIT>
+__device__ __forceinline__ uint32_t emit9(bool active, float (&v)[9], float *dst, int threshold, int lane,
+                                          uint64_t &reduced_mask_out) {
+    uint32_t issued = 0;
+    reduced_mask_out = 0;
+    if (MODE == GSR_BWD_PLAIN_ATOMIC) {
+        if (active) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) atomic_add_f32(dst + k, v[k]);
+            issued = 9;
+        }
+        return issued;
+    }
+    const uint64_t m = __ballot(active);
+    const int cnt = __popcll(m);
+    if (cnt >= threshold) { // threshold >= 1, so cnt > 0 here
+        reduced_mask_out = m;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) v[k] = wave_sum_to_lane63(v[k]);
+        if (SPLIT) {
+            float mine = 0.0f;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                const float s = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v[k]), 63));
+                mine = (lane == k) ? s : mine;
+            }
+            if (lane < 9) {
+                atomic_add_f32(dst + lane, mine);
+                issued = 1;
+            }
+        } else if (lane == 63) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) atomic_add_f32(dst + k, v[k]);
+            issued = 9;
+        }
+    } else if (active) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) atomic_add_f32(dst + k, v[k]);
+        issued = 9;
+    }
+    return issued;
+}
+
+template <int TILE, int BATCH>
+__global__ __launch_bounds__(TILE *TILE) void composite_fwd_kernel(DevCamera cam, int remap, int n_tiles,
+                                                                   const uint2 *__restrict__ ranges,
+                                                                   const uint32_t *__restrict__ ids,
+                                                                   const float4 *__restrict__ rec,
+                                                                   float *__restrict__ image,
+                                                                   float *__restrict__ T_final,
+                                                                   uint32_t *__restrict__ n_contrib) {
+    constexpr int NT = TILE * TILE;
+    constexpr int QX = TILE / 8;
+    __shared__ float4 s0[BATCH], s1[BATCH];
+    __shared__ float sb[BATCH];
+    const int tile = tile_for_block(blockIdx.x, n_tiles, remap);
+    if (tile >= n_tiles) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int px = (tile % cam.grid_x) * TILE + (wave % QX) * 8 + (lane & 7);
+    const int py = (tile / cam.grid_x) * TILE + (wave / QX) * 8 + (lane >> 3);
+    const bool inside = px < cam.width && py < cam.height;
+    const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+    const uint2 rg = ranges[tile];
+    float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+    uint32_t last = 0;
+    bool done = !inside;
+    for (uint32_t start = rg.x; start < rg.y; start += BATCH) {
+        if (__syncthreads_count(done) == NT) break;
+        const uint32_t k = start + tid;
+        if (tid < BATCH && k < rg.y) {
+            const uint32_t g = ids[k];
+            s0[tid] = rec[3 * (size_t)g];
+            s1[tid] = rec[3 * (size_t)g + 1];
+            sb[tid] = rec[3 * (size_t)g + 2].x;
+        }
+        __syncthreads();
+        const int cnt = min(BATCH, (int)(rg.y - start));
+        for (int j = 0; j < cnt && !done; ++j) {
+            const float4 a = s0[j], b = s1[j];
+            const SplatEval e = eval_splat(fpx, fpy, a.x, a.y, a.z, a.w, b.x, b.y);
+            if (!e.pass) continue;
+            const float Tn = T * (1.0f - e.alpha);
+            if (Tn < kTStop) {
+                done = true;
+                break;
+            }
+            const float w = e.alpha * T;
+            c0 = fmaf(w, b.z, c0);
+            c1 = fmaf(w, b.w, c1);
+            c2 = fmaf(w, sb[j], c2);
+            T = Tn;
+            last = start - rg.x + (uint32_t)j + 1;
+        }
+    }
+    if (inside) {
+        const size_t hw = (size_t)cam.width * cam.height;
+        const size_t pix = (size_t)py * cam.width + px;
+        image[pix] = fmaf(T, cam.bg[0], c0);
+        image[hw + pix] = fmaf(T, cam.bg[1], c1);
+        image[2 * hw + pix] = fmaf(T, cam.bg[2], c2);
+        T_final[pix] = T;
+        n_contrib[pix] = last;
+    }
+}
+
+enum { CNT_EVAL = 0, CNT_ACTIVE, CNT_WAVE_ENTRIES, CNT_REDUCED, CNT_PLAIN_LANES, CNT_LANE_ATOMICS, CNT_INSTRS, CNT_HIST };
+
+template <int TILE, int BATCH, int MODE, bool COUNT, bool SPLIT>
+__global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(DevCamera cam, int remap, int n_tiles, BwdArgs a) {
+    constexpr int QX = TILE / 8;
+    __shared__ float4 s0[BATCH], s1[BATCH];
+    __shared__ float sb[BATCH];
+    __shared__ uint32_t sid[BATCH];
+    __shared__ uint32_t s_walk;
+    __shared__ unsigned long long s_cnt[COUNT ? CNT_HIST + 65 : 1];
+    const int tile = tile_for_block(blockIdx.x, n_tiles, remap);
+    if (tile >= n_tiles) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int px = (tile % cam.grid_x) * TILE + (wave % QX) * 8 + (lane & 7);
+    const int py = (tile / cam.grid_x) * TILE + (wave / QX) * 8 + (lane >> 3);
+    const bool inside = px < cam.width && py < cam.height;
+    const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+    const size_t hw = (size_t)cam.width * cam.height;
+    const size_t pix = inside ? (size_t)py * cam.width + px : 0;
+    float T = inside ? a.T_final[pix] : 1.0f;
+    const uint32_t nc = inside ? a.n_contrib[pix] : 0u;
+    const float G0 = inside ? a.dl_dimage[pix] : 0.0f;
+    const float G1 = inside ? a.dl_dimage[hw + pix] : 0.0f;
+    const float G2 = inside ? a.dl_dimage[2 * hw + pix] : 0.0f;
+    float Q0 = cam.bg[0], Q1 = cam.bg[1], Q2 = cam.bg[2];
+    const uint2 rg = a.ranges[tile];
+
+    if (tid == 0) s_walk = 0;
+    if (COUNT)
+        for (int i = tid; i < CNT_HIST + 65; i += TILE * TILE) s_cnt[i] = 0;
+    __syncthreads();
+    const uint32_t wmax = wave_max_u32(nc);
+    if (lane == 0) atomicMax(&s_walk, wmax);
+    __syncthreads();
+    const int walk = (int)s_walk; // entries past every pixel's n_contrib contribute nothing
+
+    uint64_t c_eval = 0, c_active = 0, c_we = 0, c_red = 0, c_plain = 0, c_instr = 0;
+    uint32_t issued = 0;
+
+    for (int end = walk; end > 0; end -= BATCH) {
+        const int start = end > BATCH ? end - BATCH : 0;
+        const int cnt = end - start;
+        __syncthreads();
+        if (tid < cnt) {
+            const uint32_t g = a.sorted_ids[rg.x + start + tid];
+            sid[tid] = g;
+            s0[tid] = a.rec[3 * (size_t)g];
+            s1[tid] = a.rec[3 * (size_t)g + 1];
+            sb[tid] = a.rec[3 * (size_t)g + 2].x;
+        }
+        __syncthreads();
+        for (int j = cnt - 1; j >= 0; --j) {
+            const uint32_t pos = (uint32_t)(start + j + 1);
+            const float4 r0 = s0[j], r1 = s1[j];
+            const float rb = sb[j];
+            const SplatEval e = eval_splat(fpx, fpy, r0.x, r0.y, r0.z, r0.w, r1.x, r1.y);
+            const bool walked = pos <= nc;
+            const bool active = walked && e.pass;
+            float v[9];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) v[k] = 0.0f;
+            if (active) {
+                T = T / (1.0f - e.alpha); // transmittance in front of this entry
+                const float w = e.alpha * T;
+                v[6] = w * G0;
+                v[7] = w * G1;
+                v[8] = w * G2;
+                const float dL_dalpha = T * ((r1.z - Q0) * G0 + (r1.w - Q1) * G1 + (rb - Q2) * G2);
+                Q0 = fmaf(e.alpha, r1.z - Q0, Q0);
+                Q1 = fmaf(e.alpha, r1.w - Q1, Q1);
+                Q2 = fmaf(e.alpha, rb - Q2, Q2);
+                const float dL_doG = e.raw > kAlphaMax ? 0.0f : dL_dalpha; // alpha = min(0.99, o G)
+                v[5] = e.G * dL_doG;
+                const float dL_dp = e.raw * dL_doG;
+                v[0] = dL_dp * (r0.z * e.dx + r0.w * e.dy);
+                v[1] = dL_dp * (r0.w * e.dx + r1.x * e.dy);
+                v[2] = -0.5f * dL_dp * e.dx * e.dx;
+                v[3] = -dL_dp * e.dx * e.dy;
+                v[4] = -0.5f * dL_dp * e.dy * e.dy;
+            }
+            float *dst = a.acc + (size_t)sid[j] * GSR_ACC_STRIDE;
+            uint64_t red_mask;
+            issued += emit9<MODE, SPLIT>(active, v, dst, a.threshold, lane, red_mask);
+            if (COUNT) {
+                const uint64_t mw = __ballot(walked), ma = __ballot(active);
+                const int ca = __popcll(ma);
+                c_eval += __popcll(mw);
+                c_active += ca;
+                if (ca) {
+                    c_we += 1;
+                    if (red_mask) {
+                        c_red += 1;
+                        c_instr += SPLIT ? 1 : 9;
+                    } else {
+                        c_plain += ca;
+                        c_instr += 9;
+                    }
+                    if (lane == 0) atomicAdd(&s_cnt[CNT_HIST + ca], 1ull);
+                }
+            }
+        }
+    }
+    if (COUNT) {
+        atomicAdd(&s_cnt[CNT_LANE_ATOMICS], (unsigned long long)issued);
+        if (lane == 0) {
+            atomicAdd(&s_cnt[CNT_EVAL], (unsigned long long)c_eval);
+            atomicAdd(&s_cnt[CNT_ACTIVE], (unsigned long long)c_active);
+            atomicAdd(&s_cnt[CNT_WAVE_ENTRIES], (unsigned long long)c_we);
+            atomicAdd(&s_cnt[CNT_REDUCED], (unsigned long long)c_red);
+            atomicAdd(&s_cnt[CNT_PLAIN_LANES], (unsigned long long)c_plain);
+            atomicAdd(&s_cnt[CNT_INSTRS], (unsigned long long)c_instr);
+        }
+        __syncthreads();
+        for (int i = tid; i < CNT_HIST + 65; i += TILE * TILE)
+            if (s_cnt[i]) atomicAdd(&a.counters[i], s_cnt[i]);
+    }
+}
+
+template <int MODE, bool SPLIT>
+__global__ __launch_bounds__(64) void wave_reduce_selftest_kernel(const float *vals, const uint8_t *active,
+                                                                   int threshold, float *sums,
+                                                                   unsigned long long *lane_atomics) {
+    const int lane = threadIdx.x;
+    const size_t i = (size_t)blockIdx.x * 64 + lane;
+    float v[9];
+    const bool act = active[i] != 0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) v[k] = act ? vals[i * 9 + k] : 0.0f;
+    uint64_t red;
+    const uint32_t issued = emit9<MODE, SPLIT>(act, v, sums, threshold, lane, red);
+    if (issued) atomicAdd(lane_atomics, (unsigned long long)issued);
+}
+
+__global__ __launch_bounds__(256) void l1_grad_kernel(const float *image, const float *target, int64_t count,
+                                                       float inv, float *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const float d = image[i] - target[i];
+    out[i] = d > 0.0f ? inv : (d < 0.0f ? -inv : 0.0f);
+}
+
+template <int TILE, int BATCH>
+hipError_t fwd_t(const DevCamera &cam, int remap, const uint2 *ranges, const uint32_t *ids, const float4 *rec,
+                 float *image, float *T_final, uint32_t *n_contrib, hipStream_t st) {
+    const int n_tiles = cam.grid_x * cam.grid_y;
+    composite_fwd_kernel<TILE, BATCH><<<grid_for_tiles(n_tiles, remap), TILE * TILE, 0, st>>>(
+        cam, remap, n_tiles, ranges, ids, rec, image, T_final, n_contrib);
+    return hipGetLastError();
+}
+
+template <int TILE, int BATCH>
+hipError_t bwd_t(const DevCamera &cam, int remap, int mode, bool count, bool split, const BwdArgs &a,
+                 hipStream_t st) {
+    const int n_tiles = cam.grid_x * cam.grid_y;
+    const dim3 grid(grid_for_tiles(n_tiles, remap)), block(TILE * TILE);
+#define GSR_BWD(M, C, S) composite_bwd_kernel<TILE, BATCH, M, C, S><<<grid, block, 0, st>>>(cam, remap, n_tiles, a)
+    if (mode == GSR_BWD_PLAIN_ATOMIC) {
+        if (count) GSR_BWD(GSR_BWD_PLAIN_ATOMIC, true, false);
+        else GSR_BWD(GSR_BWD_PLAIN_ATOMIC, false, false);
+    } else if (split) {
+        if (count) GSR_BWD(GSR_BWD_WAVE_REDUCE, true, true);
+        else GSR_BWD(GSR_BWD_WAVE_REDUCE, false, true);
+    } else {
+        if (count) GSR_BWD(GSR_BWD_WAVE_REDUCE, true, false);
+        else GSR_BWD(GSR_BWD_WAVE_REDUCE, false, false);
+    }
+#undef GSR_BWD
+    return hipGetLastError();
+}
+
+} // namespace
+
+hipError_t launch_composite_fwd(const DevCamera &cam, int lds_batch, int remap, const uint2 *ranges,
+                                const uint32_t *sorted_ids, const float4 *rec, float *image, float *T_final,
+                                uint32_t *n_contrib, hipStream_t st) {
+    const int t = cam.tile;
+#define GSR_F(T, B) return fwd_t<T, B>(cam, remap, ranges, sorted_ids, rec, image, T_final, n_contrib, st)
+    if (t == 8) GSR_F(8, 64);
+    if (t == 16) {
+        if (lds_batch == 64) GSR_F(16, 64);
+        if (lds_batch == 128) GSR_F(16, 128);
+        GSR_F(16, 256);
+    }
+    if (lds_batch == 64) GSR_F(32, 64);
+    if (lds_batch == 128) GSR_F(32, 128);
+    GSR_F(32, 256);
+#undef GSR_F
+}
+
+hipError_t launch_composite_bwd(const DevCamera &cam, int lds_batch, int remap, int mode, bool count, bool lane_split,
+                                const BwdArgs &a, hipStream_t st) {
+    const int t = cam.tile;
+#define GSR_B(T, B) return bwd_t<T, B>(cam, remap, mode, count, lane_split, a, st)
+    if (t == 8) GSR_B(8, 64);
+    if (t == 16) {
+        if (lds_batch == 64) GSR_B(16, 64);
+        if (lds_batch == 128) GSR_B(16, 128);
+        GSR_B(16, 256);
+    }
+    if (lds_batch == 64) GSR_B(32, 64);
+    if (lds_batch == 128) GSR_B(32, 128);
+    GSR_B(32, 256);
+#undef GSR_B
+}
+
+hipError_t launch_l1_grad(const float *image, const float *target, int64_t count, float *out, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    l1_grad_kernel<<<(unsigned)((count + 255) / 256), 256, 0, st>>>(image, target, count, 1.0f / (float)count, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_wave_reduce_selftest(const float *vals, const uint8_t *active, int n_waves, int mode,
+                                       int threshold, int lane_split, float *sums, unsigned long long *lane_atomics,
+                                       hipStream_t st) {
+    if (n_waves <= 0) return hipSuccess;
+    if (mode == GSR_BWD_PLAIN_ATOMIC)
+        wave_reduce_selftest_kernel<GSR_BWD_PLAIN_ATOMIC, false><<<n_waves, 64, 0, st>>>(vals, active, threshold,
+                                                                                         sums, lane_atomics);
+    else if (lane_split)
+        wave_reduce_selftest_kernel<GSR_BWD_WAVE_REDUCE, true><<<n_waves, 64, 0, st>>>(vals, active, threshold, sums,
+                                                                                       lane_atomics);
+    else
+        wave_reduce_selftest_kernel<GSR_BWD_WAVE_REDUCE, false><<<n_waves, 64, 0, st>>>(vals, active, threshold,
+                                                                                        sums, lane_atomics);
+    return hipGetLastError();
+}
+
+} // namespace gsr

@@ -1,0 +1,382 @@
+// Per-Gaussian stages of the 3DGS pipeline (one thread per Gaussian, fp32):
+//   a1 preprocess_fwd: projection, EWA 2D covariance and conic, 3-sigma radius,
+//      tile count, view-dependent SH colour, depth sort key
+//   a7 preprocess_bwd: gradients of the raw parameters (means, log-scales,
+//      quaternions, opacity logits, SH) from the nine per-Gaussian
+//      accumulators of the backward composite
+// These are the first and last steps of the paper's rasterisation pipeline
+// figure (projection of the primitives; "gradients for all the parameters");
+// the math is the published 3D Gaussian Splatting method.
+#include "device_common.hpp"
+
+namespace gsr {
+namespace {
+
+struct Proj {
+    float tx, ty, tz;
+    float R[9];      // rotation of the normalised quaternion, row-major
+    float s[3];      // exp(log-scales)
+    float M[9];      // R diag(s)
+    float Sig[6];    // Sigma: 00 01 02 11 12 22
+    float T2[6];     // J * Rc, rows 0 and 1
+    float V0[3], V1[3];
+    float a, b, c, det;
+    float xc, yc;    // guard-band-clamped x, y used by J
+    bool clx, cly;
+    float qn[4];     // normalised quaternion
+    float qinv;      // 1 / |q|
+};
+
+__device__ __forceinline__ void project_splat(const DevCamera &cam, float mx, float my, float mz, float tz,
+                                              const float *ls, const float *q, Proj &p) {
+    p.tz = tz;
+    p.tx = fmaf(cam.R[0], mx, fmaf(cam.R[1], my, fmaf(cam.R[2], mz, cam.t[0])));
+    p.ty = fmaf(cam.R[3], mx, fmaf(cam.R[4], my, fmaf(cam.R[5], mz, cam.t[1])));
+
+    p.s[0] = expf(ls[0]);
+    p.s[1] = expf(ls[1]);
+    p.s[2] = expf(ls[2]);
+    const float qq = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+    p.qinv = 1.0f / sqrtf(qq);
+    const float w = q[0] * p.qinv, x = q[1] * p.qinv, y = q[2] * p.qinv, z = q[3] * p.qinv;
+    p.qn[0] = w; p.qn[1] = x; p.qn[2] = y; p.qn[3] = z;
+    p.R[0] = 1.f - 2.f * (y * y + z * z); p.R[1] = 2.f * (x * y - w * z);       p.R[2] = 2.f * (x * z + w * y);
+    p.R[3] = 2.f * (x * y + w * z);       p.R[4] = 1.f - 2.f * (x * x + z * z); p.R[5] = 2.f * (y * z - w * x);
+    p.R[6] = 2.f * (x * z - w * y);       p.R[7] = 2.f * (y * z + w * x);       p.R[8] = 1.f - 2.f * (x * x + y * y);
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) p.M[3 * r + k] = p.R[3 * r + k] * p.s[k];
+    // Sigma = M M^T
+    const float *M = p.M;
+    p.Sig[0] = M[0] * M[0] + M[1] * M[1] + M[2] * M[2];
+    p.Sig[1] = M[0] * M[3] + M[1] * M[4] + M[2] * M[5];
+    p.Sig[2] = M[0] * M[6] + M[1] * M[7] + M[2] * M[8];
+    p.Sig[3] = M[3] * M[3] + M[4] * M[4] + M[5] * M[5];
+    p.Sig[4] = M[3] * M[6] + M[4] * M[7] + M[5] * M[8];
+    p.Sig[5] = M[6] * M[6] + M[7] * M[7] + M[8] * M[8];
+
+    // Jacobian of the pinhole map, x/z and y/z held inside a 1.3x guard band.
+    const float txtz = p.tx / tz, tytz = p.ty / tz;
+    p.clx = txtz < -cam.limx || txtz > cam.limx;
+    p.cly = tytz < -cam.limy || tytz > cam.limy;
+    p.xc = fminf(cam.limx, fmaxf(-cam.limx, txtz)) * tz;
+    p.yc = fminf(cam.limy, fmaxf(-cam.limy, tytz)) * tz;
+    const float itz = 1.0f / tz;
+    const float J00 = cam.fx * itz, J02 = -cam.fx * p.xc * itz * itz;
+    const float J11 = cam.fy * itz, J12 = -cam.fy * p.yc * itz * itz;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        p.T2[k] = J00 * cam.R[k] + J02 * cam.R[6 + k];
+        p.T2[3 + k] = J11 * cam.R[3 + k] + J12 * cam.R[6 + k];
+    }
+    // V = Sigma T2^T (Sigma symmetric), a = T2_0 . V0, b = T2_0 . V1, c = T2_1 . V1
+    const float *S = p.Sig;
+    const float *T = p.T2;
+    p.V0[0] = S[0] * T[0] + S[1] * T[1] + S[2] * T[2];
+    p.V0[1] = S[1] * T[0] + S[3] * T[1] + S[4] * T[2];
+    p.V0[2] = S[2] * T[0] + S[4] * T[1] + S[5] * T[2];
+    p.V1[0] = S[0] * T[3] + S[1] * T[4] + S[2] * T[5];
+    p.V1[1] = S[1] * T[3] + S[3] * T[4] + S[4] * T[5];
+    p.V1[2] = S[2] * T[3] + S[4] * T[4] + S[5] * T[5];
+    p.a = T[0] * p.V0[0] + T[1] * p.V0[1] + T[2] * p.V0[2] + 0.3f;
+    p.b = T[0] * p.V1[0] + T[1] * p.V1[1] + T[2] * p.V1[2];
+    p.c = T[3] * p.V1[0] + T[4] * p.V1[1] + T[5] * p.V1[2] + 0.3f;
+    p.det = fmaf(p.a, p.c, -p.b * p.b);
+}
+
+// Depth key: ((R20*mx + R21*my) + R22*mz) + t2, one correctly rounded fp32
+// operation at a time, so the sort order is reproducible bit for bit.
+__device__ __forceinline__ float depth_of(const DevCamera &cam, float mx, float my, float mz) {
+    return __fadd_rn(__fadd_rn(__fadd_rn(__fmul_rn(cam.R[6], mx), __fmul_rn(cam.R[7], my)), __fmul_rn(cam.R[8], mz)),
+                     cam.t[2]);
+}
+
+template <int DEG>
+__global__ __launch_bounds__(256) void preprocess_fwd_kernel(int n, const float *__restrict__ means,
+                                                             const float *__restrict__ log_scales,
+                                                             const float *__restrict__ quats,
+                                                             const float *__restrict__ opacity_logits,
+                                                             const float *__restrict__ sh, DevCamera cam,
+                                                             float4 *__restrict__ rec, int32_t *__restrict__ radius,
+                                                             uint32_t *__restrict__ tiles_touched,
+                                                             uint32_t *__restrict__ depth_key,
+                                                             uint32_t *__restrict__ ids,
+                                                             uint8_t *__restrict__ clamp_mask) {
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    ids[i] = (uint32_t)i;
+    const float mx = means[3 * i], my = means[3 * i + 1], mz = means[3 * i + 2];
+    const float tz = depth_of(cam, mx, my, mz);
+    const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+
+    bool vis = tz > cam.znear;
+    Proj p;
+    float A = 0.f, B = 0.f, C = 0.f, u = 0.f, v = 0.f;
+    int r = 0, ntiles = 0;
+    if (vis) {
+        project_splat(cam, mx, my, mz, tz, log_scales + 3 * i, quats + 4 * i, p);
+        vis = p.det > 0.0f;
+    }
+    if (vis) {
+        const float idet = 1.0f / p.det;
+        A = p.c * idet;
+        B = -p.b * idet;
+        C = p.a * idet;
+        u = cam.fx * (p.tx / tz) + cam.cx;
+        v = cam.fy * (p.ty / tz) + cam.cy;
+        const float mid = 0.5f * (p.a + p.c);
+        const float lam1 = mid + sqrtf(fmaxf(0.1f, mid * mid - p.det));
+        r = (int)ceilf(3.0f * sqrtf(lam1));
+        int x0, x1, y0, y1;
+        rect_of(u, v, r, cam, x0, x1, y0, y1);
+        ntiles = (x1 - x0) * (y1 - y0);
+        vis = ntiles > 0;
+    }
+    if (!vis) {
+        rec[3 * (int64_t)i] = zero;
+        rec[3 * (int64_t)i + 1] = zero;
+        rec[3 * (int64_t)i + 2] = zero;
+        radius[i] = 0;
+        tiles_touched[i] = 0;
+        depth_key[i] = 0xffffffffu;
+        clamp_mask[i] = 0;
+        return;
+    }
+    // View-dependent colour along the direction from the camera centre.
+    float dx = mx - cam.centre[0], dy = my - cam.centre[1], dz = mz - cam.centre[2];
+    const float il = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+    dx *= il; dy *= il; dz *= il;
+    float Y[K];
+    sh_basis<DEG>(dx, dy, dz, Y);
+    const float *f = sh + (int64_t)i * K * 3;
+    float rgb[3] = {0.5f, 0.5f, 0.5f};
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        rgb[0] = fmaf(Y[k], f[3 * k + 0], rgb[0]);
+        rgb[1] = fmaf(Y[k], f[3 * k + 1], rgb[1]);
+        rgb[2] = fmaf(Y[k], f[3 * k + 2], rgb[2]);
+    }
+    uint8_t cm = 0;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        if (rgb[ch] < 0.0f) {
+            cm |= (uint8_t)(1u << ch);
+            rgb[ch] = 0.0f;
+        }
+    }
+    const float o = 1.0f / (1.0f + expf(-opacity_logits[i]));
+    rec[3 * (int64_t)i] = make_float4(u, v, A, B);
+    rec[3 * (int64_t)i + 1] = make_float4(C, o, rgb[0], rgb[1]);
+    rec[3 * (int64_t)i + 2] = make_float4(rgb[2], tz, 0.f, 0.f);
+    radius[i] = r;
+    tiles_touched[i] = (uint32_t)ntiles;
+    depth_key[i] = __float_as_uint(tz);
+    clamp_mask[i] = cm;
+}
+
+template <int DEG>
+__global__ __launch_bounds__(256) void preprocess_bwd_kernel(int n, const float *__restrict__ means,
+                                                             const float *__restrict__ log_scales,
+                                                             const float *__restrict__ quats,
+                                                             const float *__restrict__ opacity_logits,
+                                                             const float *__restrict__ sh, DevCamera cam,
+                                                             const int32_t *__restrict__ radius,
+                                                             const float *__restrict__ acc, gsr_grads out,
+                                                             int accumulate) {
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float *o_m = out.means3d + 3 * (int64_t)i;
+    float *o_s = out.log_scales + 3 * (int64_t)i;
+    float *o_q = out.quats + 4 * (int64_t)i;
+    float *o_o = out.opacity_logits + i;
+    float *o_sh = out.sh + (int64_t)i * K * 3;
+    if (radius[i] <= 0) {
+        if (!accumulate) {
+            for (int k = 0; k < 3; ++k) o_m[k] = 0.f, o_s[k] = 0.f;
+            for (int k = 0; k < 4; ++k) o_q[k] = 0.f;
+            *o_o = 0.f;
+            for (int k = 0; k < 3 * K; ++k) o_sh[k] = 0.f;
+        }
+        return;
+    }
+    const float *g = acc + (int64_t)i * GSR_ACC_STRIDE;
+    const float gu = g[0], gv = g[1], gA = g[2], gB = g[3], gC = g[4], go = g[5];
+    const float grgb[3] = {g[6], g[7], g[8]};
+
+    const float mx = means[3 * i], my = means[3 * i + 1], mz = means[3 * i + 2];
+    const float tz = depth_of(cam, mx, my, mz);
+    Proj p;
+    project_splat(cam, mx, my, mz, tz, log_scales + 3 * i, quats + 4 * i, p);
+
+    // ---- colour: rgb = max(sum_k Y_k f_k + 0.5, 0) along d = (m - centre)/|m - centre| ----
+    float ex = mx - cam.centre[0], ey = my - cam.centre[1], ez = mz - cam.centre[2];
+    const float il = 1.0f / sqrtf(ex * ex + ey * ey + ez * ez);
+    const float dxn = ex * il, dyn = ey * il, dzn = ez * il;
+    float Y[K];
+    sh_basis<DEG>(dxn, dyn, dzn, Y);
+    const float *f = sh + (int64_t)i * K * 3;
+    float raw[3] = {0.5f, 0.5f, 0.5f};
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        raw[0] = fmaf(Y[k], f[3 * k + 0], raw[0]);
+        raw[1] = fmaf(Y[k], f[3 * k + 1], raw[1]);
+        raw[2] = fmaf(Y[k], f[3 * k + 2], raw[2]);
+    }
+    float graw[3];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) graw[ch] = raw[ch] < 0.0f ? 0.0f : grgb[ch];
+    float ddir[3] = {0.f, 0.f, 0.f};
+    if (DEG > 0) {
+        float gx[K], gy[K], gz[K];
+        sh_basis_grad<DEG>(dxn, dyn, dzn, gx, gy, gz);
+#pragma unroll
+        for (int k = 1; k < K; ++k) {
+            const float wk = graw[0] * f[3 * k] + graw[1] * f[3 * k + 1] + graw[2] * f[3 * k + 2];
+            ddir[0] = fmaf(wk, gx[k], ddir[0]);
+            ddir[1] = fmaf(wk, gy[k], ddir[1]);
+            ddir[2] = fmaf(wk, gz[k], ddir[2]);
+        }
+    }
+    // d(dir)/d(m) = (I - dir dir^T) / |m - centre|
+    const float proj = ddir[0] * dxn + ddir[1] * dyn + ddir[2] * dzn;
+    float dm[3] = {(ddir[0] - proj * dxn) * il, (ddir[1] - proj * dyn) * il, (ddir[2] - proj * dzn) * il};
+    if (accumulate) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) o_sh[3 * k + ch] += Y[k] * graw[ch];
+    } else {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) o_sh[3 * k + ch] = Y[k] * graw[ch];
+    }
+
+    // ---- conic (A,B,C) = (c, -b, a) / det  ->  2D covariance (a, b, c) ----
+    const float a = p.a, b = p.b, c = p.c;
+    const float id2 = 1.0f / (p.det * p.det);
+    const float ga = (-gA * c * c + gB * b * c - gC * b * b) * id2;
+    const float gb = (2.0f * gA * b * c - gB * (a * c + b * b) + 2.0f * gC * a * b) * id2;
+    const float gc = (-gA * b * b + gB * a * b - gC * a * a) * id2;
+
+    // ---- Sigma2 = T2 Sigma T2^T: dSigma = T2^T G2 T2, dT2 = 2 G2 T2 Sigma, G2 = [[ga, gb/2],[gb/2, gc]] ----
+    const float *T = p.T2;
+    float dS[6];
+    {
+        const int rr[6] = {0, 0, 0, 1, 1, 2}, cc[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+        for (int e = 0; e < 6; ++e) {
+            const int r = rr[e], q = cc[e];
+            dS[e] = ga * T[r] * T[q] + 0.5f * gb * (T[r] * T[3 + q] + T[3 + r] * T[q]) + gc * T[3 + r] * T[3 + q];
+        }
+    }
+    float dT0[3], dT1[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        dT0[k] = 2.0f * ga * p.V0[k] + gb * p.V1[k];
+        dT1[k] = gb * p.V0[k] + 2.0f * gc * p.V1[k];
+    }
+    // ---- T2 = J Rc ----
+    const float dJ00 = dT0[0] * cam.R[0] + dT0[1] * cam.R[1] + dT0[2] * cam.R[2];
+    const float dJ02 = dT0[0] * cam.R[6] + dT0[1] * cam.R[7] + dT0[2] * cam.R[8];
+    const float dJ11 = dT1[0] * cam.R[3] + dT1[1] * cam.R[4] + dT1[2] * cam.R[5];
+    const float dJ12 = dT1[0] * cam.R[6] + dT1[1] * cam.R[7] + dT1[2] * cam.R[8];
+    // ---- J(t) and (u,v)(t); a clamped coordinate passes no gradient through x/z ----
+    const float itz = 1.0f / tz, itz2 = itz * itz, itz3 = itz2 * itz;
+    const float fx = cam.fx, fy = cam.fy;
+    const float dtx = gu * fx * itz + (p.clx ? 0.0f : -fx * itz2 * dJ02);
+    const float dty = gv * fy * itz + (p.cly ? 0.0f : -fy * itz2 * dJ12);
+    const float dtz = -(gu * fx * p.tx + gv * fy * p.ty) * itz2 - fx * itz2 * dJ00 - fy * itz2 * dJ11 +
+                      dJ02 * fx * p.xc * itz3 * (p.clx ? 1.0f : 2.0f) +
+                      dJ12 * fy * p.yc * itz3 * (p.cly ? 1.0f : 2.0f);
+    // t = Rc m + tc
+#pragma unroll
+    for (int k = 0; k < 3; ++k) dm[k] += cam.R[k] * dtx + cam.R[3 + k] * dty + cam.R[6 + k] * dtz;
+
+    // ---- Sigma = M M^T: dM = 2 dSigma M;  M = R diag(s) ----
+    const float dSf[9] = {dS[0], dS[1], dS[2], dS[1], dS[3], dS[4], dS[2], dS[4], dS[5]};
+    float dM[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+            dM[3 * r + q] = 2.0f * (dSf[3 * r] * p.M[q] + dSf[3 * r + 1] * p.M[3 + q] + dSf[3 * r + 2] * p.M[6 + q]);
+    float dR[9], dls[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const float ds = dM[q] * p.R[q] + dM[3 + q] * p.R[3 + q] + dM[6 + q] * p.R[6 + q];
+        dls[q] = ds * p.s[q];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) dR[3 * r + q] = dM[3 * r + q] * p.s[q];
+    }
+    // ---- R(qn) -> qn -> q (through the normalisation) ----
+    const float w = p.qn[0], x = p.qn[1], y = p.qn[2], z = p.qn[3];
+    float dq[4];
+    dq[0] = 2.f * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+    dq[1] = 2.f * (y * dR[1] + z * dR[2] + y * dR[3] - 2.f * x * dR[4] - w * dR[5] + z * dR[6] + w * dR[7] -
+                   2.f * x * dR[8]);
+    dq[2] = 2.f * (-2.f * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] + z * dR[7] -
+                   2.f * y * dR[8]);
+    dq[3] = 2.f * (-2.f * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.f * z * dR[4] + y * dR[5] + x * dR[6] +
+                   y * dR[7]);
+    const float qd = dq[0] * w + dq[1] * x + dq[2] * y + dq[3] * z;
+    const float op = 1.0f / (1.0f + expf(-opacity_logits[i]));
+    const float dop = go * op * (1.0f - op);
+    if (accumulate) {
+        for (int k = 0; k < 3; ++k) o_m[k] += dm[k], o_s[k] += dls[k];
+        o_q[0] += (dq[0] - qd * w) * p.qinv;
+        o_q[1] += (dq[1] - qd * x) * p.qinv;
+        o_q[2] += (dq[2] - qd * y) * p.qinv;
+        o_q[3] += (dq[3] - qd * z) * p.qinv;
+        *o_o += dop;
+    } else {
+        for (int k = 0; k < 3; ++k) o_m[k] = dm[k], o_s[k] = dls[k];
+        o_q[0] = (dq[0] - qd * w) * p.qinv;
+        o_q[1] = (dq[1] - qd * x) * p.qinv;
+        o_q[2] = (dq[2] - qd * y) * p.qinv;
+        o_q[3] = (dq[3] - qd * z) * p.qinv;
+        *o_o = dop;
+    }
+}
+
+} // namespace
+
+hipError_t launch_preprocess_fwd(const gsr_scene &s, const DevCamera &cam, float4 *rec, int32_t *radius,
+                                 uint32_t *tiles_touched, uint32_t *depth_key, uint32_t *ids, uint8_t *clamp_mask,
+                                 hipStream_t st) {
+    if (s.n <= 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((s.n + 255) / 256);
+#define GSR_PF(D)                                                                                                  \
+    preprocess_fwd_kernel<D><<<blocks, 256, 0, st>>>(s.n, s.means3d, s.log_scales, s.quats, s.opacity_logits, s.sh, \
+                                                      cam, rec, radius, tiles_touched, depth_key, ids, clamp_mask)
+    switch (s.sh_degree) {
+    case 0: GSR_PF(0); break;
+    case 1: GSR_PF(1); break;
+    case 2: GSR_PF(2); break;
+    default: GSR_PF(3); break;
+    }
+#undef GSR_PF
+    return hipGetLastError();
+}
+
+hipError_t launch_preprocess_bwd(const gsr_scene &s, const DevCamera &cam, const int32_t *radius, const float *acc,
+                                 const gsr_grads &out, int accumulate, hipStream_t st) {
+    if (s.n <= 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((s.n + 255) / 256);
+#define GSR_PB(D)                                                                                                  \
+    preprocess_bwd_kernel<D><<<blocks, 256, 0, st>>>(s.n, s.means3d, s.log_scales, s.quats, s.opacity_logits, s.sh, \
+                                                      cam, radius, acc, out, accumulate)
+    switch (s.sh_degree) {
+    case 0: GSR_PB(0); break;
+    case 1: GSR_PB(1); break;
+    case 2: GSR_PB(2); break;
+    default: GSR_PB(3); break;
+    }
+#undef GSR_PB
+    return hipGetLastError();
+}
+
+} // namespace gsr

@@ -1,0 +1,351 @@
+// Tile binning for the 3DGS rasteriser: device exclusive scan, stable LSD
+// radix sort, (tile, Gaussian) pair emission and per-tile ranges.
+//
+// The lists the gradient kernel consumes are ordered by (tile, depth, index)
+// (3DGS sorts one composite (tile, depth) key). Here the LSD radix sort of
+// that composite key is split in two: the depth digits are sorted over the n
+// Gaussians before the pairs are emitted (emission in depth order keeps the
+// relative order of equal tiles), then only the tile digits are sorted over
+// the P pairs. Same order, but P is touched by 1-2 passes instead of ~6.
+#include "device_common.hpp"
+
+namespace gsr {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kItems = 16;
+constexpr int kTileItems = kThreads * kItems; // 4096 items per block
+constexpr int kWaves = kThreads / 64;
+
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v, int lane) {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t o = __shfl_up(v, d, 64);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
+// Exclusive scan of one value per thread across the block; returns the
+// thread's exclusive prefix and the block total.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *s_wave, uint32_t &total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t inc = wave_inclusive_scan(v, lane);
+    if (lane == 63) s_wave[wave] = inc;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        uint32_t x = s_wave[w];
+        off += (w < wave) ? x : 0u;
+        tot += x;
+    }
+    __syncthreads();
+    total = tot;
+    return off + inc - v;
+}
+
+__device__ __forceinline__ uint32_t load_item(const uint32_t *in, const uint32_t *gather, int64_t i) {
+    return gather ? in[gather[i]] : in[i];
+}
+
+// Per-block sums of 4096 consecutive items.
+__global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const uint32_t *in, const uint32_t *gather,
+                                                               int64_t n, uint32_t *partials) {
+    __shared__ uint32_t s_wave[kWaves];
+    const int64_t base = (int64_t)blockIdx.x * kTileItems;
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        int64_t i = base + (int64_t)k * kThreads + threadIdx.x;
+        if (i < n) s += load_item(in, gather, i);
+    }
+    uint32_t total;
+    block_exclusive_scan(s, s_wave, total);
+    if (threadIdx.x == 0) partials[blockIdx.x] = total;
+}
+
+// Exclusive scan of each block's 4096 items plus the block's offset
+// (offsets == nullptr: single block, offset 0). Thread t owns items
+// [t*16, t*16+16) of the block so the order is the natural one.
+__global__ __launch_bounds__(kThreads) void scan_apply_kernel(const uint32_t *in, const uint32_t *gather, int64_t n,
+                                                              const uint32_t *offsets, uint32_t *out,
+                                                              uint32_t *total_out) {
+    __shared__ uint32_t s_wave[kWaves];
+    const int64_t base = (int64_t)blockIdx.x * kTileItems + (int64_t)threadIdx.x * kItems;
+    uint32_t v[kItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        int64_t i = base + k;
+        v[k] = (i < n) ? load_item(in, gather, i) : 0u;
+        s += v[k];
+    }
+    uint32_t total;
+    uint32_t run = block_exclusive_scan(s, s_wave, total) + (offsets ? offsets[blockIdx.x] : 0u);
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        int64_t i = base + k;
+        if (i < n) out[i] = run;
+        run += v[k];
+    }
+    if (total_out && blockIdx.x == gridDim.x - 1 && threadIdx.x == kThreads - 1) {
+        // Last item of the last block: its exclusive prefix plus itself is the grand total.
+        *total_out = run;
+    }
+}
+
+} // namespace
+
+size_t scan_partial_count(int64_t n) {
+    // Level sizes: ceil(n/4096) + ceil(that/4096) + ... (plus slack).
+    size_t total = 0;
+    int64_t m = n;
+    while (m > kTileItems) {
+        m = (m + kTileItems - 1) / kTileItems;
+        total += (size_t)m + 1;
+    }
+    return total + 8;
+}
+
+hipError_t device_exclusive_scan(const uint32_t *in, const uint32_t *gather, uint32_t *out, int64_t n,
+                                 uint32_t *total, uint32_t *partials, hipStream_t st) {
+    if (n <= 0) {
+        if (total) return launch_fill_u32(total, 0u, 1, st);
+        return hipSuccess;
+    }
+    const int64_t blocks = (n + kTileItems - 1) / kTileItems;
+    if (blocks == 1) {
+        scan_apply_kernel<<<1, kThreads, 0, st>>>(in, gather, n, nullptr, out, total);
+        return hipGetLastError();
+    }
+    scan_reduce_kernel<<<(unsigned)blocks, kThreads, 0, st>>>(in, gather, n, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // Scan the partials in place (recursively), then apply.
+    e = device_exclusive_scan(partials, nullptr, partials, blocks, nullptr, partials + blocks + 1, st);
+    if (e != hipSuccess) return e;
+    scan_apply_kernel<<<(unsigned)blocks, kThreads, 0, st>>>(in, gather, n, partials, out, total);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Radix sort: 8-bit digits (fewer in the last pass), reduce-then-scan.
+namespace {
+
+constexpr int kBins = 256;
+
+// Digit histogram of each 4096-item block, written digit-major so one
+// exclusive scan of the whole table yields every block's output offsets.
+__global__ __launch_bounds__(kThreads) void radix_hist_kernel(const uint32_t *keys, int64_t n, int shift,
+                                                              uint32_t mask, uint32_t *hist, int64_t blocks) {
+    __shared__ uint32_t s_count[kBins];
+    s_count[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kTileItems;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        int64_t i = base + (int64_t)k * kThreads + threadIdx.x;
+        if (i < n) atomicAdd(&s_count[(keys[i] >> shift) & mask], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * blocks + blockIdx.x] = s_count[threadIdx.x];
+}
+
+// Stable scatter of one 4096-item block. Wave w ranks items
+// [w*1024, (w+1)*1024) of the block in 16 rounds of 64; lanes with equal
+// digits find each other with one ballot per digit bit. Items are staged in
+// LDS in digit order and written out with consecutive threads on
+// consecutive addresses.
+__global__ __launch_bounds__(kThreads) void radix_scatter_kernel(const uint32_t *keys_in, const uint32_t *vals_in,
+                                                                 uint32_t *keys_out, uint32_t *vals_out, int64_t n,
+                                                                 int shift, int nbits, const uint32_t *offsets,
+                                                                 int64_t blocks) {
+    __shared__ uint32_t s_wcount[kWaves][kBins];
+    __shared__ uint32_t s_dstart[kBins];
+    __shared__ uint32_t s_wave[kWaves];
+    __shared__ uint32_t s_key[kTileItems];
+    __shared__ uint32_t s_val[kTileItems];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t mask = (1u << nbits) - 1u;
+    for (int i = threadIdx.x; i < kWaves * kBins; i += kThreads) (&s_wcount[0][0])[i] = 0;
+    __syncthreads();
+
+    const int64_t base = (int64_t)blockIdx.x * kTileItems;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint32_t key[kItems], val[kItems], pos[kItems];
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        const int64_t i = base + (int64_t)wave * (kItems * 64) + r * 64 + lane;
+        const bool valid = i < n;
+        key[r] = valid ? keys_in[i] : 0u;
+        val[r] = valid ? vals_in[i] : 0u;
+        const uint32_t d = (key[r] >> shift) & mask;
+        uint64_t peers = __ballot(valid);
+        for (int b = 0; b < nbits; ++b) {
+            const uint64_t bal = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? bal : ~bal;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
+        const int leader = __ffsll((long long)peers) - 1;
+        uint32_t old = 0;
+        if (valid && rank == 0) old = atomicAdd(&s_wcount[wave][d], (uint32_t)__popcll(peers));
+        old = __shfl(old, leader < 0 ? 0 : leader, 64);
+        pos[r] = valid ? old + rank : 0xffffffffu;
+    }
+    __syncthreads();
+    // Per digit: exclusive prefix over the waves, then over the digits.
+    uint32_t tot = 0;
+    {
+        const int d = threadIdx.x; // kThreads == kBins
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            uint32_t c = s_wcount[w][d];
+            s_wcount[w][d] = tot;
+            tot += c;
+        }
+    }
+    uint32_t block_total;
+    const uint32_t dstart = block_exclusive_scan(tot, s_wave, block_total);
+    s_dstart[threadIdx.x] = dstart;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        if (pos[r] == 0xffffffffu) continue;
+        const uint32_t d = (key[r] >> shift) & mask;
+        const uint32_t slot = s_dstart[d] + s_wcount[wave][d] + pos[r];
+        s_key[slot] = key[r];
+        s_val[slot] = val[r];
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < block_total; i += kThreads) {
+        const uint32_t k = s_key[i];
+        const uint32_t d = (k >> shift) & mask;
+        const int64_t dst = (int64_t)offsets[(int64_t)d * blocks + blockIdx.x] + (i - s_dstart[d]);
+        keys_out[dst] = k;
+        vals_out[dst] = s_val[i];
+    }
+}
+
+} // namespace
+
+size_t radix_hist_count(int64_t n) {
+    const int64_t blocks = (n + kTileItems - 1) / kTileItems;
+    return (size_t)blocks * kBins + 8;
+}
+
+hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n, int bits,
+                            uint32_t *hist, uint32_t *partials, int *which, hipStream_t st) {
+    *which = 0;
+    if (n <= 1 || bits <= 0) return hipSuccess;
+    const int64_t blocks = (n + kTileItems - 1) / kTileItems;
+    uint32_t *ks[2] = {k0, k1}, *vs[2] = {v0, v1};
+    int cur = 0;
+    for (int shift = 0; shift < bits; shift += 8) {
+        const int nb = (bits - shift) < 8 ? (bits - shift) : 8;
+        const uint32_t mask = (1u << nb) - 1u;
+        radix_hist_kernel<<<(unsigned)blocks, kThreads, 0, st>>>(ks[cur], n, shift, mask, hist, blocks);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        e = device_exclusive_scan(hist, nullptr, hist, blocks * kBins, nullptr, partials, st);
+        if (e != hipSuccess) return e;
+        radix_scatter_kernel<<<(unsigned)blocks, kThreads, 0, st>>>(ks[cur], vs[cur], ks[cur ^ 1], vs[cur ^ 1], n,
+                                                                     shift, nb, hist, blocks);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        cur ^= 1;
+    }
+    *which = cur;
+    return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+namespace {
+
+__global__ __launch_bounds__(256) void emit_pairs_kernel(int64_t n, const uint32_t *sorted_ids,
+                                                          const uint32_t *offsets, const float4 *rec,
+                                                          const int32_t *radius, DevCamera cam, uint32_t *pair_tile,
+                                                          uint32_t *pair_id) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t g = sorted_ids[i];
+    const int r = radius[g];
+    if (r <= 0) return;
+    const float4 r0 = rec[3 * (int64_t)g];
+    int x0, x1, y0, y1;
+    rect_of(r0.x, r0.y, r, cam, x0, x1, y0, y1);
+    uint32_t o = offsets[i];
+    for (int ty = y0; ty < y1; ++ty)
+        for (int tx = x0; tx < x1; ++tx) {
+            pair_tile[o] = (uint32_t)(ty * cam.grid_x + tx);
+            pair_id[o] = g;
+            ++o;
+        }
+}
+
+__global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t *p, uint32_t value, int64_t count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = value;
+}
+
+__global__ __launch_bounds__(256) void tile_ranges_kernel(int64_t P, const uint32_t *tile, uint2 *ranges) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P) return;
+    const uint32_t t = tile[i];
+    if (i == 0 || tile[i - 1] != t) ranges[t].x = (uint32_t)i;
+    if (i == P - 1 || tile[i + 1] != t) ranges[t].y = (uint32_t)(i + 1);
+}
+
+} // namespace
+
+hipError_t launch_emit_pairs(int64_t n, const uint32_t *sorted_ids, const uint32_t *offsets, const float4 *rec,
+                             const int32_t *radius, const DevCamera &cam, uint32_t *pair_tile, uint32_t *pair_id,
+                             hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    emit_pairs_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, sorted_ids, offsets, rec, radius, cam,
+                                                                   pair_tile, pair_id);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    fill_u32_kernel<<<(unsigned)((count + 255) / 256), 256, 0, st>>>(p, value, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_ranges(int64_t P, const uint32_t *sorted_tile, uint2 *ranges, int64_t n_tiles,
+                              hipStream_t st) {
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), 0u, 2 * n_tiles, st);
+    if (e != hipSuccess || P <= 0) return e;
+    tile_ranges_kernel<<<(unsigned)((P + 255) / 256), 256, 0, st>>>(P, sorted_tile, ranges);
+    return hipGetLastError();
+}
+
+} // namespace gsr
+
+namespace gsr {
+namespace {
+
+// out[0] += number of entries with r[i] > 0 (one atomic per block).
+__global__ __launch_bounds__(256) void count_positive_kernel(const int32_t *r, int64_t n, uint32_t *out) {
+    __shared__ uint32_t s_wave[4];
+    uint32_t c = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        c += r[i] > 0 ? 1u : 0u;
+    uint32_t total;
+    block_exclusive_scan(c, s_wave, total);
+    if (threadIdx.x == 0 && total) atomicAdd(out, total);
+}
+
+} // namespace
+
+hipError_t launch_count_positive(const int32_t *r, int64_t n, uint32_t *out, hipStream_t st) {
+    hipError_t e = launch_fill_u32(out, 0u, 1, st);
+    if (e != hipSuccess || n <= 0) return e;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    count_positive_kernel<<<(unsigned)blocks, 256, 0, st>>>(r, n, out);
+    return hipGetLastError();
+}
+
+} // namespace gsr

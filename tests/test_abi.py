@@ -1,0 +1,101 @@
+"""The C-ABI library loads on a machine without a GPU, exports every function
+include/gsr.h declares, and its host-only argument checks behave (no device
+calls are made here)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2401_05345_amd import gsr
+from paper_2401_05345_amd import scenegen as sg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "gsr.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(gsr_[a-z_0-9]+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(gsr.LIB_PATH):
+        from paper_2401_05345_amd import build
+        build.build()
+    return gsr.load()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("gsr_ctx_create", "gsr_render", "gsr_backward", "gsr_fwd_release", "gsr_validate_scene",
+                 "gsr_wave_reduce_selftest", "gsr_fwd_export", "gsr_bwd_counters"):
+        assert must in names
+    assert len(names) >= 19
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(declared_functions()) <= set(gsr._PROTOS), "binding lacks a prototype"
+
+
+def test_version(lib):
+    assert "gfx950" in gsr.gsr_version()
+
+
+def _cam(**kw):
+    c = sg.make_camera(64, 48, (0.0, 0.0, -3.0))
+    cam = gsr.make_camera(c.width, c.height, c.fx, c.fy, c.cx, c.cy, c.world_to_cam)
+    for k, v in kw.items():
+        setattr(cam, k, v)
+    return cam
+
+
+def test_validate_camera(lib):
+    assert gsr.gsr_validate_camera(_cam()) == gsr.GSR_OK
+    assert gsr.gsr_validate_camera(_cam(width=0)) == gsr.GSR_EINVAL
+    assert gsr.gsr_validate_camera(_cam(fx=float("nan"))) == gsr.GSR_EINVAL
+    assert gsr.gsr_validate_camera(_cam(fy=-1.0)) == gsr.GSR_EINVAL
+    assert gsr.gsr_validate_camera(_cam(znear=0.0)) == gsr.GSR_EINVAL
+    bad = _cam()
+    bad.world_to_cam[0] = 2.0          # not a rotation
+    assert gsr.gsr_validate_camera(bad) == gsr.GSR_EINVAL
+
+
+def test_validate_scene(lib):
+    ok = gsr.gsr_scene(0, 0, None, None, None, None, None)
+    assert gsr.gsr_validate_scene(ok) == gsr.GSR_OK          # empty scene is valid
+    assert gsr.gsr_validate_scene(gsr.gsr_scene(5, 0, None, None, None, None, None)) == gsr.GSR_EINVAL
+    assert gsr.gsr_validate_scene(gsr.gsr_scene(-1, 0, None, None, None, None, None)) == gsr.GSR_EINVAL
+    p = ctypes.c_void_p(64)
+    assert gsr.gsr_validate_scene(gsr.gsr_scene(5, 3, p, p, p, p, p)) == gsr.GSR_OK
+    assert gsr.gsr_validate_scene(gsr.gsr_scene(5, 4, p, p, p, p, p)) == gsr.GSR_EINVAL
+
+
+@pytest.mark.parametrize("tile,batch,ok", [(16, 256, True), (8, 64, True), (8, 128, False), (32, 256, True),
+                                            (12, 64, False), (16, 96, False)])
+def test_validate_config_tiles(lib, tile, batch, ok):
+    cfg = gsr.make_config(tile=tile, lds_batch=batch)
+    assert (gsr.gsr_validate_config(cfg, _cam()) == gsr.GSR_OK) == ok
+
+
+def test_validate_config_modes_and_thresholds(lib):
+    for thr in (0, 1, 32, 64, 65):
+        assert gsr.gsr_validate_config(gsr.make_config(reduce_threshold=thr)) == gsr.GSR_OK
+    for thr in (-1, 66):
+        assert gsr.gsr_validate_config(gsr.make_config(reduce_threshold=thr)) == gsr.GSR_EINVAL
+    assert gsr.gsr_validate_config(gsr.make_config(bwd_mode=2)) == gsr.GSR_EINVAL
+    assert gsr.gsr_validate_config(gsr.make_config(flags=1 << 10)) == gsr.GSR_EINVAL
+
+
+def test_ctx_create_without_gpu_reports_error(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    out = ctypes.c_void_p()
+    st = lib.gsr_ctx_create(ctypes.byref(out), 0, None)
+    assert st != gsr.GSR_OK and not out.value

@@ -1,0 +1,192 @@
+"""GPU parity: the HIP path through the C ABI against the fp64 oracle.
+
+Tolerances (stated for the path): relative L2 <= 1e-5 on the image and <= 1e-3
+on each gradient tensor (atomic order is free). Integer results (radius, tile
+counts, sort order, n_contrib) are compared exactly. Pixels whose per-pixel
+decision sits within 1e-4 (relative) of its threshold, or whose tile is next to
+a Gaussian whose radius/rectangle decision sits within 1e-3 px of a flip, admit
+several correct results; they are excluded from the exact comparisons and
+checked to be few.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2401_05345_amd import gsr
+from paper_2401_05345_amd import scenegen as sg
+from gpu_util import (GpuScene, run_render, run_backward, tie_pixels, geometric_ties, oracle_dl_dimage,
+                      rel_l2, say)
+
+pytestmark = pytest.mark.gpu
+
+NAMES = ["means3d", "log_scales", "quats", "opacity_logits", "sh"]
+
+
+@pytest.fixture(scope="module")
+def renderer(gsr):
+    import torch
+    r = gsr.Renderer(0)
+    yield r
+    torch.cuda.synchronize()
+    r.close()
+
+
+def _check_forward(out, rr, tile):
+    pr = rr.proj
+    # radius / tile counts: exact, except Gaussians sitting on a geometric tie (checked inside).
+    differ, _ = geometric_ties(rr, out)
+    assert differ.size <= max(3, 0.002 * pr.n), differ.size
+    same = np.ones(pr.n, bool)
+    same[differ] = False
+    # depth key: the same fp32 formula on both sides, so bit-exact for every listed Gaussian.
+    vis = pr.visible & same
+    assert np.array_equal(out["depth"][vis].view(np.uint32), pr.depth_key[vis].view(np.uint32))
+    assert np.array_equal(out["radius"] > 0, pr.visible | ~same) or differ.size > 0
+    # projected values (fp32 vs fp64)
+    v = np.nonzero(pr.visible & (out["radius"] > 0))[0]
+    assert rel_l2(out["mean2d"][v], pr.mean2d[v]) < 1e-6
+    assert rel_l2(out["conic_opacity"][v, :3], pr.conic[v]) < 2e-6
+    assert rel_l2(out["conic_opacity"][v, 3], pr.opacity[v]) < 1e-6
+    assert rel_l2(out["rgb"][v], pr.rgb[v]) < 1e-6
+    assert np.array_equal(out["clamp_mask"][v], pr.clamp_mask[v])
+    # lists: exact per tile unless a geometric tie changes the tile's membership
+    _, tie_tiles = geometric_ties(rr, out)
+    ties = tie_pixels(rr, out)
+    gx, gy = pr.grid
+    bad_tiles = 0
+    for t in range(gx * gy):
+        a, b = out["ranges"][t]
+        o0, o1 = rr.lists.tile_start[t], rr.lists.tile_start[t + 1]
+        if (t % gx, t // gx) in tie_tiles:
+            continue
+        if not np.array_equal(out["sorted_ids"][a:b], rr.lists.ids[o0:o1]):
+            bad_tiles += 1
+    assert bad_tiles == 0
+    assert len(tie_tiles) <= max(2, 0.01 * gx * gy)
+    # per-pixel decisions and the image
+    keep = ~ties
+    assert ties.mean() < 0.01, ties.mean()
+    assert np.array_equal(out["n_contrib"][keep], rr.n_contrib[keep])
+    assert rel_l2(out["T_final"][keep], rr.T_final[keep]) < 1e-5
+    img_err = rel_l2(out["image"][:, keep], rr.image[:, keep])
+    assert img_err <= 1e-5, img_err
+    assert np.isfinite(out["image"]).all()
+    return img_err, ties
+
+
+def _check_grads(grads_gpu, acc_gpu, acc_ref, grads_ref, tol=1e-3):
+    errs = {}
+    for name, g, ref in zip(NAMES, grads_gpu, grads_ref):
+        assert np.isfinite(g).all(), name
+        errs[name] = rel_l2(g, ref)
+        assert errs[name] <= tol, (name, errs[name])
+    errs["acc9"] = rel_l2(acc_gpu, acc_ref)
+    assert errs["acc9"] <= tol
+    return errs
+
+
+def _workload_tiny():
+    wl = sg.tiny_1k()
+    return wl, wl.camera.with_bg((0.1, 0.3, 0.2))
+
+
+@pytest.mark.parametrize("mode,thr,flags", [
+    (gsr.GSR_BWD_PLAIN_ATOMIC, 0, 0),
+    (gsr.GSR_BWD_WAVE_REDUCE, 0, 0),
+    (gsr.GSR_BWD_WAVE_REDUCE, 32, 0),
+    (gsr.GSR_BWD_WAVE_REDUCE, 64, 0),
+    (gsr.GSR_BWD_WAVE_REDUCE, 65, 0),
+    (gsr.GSR_BWD_WAVE_REDUCE, 8, gsr.GSR_FLAG_LANE_SPLIT_ATOMICS),
+    (gsr.GSR_BWD_WAVE_REDUCE, 16, gsr.GSR_FLAG_XCD_REMAP),
+])
+def test_tiny_parity(renderer, mode, thr, flags):
+    say(f"[gpu] tiny_1k parity mode={mode} thr={thr} flags={flags}")
+    wl, cam = _workload_tiny()
+    rr = oracle.render(wl.scene, cam)
+    dl = oracle_dl_dimage(rr, wl.target, "l1")
+    acc_ref, grads_ref = oracle.backward(wl.scene, rr, dl.astype(np.float64))
+    gs = GpuScene(wl.scene, cam)
+    cfg = gsr.make_config(16, 256, mode, thr, flags)
+    st, out = run_render(renderer, gs, cfg)
+    try:
+        _check_forward(out, rr, 16)
+        grads, acc, _ = run_backward(renderer, gs, st, dl, cfg)
+        _check_grads(grads, acc, acc_ref, grads_ref)
+    finally:
+        gsr.gsr_fwd_release(renderer.ctx, st)
+
+
+@pytest.mark.parametrize("tile,batch", [(8, 64), (16, 64), (16, 128), (32, 128), (32, 256)])
+def test_tiles_and_batches_ragged_image(renderer, tile, batch):
+    # 60x50 is not a multiple of any tile size: partial tiles have inactive lanes.
+    say(f"[gpu] ragged 60x50 tile={tile} batch={batch}")
+    wl = sg.tiny_scene(12, 300, 60, 50, sh_degree=2, log_scale=(-2.6, 0.5), half=0.7)
+    cam = wl.camera.with_bg((0.3, 0.1, 0.6))
+    rr = oracle.render(wl.scene, cam, tile)
+    dl = oracle_dl_dimage(rr, wl.target, "l1")
+    acc_ref, grads_ref = oracle.backward(wl.scene, rr, dl.astype(np.float64))
+    gs = GpuScene(wl.scene, cam)
+    for mode in (gsr.GSR_BWD_PLAIN_ATOMIC, gsr.GSR_BWD_WAVE_REDUCE):
+        cfg = gsr.make_config(tile, batch, mode, 24, 0)
+        st, out = run_render(renderer, gs, cfg)
+        try:
+            _check_forward(out, rr, tile)
+            grads, acc, _ = run_backward(renderer, gs, st, dl, cfg)
+            _check_grads(grads, acc, acc_ref, grads_ref)
+        finally:
+            gsr.gsr_fwd_release(renderer.ctx, st)
+
+
+def test_object_100k_parity_and_modes(renderer):
+    # 100k Gaussians, 800x800, SH degree 3, L1 + 0.2 D-SSIM against the perturbed scene's render.
+    say("[gpu] object_100k parity")
+    wl = sg.object_100k()
+    cam = wl.camera
+    rr = oracle.render(wl.scene, cam)
+    target = oracle.render(wl.perturbed, cam).image
+    dl = oracle_dl_dimage(rr, target, "l1_dssim")
+    acc_ref, grads_ref = oracle.backward(wl.scene, rr, dl.astype(np.float64))
+    gs = GpuScene(wl.scene, cam)
+    cfg = gsr.make_config(16, 256, gsr.GSR_BWD_WAVE_REDUCE, 32, gsr.GSR_FLAG_DEBUG_COUNTERS)
+    st, out = run_render(renderer, gs, cfg)
+    try:
+        img_err, ties = _check_forward(out, rr, 16)
+        say(f"[gpu] object_100k image rel-L2 {img_err:.3e}, tie pixels {ties.sum()}")
+        for mode, thr, flags in [(gsr.GSR_BWD_WAVE_REDUCE, 32, 0), (gsr.GSR_BWD_PLAIN_ATOMIC, 0, 0),
+                                 (gsr.GSR_BWD_WAVE_REDUCE, 1, gsr.GSR_FLAG_LANE_SPLIT_ATOMICS)]:
+            grads, acc, _ = run_backward(renderer, gs, st, dl, gsr.make_config(16, 256, mode, thr, flags))
+            errs = _check_grads(grads, acc, acc_ref, grads_ref)
+            say(f"[gpu] object_100k mode={mode} thr={thr} grad rel-L2 {errs}")
+    finally:
+        gsr.gsr_fwd_release(renderer.ctx, st)
+
+
+def test_forward_is_bitwise_deterministic(renderer):
+    say("[gpu] determinism")
+    wl = sg.object_100k(n=20000, width=320, height=240)
+    gs = GpuScene(wl.scene, wl.camera)
+    cfg = gsr.make_config()
+    outs = []
+    for _ in range(2):
+        st, out = run_render(renderer, gs, cfg)
+        gsr.gsr_fwd_release(renderer.ctx, st)
+        outs.append(out)
+    for k in ("image", "sorted_ids", "ranges", "T_final", "n_contrib", "radius"):
+        assert np.array_equal(outs[0][k].view(np.uint8), outs[1][k].view(np.uint8)), k
+
+
+def test_accumulate_adds(renderer):
+    say("[gpu] accumulate")
+    wl, cam = _workload_tiny()
+    gs = GpuScene(wl.scene, cam)
+    cfg = gsr.make_config(16, 256, gsr.GSR_BWD_WAVE_REDUCE, 32)
+    st, out = run_render(renderer, gs, cfg)
+    try:
+        rr = oracle.render(wl.scene, cam)
+        dl = oracle_dl_dimage(rr, wl.target, "l1")
+        g1, _, held = run_backward(renderer, gs, st, dl, cfg)
+        g2, _, _ = run_backward(renderer, gs, st, dl, cfg, accumulate=1, grads=held)
+        for a, b in zip(g1, g2):
+            assert rel_l2(b, 2 * a) < 1e-4      # two backwards differ only by atomic summation order
+    finally:
+        gsr.gsr_fwd_release(renderer.ctx, st)
