@@ -56,6 +56,11 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--threshold", type=int, default=None, help="fix the threshold (skip the sweep)")
     p.add_argument("--profile-only", action="store_true", help="only the timed steps (for rocprofv3 runs)")
+    p.add_argument("--mode", default="reduce", choices=["reduce", "plain"], help="backward mode of --profile-only")
+    p.add_argument("--lane-split", action="store_true", help="reduced sums issued by lanes 0..8 in one instruction")
+    p.add_argument("--xcd-remap", action="store_true", help="map neighbouring tiles to one XCD")
+    p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                   help="only run a plain device copy of MIB MiB five times (reference for HBM counters)")
     return p.parse_args()
 
 
@@ -83,8 +88,10 @@ class Bench:
         else:
             self.target = torch.from_numpy(wl.target).to(dev)
 
+    extra_flags = 0
+
     def cfg(self, mode, thr, flags=0):
-        return self.gsr.make_config(16, 256, mode, thr, flags | self.gsr.GSR_FLAG_STAGE_TIMING)
+        return self.gsr.make_config(16, 256, mode, thr, flags | self.extra_flags | self.gsr.GSR_FLAG_STAGE_TIMING)
 
     def step(self, cfg):
         """One whole pass; returns (stage times, frame stats)."""
@@ -121,7 +128,7 @@ class Bench:
 
     def counters(self, fr, mode, thr):
         gsr = self.gsr
-        cfg = gsr.make_config(16, 256, mode, thr, gsr.GSR_FLAG_DEBUG_COUNTERS)
+        cfg = gsr.make_config(16, 256, mode, thr, gsr.GSR_FLAG_DEBUG_COUNTERS | self.extra_flags)
         gsr.gsr_backward(self.r.ctx, fr.state, self.dl, self.gstruct, 0, cfg)
         return gsr.gsr_bwd_counters(self.r.ctx, fr.state)
 
@@ -174,26 +181,38 @@ def main():
     import torch
     from paper_2401_05345_amd import gsr
     from paper_2401_05345_amd import scenegen as sg
-    gsr.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": n * 4, "launches": 5}))
+        return
+    gsr.load()
 
     wl = sg.WORKLOADS[args.workload]()
     log(f"[bench] workload {wl.name}: {wl.scene.n} Gaussians, {wl.camera.width}x{wl.camera.height}")
+    Bench.extra_flags = ((gsr.GSR_FLAG_LANE_SPLIT_ATOMICS if args.lane_split else 0) |
+                         (gsr.GSR_FLAG_XCD_REMAP if args.xcd_remap else 0))
     b = Bench(wl)
 
     # Threshold: one backward per candidate on a warm forward state (the paper's tuning rule).
-    fr = b.forward_state(b.cfg(gsr.GSR_BWD_WAVE_REDUCE, 32))
-    b.backward_only(fr, b.cfg(gsr.GSR_BWD_WAVE_REDUCE, 32), 2)
     sweep = None
     if args.threshold is None and not args.profile_only:
+        fr = b.forward_state(b.cfg(gsr.GSR_BWD_WAVE_REDUCE, 32))
+        b.backward_only(fr, b.cfg(gsr.GSR_BWD_WAVE_REDUCE, 32), 2)
         sweep = b.sweep(fr)
         thr = min(sweep, key=sweep.get)
         log(f"[bench] threshold sweep (a6 ms): {sweep} -> {thr}")
+        b.r.release(fr)
     else:
+        # Profiled runs launch only the configuration they measure.
         thr = args.threshold if args.threshold is not None else 32
-    b.r.release(fr)
 
-    cfg_r = b.cfg(gsr.GSR_BWD_WAVE_REDUCE, thr)
+    cfg_r = b.cfg(gsr.GSR_BWD_WAVE_REDUCE if args.mode == "reduce" else gsr.GSR_BWD_PLAIN_ATOMIC, thr)
     for _ in range(args.warmup):
         b.step(cfg_r)
     torch.cuda.synchronize()
