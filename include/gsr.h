@@ -57,7 +57,7 @@ enum {
 
 /* Number of floats reserved per Gaussian in the backward accumulators:
  * (dL/du, dL/dv, dL/dA, dL/dB, dL/dC, dL/do, dL/dr, dL/dg, dL/db, pad...). */
-#define GSR_ACC_STRIDE 12
+#define GSR_ACC_STRIDE 16
 
 /* Learnable scene. n >= 0; sh_degree 0..3, K = (sh_degree+1)^2 coefficients.
  *  means3d [n,3], log_scales [n,3], quats [n,4] as (w,x,y,z) (need not be

@@ -92,15 +92,16 @@ __global__ __launch_bounds__(TILE *TILE) void composite_fwd_kernel(DevCamera cam
                                                                    uint32_t *__restrict__ n_contrib) {
     constexpr int NT = TILE * TILE;
     constexpr int QX = TILE / 8;
-    __shared__ float4 s0[BATCH], s1[BATCH];
-    __shared__ float sb[BATCH];
+    __shared__ float4 s0[BATCH], s1[BATCH], s2[BATCH];
     const int tile = tile_for_block(blockIdx.x, n_tiles, remap);
     if (tile >= n_tiles) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int px = (tile % cam.grid_x) * TILE + (wave % QX) * 8 + (lane & 7);
-    const int py = (tile / cam.grid_x) * TILE + (wave / QX) * 8 + (lane >> 3);
+    const int qx0 = (tile % cam.grid_x) * TILE + (wave % QX) * 8;
+    const int qy0 = (tile / cam.grid_x) * TILE + (wave / QX) * 8;
+    const int px = qx0 + (lane & 7), py = qy0 + (lane >> 3);
     const bool inside = px < cam.width && py < cam.height;
     const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+    const float qcx = (float)qx0 + 4.0f, qcy = (float)qy0 + 4.0f; // centre of the wave's 8x8 sample points
     const uint2 rg = ranges[tile];
     float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
     uint32_t last = 0;
@@ -112,12 +113,16 @@ __global__ __launch_bounds__(TILE *TILE) void composite_fwd_kernel(DevCamera cam
             const uint32_t g = ids[k];
             s0[tid] = rec[3 * (size_t)g];
             s1[tid] = rec[3 * (size_t)g + 1];
-            sb[tid] = rec[3 * (size_t)g + 2].x;
+            s2[tid] = rec[3 * (size_t)g + 2];
         }
         __syncthreads();
         const int cnt = min(BATCH, (int)(rg.y - start));
         for (int j = 0; j < cnt && !done; ++j) {
-            const float4 a = s0[j], b = s1[j];
+            const float4 a = s0[j], c = s2[j];
+            // No sample point of this wave lies inside the splat's alpha >= 1/255 box (3.5 px half-width
+            // plus 1 px margin): every lane would skip it.
+            if (fabsf(a.x - qcx) > c.z + 4.5f || fabsf(a.y - qcy) > c.w + 4.5f) continue;
+            const float4 b = s1[j];
             const SplatEval e = eval_splat(fpx, fpy, a.x, a.y, a.z, a.w, b.x, b.y);
             if (!e.pass) continue;
             const float Tn = T * (1.0f - e.alpha);
@@ -128,7 +133,7 @@ __global__ __launch_bounds__(TILE *TILE) void composite_fwd_kernel(DevCamera cam
             const float w = e.alpha * T;
             c0 = fmaf(w, b.z, c0);
             c1 = fmaf(w, b.w, c1);
-            c2 = fmaf(w, sb[j], c2);
+            c2 = fmaf(w, c.x, c2);
             T = Tn;
             last = start - rg.x + (uint32_t)j + 1;
         }
@@ -149,18 +154,19 @@ enum { CNT_EVAL = 0, CNT_ACTIVE, CNT_WAVE_ENTRIES, CNT_REDUCED, CNT_PLAIN_LANES,
 template <int TILE, int BATCH, int MODE, bool COUNT, bool SPLIT>
 __global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(DevCamera cam, int remap, int n_tiles, BwdArgs a) {
     constexpr int QX = TILE / 8;
-    __shared__ float4 s0[BATCH], s1[BATCH];
-    __shared__ float sb[BATCH];
+    __shared__ float4 s0[BATCH], s1[BATCH], s2[BATCH];
     __shared__ uint32_t sid[BATCH];
     __shared__ uint32_t s_walk;
     __shared__ unsigned long long s_cnt[COUNT ? CNT_HIST + 65 : 1];
     const int tile = tile_for_block(blockIdx.x, n_tiles, remap);
     if (tile >= n_tiles) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int px = (tile % cam.grid_x) * TILE + (wave % QX) * 8 + (lane & 7);
-    const int py = (tile / cam.grid_x) * TILE + (wave / QX) * 8 + (lane >> 3);
+    const int qx0 = (tile % cam.grid_x) * TILE + (wave % QX) * 8;
+    const int qy0 = (tile / cam.grid_x) * TILE + (wave / QX) * 8;
+    const int px = qx0 + (lane & 7), py = qy0 + (lane >> 3);
     const bool inside = px < cam.width && py < cam.height;
     const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+    const float qcx = (float)qx0 + 4.0f, qcy = (float)qy0 + 4.0f;
     const size_t hw = (size_t)cam.width * cam.height;
     const size_t pix = inside ? (size_t)py * cam.width + px : 0;
     float T = inside ? a.T_final[pix] : 1.0f;
@@ -175,13 +181,22 @@ __global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(DevCamera cam
     if (COUNT)
         for (int i = tid; i < CNT_HIST + 65; i += TILE * TILE) s_cnt[i] = 0;
     __syncthreads();
-    const uint32_t wmax = wave_max_u32(nc);
+    // Entries past every pixel's n_contrib contribute nothing: the block walks to its deepest
+    // pixel, each wave only to its own.
+    const uint32_t wmax = (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_max_u32(nc));
     if (lane == 0) atomicMax(&s_walk, wmax);
     __syncthreads();
-    const int walk = (int)s_walk; // entries past every pixel's n_contrib contribute nothing
+    const int walk = (int)s_walk;
 
     uint64_t c_eval = 0, c_active = 0, c_we = 0, c_red = 0, c_plain = 0, c_instr = 0;
     uint32_t issued = 0;
+    if (COUNT) {
+        // E = sum of n_contrib: every pixel walks its entries 1..n_contrib.
+        uint32_t s = nc;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) s += (uint32_t)__shfl_xor((int)s, d, 64);
+        c_eval = s;
+    }
 
     for (int end = walk; end > 0; end -= BATCH) {
         const int start = end > BATCH ? end - BATCH : 0;
@@ -192,13 +207,17 @@ __global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(DevCamera cam
             sid[tid] = g;
             s0[tid] = a.rec[3 * (size_t)g];
             s1[tid] = a.rec[3 * (size_t)g + 1];
-            sb[tid] = a.rec[3 * (size_t)g + 2].x;
+            s2[tid] = a.rec[3 * (size_t)g + 2];
         }
         __syncthreads();
-        for (int j = cnt - 1; j >= 0; --j) {
+        const int jtop = min(cnt, (int)wmax - start) - 1;
+        for (int j = jtop; j >= 0; --j) {
             const uint32_t pos = (uint32_t)(start + j + 1);
-            const float4 r0 = s0[j], r1 = s1[j];
-            const float rb = sb[j];
+            const float4 r0 = s0[j], r2 = s2[j];
+            // Same conservative skip as the forward: no lane of this wave can pass this entry.
+            if (fabsf(r0.x - qcx) > r2.z + 4.5f || fabsf(r0.y - qcy) > r2.w + 4.5f) continue;
+            const float4 r1 = s1[j];
+            const float rb = r2.x;
             const SplatEval e = eval_splat(fpx, fpy, r0.x, r0.y, r0.z, r0.w, r1.x, r1.y);
             const bool walked = pos <= nc;
             const bool active = walked && e.pass;
@@ -228,9 +247,8 @@ __global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(DevCamera cam
             uint64_t red_mask;
             issued += emit9<MODE, SPLIT>(active, v, dst, a.threshold, lane, red_mask);
             if (COUNT) {
-                const uint64_t mw = __ballot(walked), ma = __ballot(active);
+                const uint64_t ma = __ballot(active);
                 const int ca = __popcll(ma);
-                c_eval += __popcll(mw);
                 c_active += ca;
                 if (ca) {
                     c_we += 1;

@@ -167,9 +167,17 @@ __global__ __launch_bounds__(256) void preprocess_fwd_kernel(int n, const float 
         }
     }
     const float o = 1.0f / (1.0f + expf(-opacity_logits[i]));
+    // Bounding box of the pixels this splat can reach: alpha >= 1/255 needs
+    // power >= -ln(255 o), i.e. d^T K d <= 2 ln(255 o), an ellipse whose
+    // half-extents are sqrt(2 ln(255 o) a) and sqrt(2 ln(255 o) c) (K^-1 =
+    // [[a, b], [b, c]]). Composite kernels use it only to skip work for
+    // wavefronts none of whose pixels can pass, with a pixel of margin.
+    const float tau = logf(255.0f * o);
+    const float ex = tau > 0.0f ? sqrtf(2.0f * tau * p.a) : -INFINITY;
+    const float ey = tau > 0.0f ? sqrtf(2.0f * tau * p.c) : -INFINITY;
     rec[3 * (int64_t)i] = make_float4(u, v, A, B);
     rec[3 * (int64_t)i + 1] = make_float4(C, o, rgb[0], rgb[1]);
-    rec[3 * (int64_t)i + 2] = make_float4(rgb[2], tz, 0.f, 0.f);
+    rec[3 * (int64_t)i + 2] = make_float4(rgb[2], tz, ex, ey);
     radius[i] = r;
     tiles_touched[i] = (uint32_t)ntiles;
     depth_key[i] = __float_as_uint(tz);
