@@ -86,10 +86,16 @@ __device__ __forceinline__ void project_splat(const DevCamera &cam, float mx, fl
 }
 
 // Depth key: ((R20*mx + R21*my) + R22*mz) + t2, one correctly rounded fp32
-// operation at a time, so the sort order is reproducible bit for bit.
+// operation at a time, so the sort order is reproducible bit for bit. The
+// operations are written in this scope with contraction off: helper
+// intrinsics would be inlined as plain products and sums, which the default
+// contraction mode may fuse into FMAs.
 __device__ __forceinline__ float depth_of(const DevCamera &cam, float mx, float my, float mz) {
-    return __fadd_rn(__fadd_rn(__fadd_rn(__fmul_rn(cam.R[6], mx), __fmul_rn(cam.R[7], my)), __fmul_rn(cam.R[8], mz)),
-                     cam.t[2]);
+#pragma clang fp contract(off)
+    const float a = cam.R[6] * mx;
+    const float b = cam.R[7] * my;
+    const float c = cam.R[8] * mz;
+    return ((a + b) + c) + cam.t[2];
 }
 
 template <int DEG>

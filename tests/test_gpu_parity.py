@@ -137,6 +137,28 @@ def test_tiles_and_batches_ragged_image(renderer, tile, batch):
             gsr.gsr_fwd_release(renderer.ctx, st)
 
 
+def test_rotated_camera_parity(renderer):
+    # A camera off the axes: the rotation's products round, so the fp32 depth key, the
+    # lists and the colours exercise every term of the projection.
+    say("[gpu] rotated camera parity")
+    wl = sg.tiny_scene(44, 2000, 96, 80, sh_degree=3, log_scale=(-3.0, 0.5), eye=(1.3, -0.9, -2.6), half=0.8)
+    cam = wl.camera.with_bg((0.05, 0.1, 0.15))
+    rr = oracle.render(wl.scene, cam)
+    dl = oracle_dl_dimage(rr, wl.target, "l1")
+    acc_ref, grads_ref = oracle.backward(wl.scene, rr, dl.astype(np.float64))
+    gs = GpuScene(wl.scene, cam)
+    cfg = gsr.make_config(16, 256, gsr.GSR_BWD_WAVE_REDUCE, 4, gsr.GSR_FLAG_LANE_SPLIT_ATOMICS)
+    st, out = run_render(renderer, gs, cfg)
+    try:
+        both = rr.proj.visible & (out["radius"] > 0)
+        assert np.array_equal(out["depth"][both].view(np.uint32), rr.proj.depth_key[both].view(np.uint32))
+        _check_forward(out, rr, 16)
+        grads, acc, _ = run_backward(renderer, gs, st, dl, cfg)
+        _check_grads(grads, acc, acc_ref, grads_ref)
+    finally:
+        gsr.gsr_fwd_release(renderer.ctx, st)
+
+
 def test_object_100k_parity_and_modes(renderer):
     # 100k Gaussians, 800x800, SH degree 3, L1 + 0.2 D-SSIM against the perturbed scene's render.
     say("[gpu] object_100k parity")
