@@ -59,6 +59,7 @@ def parse():
     p.add_argument("--mode", default="reduce", choices=["reduce", "plain"], help="backward mode of --profile-only")
     p.add_argument("--lane-split", action="store_true", help="reduced sums issued by lanes 0..8 in one instruction")
     p.add_argument("--xcd-remap", action="store_true", help="map neighbouring tiles to one XCD")
+    p.add_argument("--no-tile-order", action="store_true", help="launch tiles in index order (no longest-first)")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                    help="only run a plain device copy of MIB MiB five times (reference for HBM counters)")
     return p.parse_args()
@@ -196,7 +197,8 @@ def main():
     wl = sg.WORKLOADS[args.workload]()
     log(f"[bench] workload {wl.name}: {wl.scene.n} Gaussians, {wl.camera.width}x{wl.camera.height}")
     Bench.extra_flags = ((gsr.GSR_FLAG_LANE_SPLIT_ATOMICS if args.lane_split else 0) |
-                         (gsr.GSR_FLAG_XCD_REMAP if args.xcd_remap else 0))
+                         (gsr.GSR_FLAG_XCD_REMAP if args.xcd_remap else 0) |
+                         (gsr.GSR_FLAG_NO_TILE_ORDER if args.no_tile_order else 0))
     b = Bench(wl)
 
     # Threshold: one backward per candidate on a warm forward state (the paper's tuning rule).

@@ -52,7 +52,8 @@ enum {
     GSR_FLAG_DEBUG_COUNTERS = 1, /* backward counts wave-entries, active lanes and issued atomics */
     GSR_FLAG_XCD_REMAP = 2,      /* composite kernels map consecutive blocks of one XCD to neighbouring tiles */
     GSR_FLAG_STAGE_TIMING = 4,   /* record HIP events around each stage (gsr_ctx_stage_times) */
-    GSR_FLAG_LANE_SPLIT_ATOMICS = 8 /* reduce path: lanes 0..8 each issue one of the 9 sums in one instruction */
+    GSR_FLAG_LANE_SPLIT_ATOMICS = 8, /* reduce path: lanes 0..8 each issue one of the 9 sums in one instruction */
+    GSR_FLAG_NO_TILE_ORDER = 16      /* launch tiles in index order instead of longest-work first */
 };
 
 /* Number of floats reserved per Gaussian in the backward accumulators:

@@ -104,9 +104,21 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream
 hipError_t launch_count_positive(const int32_t *r, int64_t n, uint32_t *out, hipStream_t st);
 
 // a5: forward composite.
-hipError_t launch_composite_fwd(const DevCamera &cam, int lds_batch, int remap, const uint2 *ranges,
-                                const uint32_t *sorted_ids, const float4 *rec, float *image, float *T_final,
-                                uint32_t *n_contrib, hipStream_t st);
+struct FwdArgs {
+    const uint2 *ranges;
+    const uint32_t *ids;
+    const float4 *rec;
+    float *image;
+    float *T_final;
+    uint32_t *n_contrib;
+    const uint32_t *order; // block -> tile (nullptr: identity / XCD remap)
+    uint32_t *tile_walk;   // optional out: deepest n_contrib per tile
+};
+hipError_t launch_composite_fwd(const DevCamera &cam, int lds_batch, int remap, const FwdArgs &f, hipStream_t st);
+
+// Tiles ordered by decreasing work (tile_walk when given, else list length).
+hipError_t launch_order_tiles(const uint32_t *tile_walk, const uint2 *ranges, int64_t n_tiles, uint32_t *order,
+                              hipStream_t st);
 
 // a6: backward composite.
 struct BwdArgs {
@@ -119,6 +131,7 @@ struct BwdArgs {
     float *acc;
     unsigned long long *counters; // [7 + 65] when counting
     int threshold;                // effective: reduce iff active >= threshold (>= 1)
+    const uint32_t *order;        // block -> tile (nullptr: identity / XCD remap)
 };
 hipError_t launch_composite_bwd(const DevCamera &cam, int lds_batch, int remap, int mode, bool count,
                                 bool lane_split, const BwdArgs &a, hipStream_t st);
@@ -159,6 +172,7 @@ struct gsr_fwd {
     uint32_t *pair_tile = nullptr, *pair_id = nullptr, *pair_tile_alt = nullptr, *pair_id_alt = nullptr;
     uint32_t *sorted_pair_id = nullptr; // points into pair_id or pair_id_alt
     uint2 *ranges = nullptr;
+    uint32_t *order_fwd = nullptr, *order_bwd = nullptr, *tile_walk = nullptr;
     float *T_final = nullptr;
     uint32_t *n_contrib = nullptr;
     float *acc = nullptr;

@@ -84,17 +84,18 @@ __device__ __forceinline__ uint32_t emit9(bool active, float (&v)[9], float *dst
 
 template <int TILE, int BATCH>
 __global__ __launch_bounds__(TILE *TILE) void composite_fwd_kernel(DevCamera cam, int remap, int n_tiles,
-                                                                   const uint2 *__restrict__ ranges,
-                                                                   const uint32_t *__restrict__ ids,
-                                                                   const float4 *__restrict__ rec,
-                                                                   float *__restrict__ image,
-                                                                   float *__restrict__ T_final,
-                                                                   uint32_t *__restrict__ n_contrib) {
+                                                                   FwdArgs f) {
     constexpr int NT = TILE * TILE;
     constexpr int QX = TILE / 8;
     __shared__ float4 s0[BATCH], s1[BATCH], s2[BATCH];
-    const int tile = tile_for_block(blockIdx.x, n_tiles, remap);
+    __shared__ uint32_t s_deepest;
+    const uint2 *__restrict__ ranges = f.ranges;
+    const uint32_t *__restrict__ ids = f.ids;
+    const float4 *__restrict__ rec = f.rec;
+    const int tile = f.order ? (int)f.order[blockIdx.x] : tile_for_block(blockIdx.x, n_tiles, remap);
     if (tile >= n_tiles) return;
+    if (threadIdx.x == 0) s_deepest = 0;
+    __syncthreads();
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int qx0 = (tile % cam.grid_x) * TILE + (wave % QX) * 8;
     const int qy0 = (tile / cam.grid_x) * TILE + (wave / QX) * 8;
@@ -141,11 +142,18 @@ __global__ __launch_bounds__(TILE *TILE) void composite_fwd_kernel(DevCamera cam
     if (inside) {
         const size_t hw = (size_t)cam.width * cam.height;
         const size_t pix = (size_t)py * cam.width + px;
-        image[pix] = fmaf(T, cam.bg[0], c0);
-        image[hw + pix] = fmaf(T, cam.bg[1], c1);
-        image[2 * hw + pix] = fmaf(T, cam.bg[2], c2);
-        T_final[pix] = T;
-        n_contrib[pix] = last;
+        f.image[pix] = fmaf(T, cam.bg[0], c0);
+        f.image[hw + pix] = fmaf(T, cam.bg[1], c1);
+        f.image[2 * hw + pix] = fmaf(T, cam.bg[2], c2);
+        f.T_final[pix] = T;
+        f.n_contrib[pix] = last;
+    }
+    if (f.tile_walk) {
+        // Deepest n_contrib of the tile: the backward's walk length, used to order its blocks.
+        const uint32_t w = wave_max_u32(last);
+        if (lane == 0) atomicMax(&s_deepest, w);
+        __syncthreads();
+        if (threadIdx.x == 0) f.tile_walk[tile] = s_deepest;
     }
 }
 
@@ -158,7 +166,7 @@ __global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(DevCamera cam
     __shared__ uint32_t sid[BATCH];
     __shared__ uint32_t s_walk;
     __shared__ unsigned long long s_cnt[COUNT ? CNT_HIST + 65 : 1];
-    const int tile = tile_for_block(blockIdx.x, n_tiles, remap);
+    const int tile = a.order ? (int)a.order[blockIdx.x] : tile_for_block(blockIdx.x, n_tiles, remap);
     if (tile >= n_tiles) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int qx0 = (tile % cam.grid_x) * TILE + (wave % QX) * 8;
@@ -303,12 +311,39 @@ __global__ __launch_bounds__(256) void l1_grad_kernel(const float *image, const 
     out[i] = d > 0.0f ? inv : (d < 0.0f ? -inv : 0.0f);
 }
 
+// Orders tiles by decreasing work (longest first, so the dispatcher's greedy
+// assignment of workgroups to free CUs approximates longest-processing-time
+// scheduling). work = tile_walk[t] when given, else the list length. Counting
+// sort on a log-scale bucket of the work (16 buckets per octave), one block.
+__global__ __launch_bounds__(1024) void order_tiles_kernel(const uint32_t *tile_walk, const uint2 *ranges, int n,
+                                                           uint32_t *order) {
+    __shared__ uint32_t s_count[256];
+    if (threadIdx.x < 256) s_count[threadIdx.x] = 0;
+    __syncthreads();
+    const auto bucket = [&](int t) -> uint32_t {
+        const uint32_t w = tile_walk ? tile_walk[t] : ranges[t].y - ranges[t].x;
+        const int b = w ? min(255, 1 + (int)(16.0f * __log2f((float)w))) : 0;
+        return 255u - (uint32_t)b; // ascending key = descending work
+    };
+    for (int t = threadIdx.x; t < n; t += blockDim.x) atomicAdd(&s_count[bucket(t)], 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int b = 0; b < 256; ++b) {
+            const uint32_t c = s_count[b];
+            s_count[b] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < n; t += blockDim.x) order[atomicAdd(&s_count[bucket(t)], 1u)] = (uint32_t)t;
+}
+
 template <int TILE, int BATCH>
-hipError_t fwd_t(const DevCamera &cam, int remap, const uint2 *ranges, const uint32_t *ids, const float4 *rec,
-                 float *image, float *T_final, uint32_t *n_contrib, hipStream_t st) {
+hipError_t fwd_t(const DevCamera &cam, int remap, const FwdArgs &f, hipStream_t st) {
     const int n_tiles = cam.grid_x * cam.grid_y;
-    composite_fwd_kernel<TILE, BATCH><<<grid_for_tiles(n_tiles, remap), TILE * TILE, 0, st>>>(
-        cam, remap, n_tiles, ranges, ids, rec, image, T_final, n_contrib);
+    composite_fwd_kernel<TILE, BATCH><<<f.order ? n_tiles : grid_for_tiles(n_tiles, remap), TILE * TILE, 0, st>>>(
+        cam, remap, n_tiles, f);
     return hipGetLastError();
 }
 
@@ -316,7 +351,7 @@ template <int TILE, int BATCH>
 hipError_t bwd_t(const DevCamera &cam, int remap, int mode, bool count, bool split, const BwdArgs &a,
                  hipStream_t st) {
     const int n_tiles = cam.grid_x * cam.grid_y;
-    const dim3 grid(grid_for_tiles(n_tiles, remap)), block(TILE * TILE);
+    const dim3 grid(a.order ? n_tiles : grid_for_tiles(n_tiles, remap)), block(TILE * TILE);
 #define GSR_BWD(M, C, S) composite_bwd_kernel<TILE, BATCH, M, C, S><<<grid, block, 0, st>>>(cam, remap, n_tiles, a)
     if (mode == GSR_BWD_PLAIN_ATOMIC) {
         if (count) GSR_BWD(GSR_BWD_PLAIN_ATOMIC, true, false);
@@ -334,11 +369,16 @@ hipError_t bwd_t(const DevCamera &cam, int remap, int mode, bool count, bool spl
 
 } // namespace
 
-hipError_t launch_composite_fwd(const DevCamera &cam, int lds_batch, int remap, const uint2 *ranges,
-                                const uint32_t *sorted_ids, const float4 *rec, float *image, float *T_final,
-                                uint32_t *n_contrib, hipStream_t st) {
+hipError_t launch_order_tiles(const uint32_t *tile_walk, const uint2 *ranges, int64_t n_tiles, uint32_t *order,
+                              hipStream_t st) {
+    if (n_tiles <= 0) return hipSuccess;
+    order_tiles_kernel<<<1, 1024, 0, st>>>(tile_walk, ranges, (int)n_tiles, order);
+    return hipGetLastError();
+}
+
+hipError_t launch_composite_fwd(const DevCamera &cam, int lds_batch, int remap, const FwdArgs &f, hipStream_t st) {
     const int t = cam.tile;
-#define GSR_F(T, B) return fwd_t<T, B>(cam, remap, ranges, sorted_ids, rec, image, T_final, n_contrib, st)
+#define GSR_F(T, B) return fwd_t<T, B>(cam, remap, f, st)
     if (t == 8) GSR_F(8, 64);
     if (t == 16) {
         if (lds_batch == 64) GSR_F(16, 64);

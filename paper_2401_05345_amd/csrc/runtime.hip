@@ -178,7 +178,7 @@ gsr_status gsr_validate_config(const gsr_config *cf, const gsr_camera *c) {
     if (cf->bwd_mode != GSR_BWD_PLAIN_ATOMIC && cf->bwd_mode != GSR_BWD_WAVE_REDUCE) return GSR_EINVAL;
     if (cf->reduce_threshold < 0 || cf->reduce_threshold > 65) return GSR_EINVAL;
     if (cf->flags & ~(GSR_FLAG_DEBUG_COUNTERS | GSR_FLAG_XCD_REMAP | GSR_FLAG_STAGE_TIMING |
-                      GSR_FLAG_LANE_SPLIT_ATOMICS))
+                      GSR_FLAG_LANE_SPLIT_ATOMICS | GSR_FLAG_NO_TILE_ORDER))
         return GSR_EINVAL;
     if (c) {
         const int64_t tiles = (int64_t)((c->width + cf->tile - 1) / cf->tile) * ((c->height + cf->tile - 1) / cf->tile);
@@ -367,9 +367,19 @@ gsr_status gsr_render(gsr_ctx *ctx, const gsr_scene *scene, const gsr_camera *ca
     // a4: per-tile ranges
     GSR_RH(launch_tile_ranges(P, sorted_tile, st->ranges, st->n_tiles, s));
     mark(ctx, tm, EV_R5);
-    // a5: forward composite
-    GSR_RH(launch_composite_fwd(st->dcam, config->lds_batch, (config->flags & GSR_FLAG_XCD_REMAP) ? 1 : 0, st->ranges,
-                                st->sorted_pair_id, st->rec, image_chw, st->T_final, st->n_contrib, s));
+    // a5: forward composite, tiles launched longest list first; it records each tile's
+    // deepest n_contrib, which orders the backward's tiles the same way.
+    const bool ordered = !(config->flags & (GSR_FLAG_XCD_REMAP | GSR_FLAG_NO_TILE_ORDER));
+    if (ordered) {
+        GSR_RT(pool_alloc(ctx, st, &st->order_fwd, st->n_tiles));
+        GSR_RT(pool_alloc(ctx, st, &st->order_bwd, st->n_tiles));
+        GSR_RT(pool_alloc(ctx, st, &st->tile_walk, st->n_tiles));
+        GSR_RH(launch_order_tiles(nullptr, st->ranges, st->n_tiles, st->order_fwd, s));
+    }
+    FwdArgs fa{st->ranges, st->sorted_pair_id, st->rec, image_chw, st->T_final, st->n_contrib,
+               ordered ? st->order_fwd : nullptr, ordered ? st->tile_walk : nullptr};
+    GSR_RH(launch_composite_fwd(st->dcam, config->lds_batch, (config->flags & GSR_FLAG_XCD_REMAP) ? 1 : 0, fa, s));
+    if (ordered) GSR_RH(launch_order_tiles(st->tile_walk, nullptr, st->n_tiles, st->order_bwd, s));
     mark(ctx, tm, EV_R6);
 #undef GSR_RT
 #undef GSR_RH
@@ -398,6 +408,7 @@ static gsr_status bwd_composite(gsr_ctx *ctx, gsr_fwd *st, const float *dl, cons
     a.acc = st->acc;
     a.counters = st->counters;
     a.threshold = cfg->reduce_threshold < 1 ? 1 : cfg->reduce_threshold;
+    a.order = (cfg->flags & (GSR_FLAG_XCD_REMAP | GSR_FLAG_NO_TILE_ORDER)) ? nullptr : st->order_bwd;
     GSR_HIP(ctx, launch_composite_bwd(st->dcam, cfg->lds_batch, (cfg->flags & GSR_FLAG_XCD_REMAP) ? 1 : 0,
                                       cfg->bwd_mode, count, (cfg->flags & GSR_FLAG_LANE_SPLIT_ATOMICS) != 0, a, s));
     mark(ctx, tm, EV_B2);

@@ -20,6 +20,7 @@ GSR_FLAG_DEBUG_COUNTERS = 1
 GSR_FLAG_XCD_REMAP = 2
 GSR_FLAG_STAGE_TIMING = 4
 GSR_FLAG_LANE_SPLIT_ATOMICS = 8
+GSR_FLAG_NO_TILE_ORDER = 16
 GSR_ACC_STRIDE = 16
 
 c_void_p = ctypes.c_void_p
