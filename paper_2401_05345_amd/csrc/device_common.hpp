@@ -61,6 +61,32 @@ __device__ __forceinline__ float wave_sum_to_lane63(float v) {
     return v;
 }
 
+// Nine values summed over the 64 lanes, the total of value k delivered to the
+// lanes whose index within their 16-lane row is k (k < 9), every lane active.
+//  1. in-row butterfly, the four DPP steps interleaved across the nine values
+//     (independent chains, so no hazard padding between dependent DPP ops);
+//  2. transpose: lane k of each row keeps its row's partial of value k;
+//  3. the four rows added by two lane permutes (xor 16, xor 32). (The gfx950
+//     row-swap builtins were not used: this toolchain returned the first
+//     operand for both results of the swap.)
+__device__ __forceinline__ float wave_sum9_to_row_lanes(float (&v)[9], int lane) {
+#define GSR_DPP_STEP(ctrl)                                                                                           \
+    _Pragma("unroll") for (int k = 0; k < 9; ++k) v[k] += __builtin_bit_cast(                                       \
+        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v[k]), ctrl, 0xF, 0xF, false));
+    GSR_DPP_STEP(0xB1)  // quad_perm [1,0,3,2]
+    GSR_DPP_STEP(0x4E)  // quad_perm [2,3,0,1]
+    GSR_DPP_STEP(0x141) // row_half_mirror
+    GSR_DPP_STEP(0x140) // row_mirror
+#undef GSR_DPP_STEP
+    const int r = lane & 15;
+    float w = v[0];
+#pragma unroll
+    for (int k = 1; k < 9; ++k) w = (r == k) ? v[k] : w;
+    w += __shfl_xor(w, 16, 64);
+    w += __shfl_xor(w, 32, 64);
+    return w;
+}
+
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, d, 64));

@@ -56,20 +56,17 @@ __device__ __forceinline__ uint32_t emit9(bool active, float (&v)[9], float *dst
     const int cnt = __popcll(m);
     if (cnt >= threshold) { // threshold >= 1, so cnt > 0 here
         reduced_mask_out = m;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) v[k] = wave_sum_to_lane63(v[k]);
         if (SPLIT) {
-            float mine = 0.0f;
-#pragma unroll
-            for (int k = 0; k < 9; ++k) {
-                const float s = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v[k]), 63));
-                mine = (lane == k) ? s : mine;
-            }
+            const float mine = wave_sum9_to_row_lanes(v, lane);
             if (lane < 9) {
                 atomic_add_f32(dst + lane, mine);
                 issued = 1;
             }
-        } else if (lane == 63) {
+            return issued;
+        }
+#pragma unroll
+        for (int k = 0; k < 9; ++k) v[k] = wave_sum_to_lane63(v[k]);
+        if (lane == 63) {
 #pragma unroll
             for (int k = 0; k < 9; ++k) atomic_add_f32(dst + k, v[k]);
             issued = 9;
@@ -233,7 +230,9 @@ __global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(DevCamera cam
 #pragma unroll
             for (int k = 0; k < 9; ++k) v[k] = 0.0f;
             if (active) {
-                T = T / (1.0f - e.alpha); // transmittance in front of this entry
+                // Transmittance in front of this entry; hardware reciprocal (1 ulp) instead of the
+                // IEEE division sequence.
+                T = T * __builtin_amdgcn_rcpf(1.0f - e.alpha);
                 const float w = e.alpha * T;
                 v[6] = w * G0;
                 v[7] = w * G1;
