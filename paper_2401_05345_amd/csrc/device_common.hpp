@@ -39,7 +39,9 @@ __device__ __forceinline__ SplatEval eval_splat(float px, float py, float u, flo
     e.dy = py - v;
     const float q = fmaf(A * e.dx, e.dx, (C * e.dy) * e.dy);
     e.power = fmaf(-B * e.dx, e.dy, -0.5f * q);
-    e.G = expf(e.power);
+    // Hardware exp2 of power*log2(e): relative error ~|power|*2^-24 (3e-7 where alpha meets
+    // 1/255), against ~12 instructions for the correctly rounded expf.
+    e.G = __expf(e.power);
     e.raw = o * e.G;
     e.alpha = fminf(kAlphaMax, e.raw);
     e.pass = !(e.power > 0.0f) && e.alpha >= kAlphaMin;
