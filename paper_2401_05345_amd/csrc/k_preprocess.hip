@@ -191,6 +191,16 @@ __global__ __launch_bounds__(256) void preprocess_fwd_kernel(int n, const float 
 }
 
 template <int DEG>
+__device__ __forceinline__ void preprocess_bwd_one(int i, const float *__restrict__ means,
+                                                   const float *__restrict__ log_scales,
+                                                   const float *__restrict__ quats,
+                                                   const float *__restrict__ opacity_logits,
+                                                   const float *__restrict__ sh, const DevCamera &cam,
+                                                   const int32_t *__restrict__ radius,
+                                                   const float *__restrict__ acc, const gsr_grads &out,
+                                                   int accumulate, float *Ysh, float *gsh);
+
+template <int DEG>
 __global__ __launch_bounds__(256) void preprocess_bwd_kernel(int n, const float *__restrict__ means,
                                                              const float *__restrict__ log_scales,
                                                              const float *__restrict__ quats,
@@ -200,19 +210,59 @@ __global__ __launch_bounds__(256) void preprocess_bwd_kernel(int n, const float 
                                                              const float *__restrict__ acc, gsr_grads out,
                                                              int accumulate) {
     constexpr int K = (DEG + 1) * (DEG + 1);
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    constexpr int NS = 3 * K;      // SH gradient floats per Gaussian
+    constexpr int PITCH = NS + 1;  // odd LDS pitch: lanes of a wave hit distinct banks
+    __shared__ float s_sh[4][64 * PITCH];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wave_base = blockIdx.x * blockDim.x + wave * 64;
+    if (wave_base >= n) return; // whole wave past the end
+    const int i = wave_base + lane;
+    float Ysh[K], gsh[3];
+#pragma unroll
+    for (int k = 0; k < K; ++k) Ysh[k] = 0.0f;
+    gsh[0] = gsh[1] = gsh[2] = 0.0f;
+    if (i < n) preprocess_bwd_one<DEG>(i, means, log_scales, quats, opacity_logits, sh, cam, radius, acc, out,
+                                       accumulate, Ysh, gsh);
+    // SH gradients (Y_k * dL/drgb_c, zero for culled Gaussians) leave through LDS so that the
+    // wave's 64 x 3K floats are written with consecutive lanes on consecutive addresses.
+    float *stage = s_sh[wave];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) stage[lane * PITCH + 3 * k + ch] = Ysh[k] * gsh[ch];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int count = min(64, n - wave_base);
+    float *dst = out.sh + (int64_t)wave_base * NS;
+    for (int t = lane; t < count * NS; t += 64) {
+        const float val = stage[(t / NS) * PITCH + t % NS];
+        dst[t] = accumulate ? dst[t] + val : val;
+    }
+}
+
+// Everything of one Gaussian except the SH gradient, which the caller writes
+// (Y receives the basis values, g the dL/drgb passed through the clamp; both
+// stay zero for a culled Gaussian).
+template <int DEG>
+__device__ __forceinline__ void preprocess_bwd_one(int i, const float *__restrict__ means,
+                                                   const float *__restrict__ log_scales,
+                                                   const float *__restrict__ quats,
+                                                   const float *__restrict__ opacity_logits,
+                                                   const float *__restrict__ sh, const DevCamera &cam,
+                                                   const int32_t *__restrict__ radius,
+                                                   const float *__restrict__ acc, const gsr_grads &out,
+                                                   int accumulate, float *Ysh, float *gsh) {
+    constexpr int K = (DEG + 1) * (DEG + 1);
     float *o_m = out.means3d + 3 * (int64_t)i;
     float *o_s = out.log_scales + 3 * (int64_t)i;
     float *o_q = out.quats + 4 * (int64_t)i;
     float *o_o = out.opacity_logits + i;
-    float *o_sh = out.sh + (int64_t)i * K * 3;
     if (radius[i] <= 0) {
         if (!accumulate) {
             for (int k = 0; k < 3; ++k) o_m[k] = 0.f, o_s[k] = 0.f;
             for (int k = 0; k < 4; ++k) o_q[k] = 0.f;
             *o_o = 0.f;
-            for (int k = 0; k < 3 * K; ++k) o_sh[k] = 0.f;
         }
         return;
     }
@@ -257,17 +307,11 @@ __global__ __launch_bounds__(256) void preprocess_bwd_kernel(int n, const float 
     // d(dir)/d(m) = (I - dir dir^T) / |m - centre|
     const float proj = ddir[0] * dxn + ddir[1] * dyn + ddir[2] * dzn;
     float dm[3] = {(ddir[0] - proj * dxn) * il, (ddir[1] - proj * dyn) * il, (ddir[2] - proj * dzn) * il};
-    if (accumulate) {
 #pragma unroll
-        for (int k = 0; k < K; ++k)
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) o_sh[3 * k + ch] += Y[k] * graw[ch];
-    } else {
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) o_sh[3 * k + ch] = Y[k] * graw[ch];
-    }
+    for (int k = 0; k < K; ++k) Ysh[k] = Y[k];
+    gsh[0] = graw[0];
+    gsh[1] = graw[1];
+    gsh[2] = graw[2];
 
     // ---- conic (A,B,C) = (c, -b, a) / det  ->  2D covariance (a, b, c) ----
     const float a = p.a, b = p.b, c = p.c;
