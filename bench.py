@@ -1,17 +1,22 @@
 """Benchmark: 3DGS backward ms/iter, wave-reduce vs plain atomics, on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload object_100k|large_3m]
-                    [--no-large] [--no-cpu-baseline]
+                    [--no-large] [--no-batch] [--no-serve] [--no-cpu-baseline]
 
 A step is one pass of the whole path over one synthetic view: render
-(projection, binning with the device radix sort, forward composite), the L1
-loss gradient, and the backward (backward composite + per-Gaussian chain
-rule), inputs already resident in HBM. `value` is the backward's milliseconds
-per iteration (backward composite + preprocess backward) in wave-reduce mode
-at the balancing threshold picked by a one-iteration-per-candidate sweep (the
+(projection, binning with the device radix sort, forward composite), the
+workload's loss gradient (L1 + 0.2 D-SSIM for the object scene), and the
+backward (backward composite + per-Gaussian chain rule), inputs already
+resident in HBM. `value` is the backward's milliseconds per iteration
+(backward composite + preprocess backward) in wave-reduce mode at the
+balancing threshold picked by a one-iteration-per-candidate sweep (the
 paper's tuning rule); the plain-atomic backward on the same forward state is
 reported beside it, as are the atomic-count and roofline figures of the
-backward composite kernel and the fp64 oracle timed on the host.
+backward composite kernel and the fp64 oracle timed on the host. Further
+legs: the 3M-Gaussian 1080p view (A/B), the 16-view four-scene batch
+(autotuned, batched vs one view at a time, hipGraph replay) and the served
+request stream (continuous batching vs a sequential plain-atomic server,
+p50/p99 latency and steps/s at several Poisson arrival rates).
 
 Prints exactly one JSON line.
 """
@@ -57,7 +62,11 @@ def parse():
     p.add_argument("--threshold", type=int, default=None, help="fix the threshold (skip the sweep)")
     p.add_argument("--profile-only", action="store_true", help="only the timed steps (for rocprofv3 runs)")
     p.add_argument("--mode", default="reduce", choices=["reduce", "plain"], help="backward mode of --profile-only")
-    p.add_argument("--lane-split", action="store_true", help="reduced sums issued by lanes 0..8 in one instruction")
+    p.add_argument("--no-lane-split", action="store_true",
+                   help="reduced sums issued by one lane (default: lanes 0..8, one instruction)")
+    p.add_argument("--no-batch", action="store_true", help="skip the 16-view batched leg")
+    p.add_argument("--no-serve", action="store_true", help="skip the served request stream")
+    p.add_argument("--serve-seconds", type=float, default=1.5, help="seconds of arrivals per rate")
     p.add_argument("--xcd-remap", action="store_true", help="map neighbouring tiles to one XCD")
     p.add_argument("--no-tile-order", action="store_true", help="launch tiles in index order (no longest-first)")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -97,7 +106,7 @@ class Bench:
     def step(self, cfg):
         """One whole pass; returns (stage times, frame stats)."""
         fr = self.r.render(self.scene, self.cam, cfg)
-        self.gsr.gsr_l1_grad(self.r.ctx, fr.image, self.target, self.dl)
+        self.loss_grad(fr.image)
         self.gsr.gsr_backward(self.r.ctx, fr.state, self.dl, self.gstruct, 0, cfg)
         st = self.gsr.gsr_ctx_stage_times(self.r.ctx)
         stats = fr.stats
@@ -114,9 +123,16 @@ class Bench:
             a7.append(st.preprocess_bwd)
         return a6, a7
 
+    def loss_grad(self, image):
+        """dL/dimage of the workload's loss: L1, or L1 + 0.2 D-SSIM (object scene)."""
+        if self.wl.loss == "l1_dssim":
+            self.gsr.gsr_l1_dssim_grad(self.r.ctx, image, self.target, self.dl, 0.2)
+        else:
+            self.gsr.gsr_l1_grad(self.r.ctx, image, self.target, self.dl)
+
     def forward_state(self, cfg):
         fr = self.r.render(self.scene, self.cam, cfg)
-        self.gsr.gsr_l1_grad(self.r.ctx, fr.image, self.target, self.dl)
+        self.loss_grad(fr.image)
         return fr
 
     def sweep(self, fr, iters=3):
@@ -155,6 +171,175 @@ def measured_traffic(kernel_hash):
     return d.get("bytes_per_launch")
 
 
+def timed_ms(torch, fn, reps):
+    """Median milliseconds of fn() between events on the current (null) stream."""
+    out = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        out.append(a.elapsed_time(b))
+    return float(np.median(out))
+
+
+def bench_multi_view(flags, reps=5):
+    """16 views of four scenes of uneven size at mixed resolutions: batched render and backward
+    (one composite launch per pass over every (view, tile) pair) at the autotuned configuration,
+    against the same views rendered and differentiated one call at a time; the batched backward
+    also replayed from a captured hipGraph; the plain-atomic batched backward beside it."""
+    import torch
+    from paper_2401_05345_amd import gsr
+    from paper_2401_05345_amd import scenegen as sg
+    mv = sg.multi_view()
+    log(f"[bench] {mv.name}: {[s.n for s in mv.scenes]} Gaussians, {len(mv.views)} views")
+    dev = torch.device("cuda:0")
+    st_t = [[torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in s.arrays()] for s in mv.scenes]
+    structs = [gsr.make_scene(*t, s.sh_degree) for t, s in zip(st_t, mv.scenes)]
+    grads_t = [[torch.zeros_like(x) for x in t] for t in st_t]
+    gstructs = [gsr.make_grads(*g) for g in grads_t]
+    scenes, cams, targets, imgs, dls, outs = [], [], [], [], [], []
+    for si, c, tgt in mv.views:
+        scenes.append(structs[si])
+        cams.append(gsr.make_camera(c.width, c.height, c.fx, c.fy, c.cx, c.cy, c.world_to_cam, c.znear, c.bg))
+        targets.append(torch.from_numpy(tgt).to(dev))
+        imgs.append(torch.empty((3, c.height, c.width), device=dev))
+        dls.append(torch.empty((3, c.height, c.width), device=dev))
+        outs.append(gstructs[si])
+    r = gsr.Renderer(0)
+    ctx = r.ctx
+    space = gsr.make_tune_space(reps=2, flags=flags)
+    t0 = time.perf_counter()
+    best, entries = gsr.gsr_autotune(ctx, scenes, cams, space)
+    tune_s = time.perf_counter() - t0
+    cfg = gsr.make_config(best.tile, best.lds_batch, gsr.GSR_BWD_WAVE_REDUCE, best.reduce_threshold, flags)
+    cfg_plain = gsr.make_config(best.tile, best.lds_batch, gsr.GSR_BWD_PLAIN_ATOMIC, 0, flags)
+    log(f"[bench] autotune ({tune_s:.1f} s): tile {best.tile}, lds {best.lds_batch}, thr {best.reduce_threshold}")
+
+    states = gsr.gsr_render_batch(ctx, scenes, cams, cfg, imgs)
+    for im, tg, d in zip(imgs, targets, dls):
+        gsr.gsr_l1_grad(ctx, im, tg, d)
+    res = {}
+
+    def render_batch():
+        for s in gsr.gsr_render_batch(ctx, scenes, cams, cfg, imgs):
+            gsr.gsr_fwd_release(ctx, s)
+
+    def render_seq():
+        for sc, cm, im in zip(scenes, cams, imgs):
+            gsr.gsr_fwd_release(ctx, gsr.gsr_render(ctx, sc, cm, cfg, im))
+
+    def bwd_batch(c=cfg):
+        gsr.gsr_backward_batch(ctx, states, dls, outs, 0, c)
+
+    def bwd_seq():
+        seen = set()
+        for st, d, o, si in zip(states, dls, outs, [v[0] for v in mv.views]):
+            gsr.gsr_backward(ctx, st, d, o, 1 if si in seen else 0, cfg)
+            seen.add(si)
+
+    for name, fn in (("render_batch_ms", render_batch), ("render_sequential_ms", render_seq),
+                     ("backward_batch_ms", bwd_batch), ("backward_sequential_ms", bwd_seq),
+                     ("backward_batch_plain_ms", lambda: bwd_batch(cfg_plain))):
+        fn()
+        res[name] = round(timed_ms(torch, fn, reps), 4)
+    graph = gsr.gsr_graph_capture_backward(ctx, states, dls, outs, 0, cfg)
+    gsr.gsr_graph_launch(ctx, graph)
+    res["backward_graph_ms"] = round(timed_ms(torch, lambda: gsr.gsr_graph_launch(ctx, graph), reps), 4)
+    gsr.gsr_graph_destroy(ctx, graph)
+    pairs = [int(gsr.gsr_fwd_stats(s).n_pairs) for s in states]
+    for s in states:
+        gsr.gsr_fwd_release(ctx, s)
+    r.close()
+    tot = sorted(entries, key=lambda e: e.render_ms + e.backward_ms)
+    res.update({
+        "workload": mv.name, "n_views": len(mv.views), "gaussians": [s.n for s in mv.scenes],
+        "resolutions": [[v[1].width, v[1].height] for v in mv.views], "n_pairs_total": sum(pairs),
+        "autotune": {"tile": best.tile, "lds_batch": best.lds_batch, "threshold": best.reduce_threshold,
+                     "seconds": round(tune_s, 2), "candidates": len(entries),
+                     "best_ms": round(tot[0].render_ms + tot[0].backward_ms, 3),
+                     "worst_ms": round(tot[-1].render_ms + tot[-1].backward_ms, 3),
+                     "table": [[e.config.tile, e.config.lds_batch, e.config.reduce_threshold,
+                                round(e.render_ms, 3), round(e.backward_ms, 3)] for e in entries]},
+        "speedup_backward_batch_vs_sequential": round(res["backward_sequential_ms"] / res["backward_batch_ms"], 3),
+        "speedup_render_batch_vs_sequential": round(res["render_sequential_ms"] / res["render_batch_ms"], 3),
+        "speedup_backward_reduce_vs_plain": round(res["backward_batch_plain_ms"] / res["backward_batch_ms"], 3),
+    })
+    log(f"[bench] multi-view: {json.dumps({k: v for k, v in res.items() if k != 'autotune'})}")
+    return res
+
+
+SERVE_RATES = (50, 100, 200, 400)
+
+
+def _latency_stats(res):
+    lat = np.array([(r.t_done - r.t_arrival) * 1000.0 for r in res])
+    span = max(r.t_done for r in res) - min(r.t_arrival for r in res)
+    return {"requests": len(res), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3), "mean_ms": round(float(lat.mean()), 3),
+            "steps_per_s": round(len(res) / span, 2),
+            "mean_batch": round(float(np.mean([r.batch_size for r in res])), 2),
+            "failed": int(sum(r.status != 0 for r in res))}
+
+
+def bench_serving(flags, seconds):
+    """The served stream: ten resident scenes (100k-2M Gaussians, SH3) with Adam state on the
+    device; Poisson arrivals of render + L1 + backward + Adam requests at several rates, each at
+    a random eye and resolution with a device-drawn U(0,1) target. The continuous-batching server
+    (wave-reduce backward, up to 16 requests per batch, two lanes) against a sequential
+    plain-atomic server (one request at a time, one lane) on the same arrival streams."""
+    import torch
+    from paper_2401_05345_amd import gsr
+    from paper_2401_05345_amd import scenegen as sg
+    from paper_2401_05345_amd.serve import Server
+    scenes = sg.serving_scenes()
+    sizes = [s.n for s in scenes]
+    log(f"[bench] serving: scenes {sizes}")
+    dev = torch.device("cuda:0")
+    tens = [[torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in s.arrays()] for s in scenes]
+    structs = [gsr.make_scene(*t, s.sh_degree) for t, s in zip(tens, scenes)]
+    resident = sum(gsr.gsr_server_scene_bytes(s.n, s.sh_degree) for s in scenes)
+    # Admission at an artificial 4 GiB budget: scenes that do not fit are refused.
+    admitted4 = 0
+    with Server(4 << 30, max_batch=1, lanes=1) as srv:
+        for st in structs:
+            try:
+                srv.add_scene(st)
+                admitted4 += 1
+            except gsr.GsrError as e:
+                if e.status != gsr.GSR_EBUDGET:
+                    raise
+    out = {"scenes": sizes, "resident_bytes": int(resident), "admitted_at_4GiB": admitted4,
+           "budget_bytes": int(resident + (8 << 30)), "rates": {}}
+    reduce_cfg = gsr.make_config(16, 256, gsr.GSR_BWD_WAVE_REDUCE, 4, flags)
+    plain_cfg = gsr.make_config(16, 256, gsr.GSR_BWD_PLAIN_ATOMIC, 0, flags)
+    servers = {"batched_reduce": dict(max_batch=16, lanes=2, config=reduce_cfg),
+               "sequential_plain": dict(max_batch=1, lanes=1, config=plain_cfg)}
+    for name, kw in servers.items():
+        with Server(out["budget_bytes"], lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-15, **kw) as srv:
+            ids = [srv.add_scene(st) for st in structs]
+            warm = sg.serving_requests(99, len(ids), 4, 100.0)
+            srv.replay([srv.request(ids[si], cam, seed) for _, si, cam, seed in warm], [0.0] * len(warm))
+            srv.drain()
+            srv.results()
+            for rate in SERVE_RATES:
+                stream = sg.serving_requests(1000 + rate, len(ids), max(8, int(rate * seconds)), float(rate))
+                reqs = [srv.request(ids[si], cam, seed) for _, si, cam, seed in stream]
+                t0 = time.perf_counter()
+                srv.replay(reqs, [t for t, _, _, _ in stream])
+                srv.drain()
+                res = srv.results()
+                st = _latency_stats(res)
+                st["wall_s"] = round(time.perf_counter() - t0, 2)
+                out["rates"].setdefault(str(rate), {})[name] = st
+                log(f"[bench] serve {name} {rate}/s: {st}")
+    for rate, d in out["rates"].items():
+        d["p99_speedup"] = round(d["sequential_plain"]["p99_ms"] / d["batched_reduce"]["p99_ms"], 2)
+        d["throughput_ratio"] = round(d["batched_reduce"]["steps_per_s"] / d["sequential_plain"]["steps_per_s"], 2)
+    return out
+
+
 def cpu_baseline(wl):
     """The fp64 oracle's backward (composite C loop + autograd chain rule) for the full view,
     single-threaded, on the host cores of this machine."""
@@ -163,7 +348,7 @@ def cpu_baseline(wl):
     torch.set_num_threads(1)
     rr = oracle.render(wl.scene, wl.camera)
     target = oracle.render(wl.perturbed, wl.camera).image if wl.perturbed is not None else wl.target
-    _, dl = oracle.loss_and_grad(rr.image, target, "l1")
+    _, dl = oracle.loss_and_grad(rr.image, target, wl.loss)
     t0 = time.perf_counter()
     oracle.backward(wl.scene, rr, dl)
     dt = time.perf_counter() - t0
@@ -196,7 +381,7 @@ def main():
 
     wl = sg.WORKLOADS[args.workload]()
     log(f"[bench] workload {wl.name}: {wl.scene.n} Gaussians, {wl.camera.width}x{wl.camera.height}")
-    Bench.extra_flags = ((gsr.GSR_FLAG_LANE_SPLIT_ATOMICS if args.lane_split else 0) |
+    Bench.extra_flags = ((0 if args.no_lane_split else gsr.GSR_FLAG_LANE_SPLIT_ATOMICS) |
                          (gsr.GSR_FLAG_XCD_REMAP if args.xcd_remap else 0) |
                          (gsr.GSR_FLAG_NO_TILE_ORDER if args.no_tile_order else 0))
     b = Bench(wl)
@@ -321,6 +506,13 @@ def main():
         }
         b3.r.release(fr3)
         b3.r.close()
+
+    if not args.no_batch and not args.profile_only:
+        out["multi_view_16"] = bench_multi_view(Bench.extra_flags)
+
+    if not args.no_serve and not args.profile_only:
+        out["serving"] = bench_serving(Bench.extra_flags, args.serve_seconds)
+        out["p99_step_ms"] = out["serving"]["rates"]["200"]["batched_reduce"]["p99_ms"]
 
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")

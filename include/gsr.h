@@ -40,12 +40,17 @@ typedef enum {
     GSR_EINVAL = -1,  /* bad argument; nothing was enqueued */
     GSR_ENOMEM = -2,  /* device or pinned-host allocation failed */
     GSR_EHIP = -3,    /* a HIP runtime call failed; message carries hipGetErrorString */
-    GSR_ESTATE = -4   /* object used in a wrong state (e.g. counters never collected) */
+    GSR_ESTATE = -4,  /* object used in a wrong state (e.g. counters never collected) */
+    GSR_EBUDGET = -5  /* a scene does not fit the server's HBM budget */
 } gsr_status;
 
 typedef enum {
     GSR_BWD_PLAIN_ATOMIC = 0, /* every active lane issues its own 9 atomic adds */
-    GSR_BWD_WAVE_REDUCE = 1   /* butterfly + one lane's atomics when active lanes >= threshold */
+    GSR_BWD_WAVE_REDUCE = 1,  /* butterfly + one lane's atomics when active lanes >= threshold */
+    GSR_BWD_SERIAL_REDUCE = 2, /* ablation: the sums built one active lane at a time (readlane loop, the
+                                  paper's serialised SW-S form) when active lanes >= threshold; lanes 0..8 issue */
+    GSR_BWD_BLOCK_REDUCE = 3  /* extension: waves at or above the threshold reduce by butterfly into LDS; the
+                                 block issues one atomic per (tile, Gaussian, value) after each LDS batch */
 } gsr_bwd_mode;
 
 enum {
@@ -168,9 +173,12 @@ typedef struct {
     float zero_acc, composite_bwd, preprocess_bwd;
 } gsr_stage_times_t;
 
-/* Create a context on `device`. hip_stream: a hipStream_t to enqueue on, or
- * NULL to create a stream of default priority owned by the context.
- * Returns GSR_EINVAL for a bad device, GSR_EHIP on runtime failure. */
+/* Create a context on `device`. hip_stream: the hipStream_t to enqueue on;
+ * NULL means HIP's null stream (where a framework's default stream runs, so
+ * the library's work is ordered with the caller's). The library enqueues on
+ * no other stream (the one exception: a graph capture from a context on the
+ * null stream records on a temporary stream). Returns GSR_EINVAL for a bad
+ * device, GSR_EHIP on runtime failure. */
 gsr_status gsr_ctx_create(gsr_ctx **out, int device, void *hip_stream);
 
 /* Destroy a context and free all library-owned device memory. Waits for the
@@ -181,7 +189,9 @@ void gsr_ctx_destroy(gsr_ctx *ctx);
  * string is owned by the context and valid until the next call on it. */
 const char *gsr_ctx_last_error(const gsr_ctx *ctx);
 
-/* Replace the stream the context enqueues on (NULL = its own stream). */
+/* Replace the stream the context enqueues on (NULL = HIP's null stream).
+ * Synchronises the old stream first (pooled buffers are reused in one
+ * stream order). */
 gsr_status gsr_ctx_set_stream(gsr_ctx *ctx, void *hip_stream);
 
 /* Forward pass (3DGS rasterisation: per-Gaussian projection, tile binning
@@ -214,6 +224,186 @@ gsr_status gsr_backward_composite(gsr_ctx *ctx, gsr_fwd *state, const float *dl_
  * accumulators of the last gsr_backward_composite. */
 gsr_status gsr_backward_params(gsr_ctx *ctx, gsr_fwd *state, const gsr_grads *out, int accumulate);
 
+/* Most views one batched call takes. */
+#define GSR_MAX_BATCH 16
+
+/* Forward pass over n_views (1..GSR_MAX_BATCH) views at once: scenes[i] seen
+ * by cameras[i] into images_chw[i] [3,H_i,W_i], states_out[i] receiving view
+ * i's state (as gsr_render). Views may share a scene and may differ in
+ * resolution and Gaussian count; one config (tile, LDS batch, flags) serves
+ * all. Every stage runs for all views before the next, the pair counts of
+ * all views are read back with ONE synchronisation, and the composite is one
+ * launch over every (view, tile) pair of the batch, longest tile first
+ * (GSR_FLAG_NO_TILE_ORDER: view-major index order; GSR_FLAG_XCD_REMAP has no
+ * effect on a batch of more than one view). Results equal gsr_render's for
+ * each view. On failure no state is returned. */
+gsr_status gsr_render_batch(gsr_ctx *ctx, int32_t n_views, const gsr_scene *scenes, const gsr_camera *cameras,
+                            const gsr_config *config, float *const *images_chw, gsr_fwd **states_out);
+
+/* Backward pass over n_views (1..GSR_MAX_BATCH) forward states at once (from
+ * gsr_render or gsr_render_batch, all rendered with config->tile): one
+ * composite launch over every (view, tile) pair, then each view's
+ * per-Gaussian part. dl_dimages_chw[i] [3,H_i,W_i]; outs[i] view i's
+ * gradient outputs. Views whose outs are identical (all five pointers
+ * equal) are summed: the first of them writes (or adds, when accumulate is
+ * 1), later ones add. outs that share some but not all pointers are
+ * rejected (GSR_EINVAL). With GSR_FLAG_DEBUG_COUNTERS the counters of the
+ * whole launch are kept on states[0]. config NULL = states[0]'s render
+ * config. */
+gsr_status gsr_backward_batch(gsr_ctx *ctx, int32_t n_views, gsr_fwd *const *states,
+                              const float *const *dl_dimages_chw, const gsr_grads *outs, int accumulate,
+                              const gsr_config *config);
+
+/* A batched backward captured in a HIP graph: the kernels gsr_backward_batch
+ * would enqueue for these states, dL/dimage buffers, outputs, accumulate flag
+ * and config, replayed by gsr_graph_launch without host work per kernel. The
+ * graph holds the addresses given here: write new dL/dimage values into the
+ * same buffers between launches. The states must stay alive (not released)
+ * until the graph is destroyed, and the scenes unchanged in shape. Every
+ * buffer the replay touches is allocated during this call; the capture
+ * itself holds kernel launches only (fills, not memsets). When the context's
+ * stream is the null stream the capture uses a temporary stream of default
+ * priority. GSR_FLAG_STAGE_TIMING is ignored. Nothing is executed by the
+ * capture except a single view's one-time tile ordering. */
+typedef struct gsr_graph gsr_graph;
+gsr_status gsr_graph_capture_backward(gsr_ctx *ctx, int32_t n_views, gsr_fwd *const *states,
+                                      const float *const *dl_dimages_chw, const gsr_grads *outs, int accumulate,
+                                      const gsr_config *config, gsr_graph **graph_out);
+
+/* Enqueue one replay of a captured graph on the context's stream. */
+gsr_status gsr_graph_launch(gsr_ctx *ctx, gsr_graph *graph);
+
+/* Wait for the context's stream, then free the graph. */
+void gsr_graph_destroy(gsr_ctx *ctx, gsr_graph *graph);
+
+/* Autotuner (the paper's rule: time one gradient-kernel iteration per
+ * candidate, keep the fastest, repeat periodically). Candidates are every
+ * valid (tile, lds_batch) pair of the space (lds_batch <= tile*tile) times
+ * every threshold; each is timed as one batched render plus one batched
+ * backward of the given views with HIP events (median of `reps` runs), with
+ * bwd_mode GSR_BWD_WAVE_REDUCE and `flags` (GSR_FLAG_STAGE_TIMING and
+ * GSR_FLAG_DEBUG_COUNTERS are dropped). */
+typedef struct {
+    int32_t n_tiles, tiles[3];           /* subset of {8, 16, 32} */
+    int32_t n_batches, batches[3];       /* subset of {64, 128, 256} */
+    int32_t n_thresholds, thresholds[8]; /* 1..65 */
+    int32_t reps;                        /* >= 1 */
+    int32_t flags;
+} gsr_tune_space;
+
+typedef struct {
+    gsr_config config;
+    float render_ms, backward_ms;        /* medians over reps, whole batch */
+} gsr_tune_entry;
+
+/* Time every candidate of `space` on n_views (1..GSR_MAX_BATCH) views
+ * (scenes[i] seen by cameras[i]; dl_dimages_chw[i] [3,H_i,W_i] or NULL for a
+ * constant gradient image) and write the fastest (render + backward) to
+ * *best. entries (may be NULL) receives up to max_entries timed candidates,
+ * *n_entries (may be NULL) their count. Images and gradient outputs are
+ * scratch buffers of the context's pool. Synchronises. */
+gsr_status gsr_autotune(gsr_ctx *ctx, int32_t n_views, const gsr_scene *scenes, const gsr_camera *cameras,
+                        const float *const *dl_dimages_chw, const gsr_tune_space *space, gsr_config *best,
+                        gsr_tune_entry *entries, int32_t max_entries, int32_t *n_entries);
+
+/* Periodic re-tuning: gsr_tuner_next returns the config to use for this
+ * iteration, running gsr_autotune on the given views first on iteration 0
+ * and then every `every` iterations (the paper re-tunes every 2000). */
+typedef struct gsr_tuner gsr_tuner;
+gsr_status gsr_tuner_create(const gsr_tune_space *space, int32_t every, gsr_tuner **out);
+gsr_status gsr_tuner_next(gsr_ctx *ctx, gsr_tuner *tuner, int32_t n_views, const gsr_scene *scenes,
+                          const gsr_camera *cameras, const float *const *dl_dimages_chw, gsr_config *config_out,
+                          int32_t *retuned);
+void gsr_tuner_destroy(gsr_tuner *tuner);
+
+/* ---------------------------------------------------------------------
+ * Serving: training-step requests (render + L1 loss + backward + Adam step,
+ * step 7 of the paper's training pipeline figure) against resident scenes,
+ * with continuous batching. A scheduler thread admits queued requests into
+ * a batch as soon as a lane (a stream with its own context) is free: at
+ * most max_batch requests, at most one in flight per scene (each request is
+ * one optimiser step, so a scene's steps stay in arrival order and every
+ * result equals what the request computes alone), and only while the
+ * requests' estimated HBM footprint fits beside the resident scenes in the
+ * budget. Batches on different lanes overlap on the device; a completion
+ * thread per lane stamps finished requests.
+ *
+ * Resident state per scene (server-owned device memory): parameters,
+ * gradients, Adam first and second moments, each one flat fp32 block of
+ * n*(11 + 3K) floats laid out means3d [n,3] | log_scales [n,3] | quats
+ * [n,4] | opacity_logits [n] | sh [n,K,3].
+ * ------------------------------------------------------------------- */
+typedef struct gsr_server gsr_server;
+
+typedef struct {
+    int64_t hbm_budget_bytes; /* resident scenes + in-flight request estimates */
+    int32_t max_batch;        /* 1..GSR_MAX_BATCH requests per batch */
+    int32_t lanes;            /* 1..4 streams batches rotate over */
+    gsr_config config;        /* render/backward configuration of every batch */
+    float lr, beta1, beta2, eps;
+} gsr_server_opts;
+
+/* One request: a step of scene `scene` seen by `camera` against a target
+ * image drawn on the device, U[0,1) per value from SplitMix64 seeded with
+ * target_seed (value i of the [3,H,W] image uses counter i). */
+typedef struct {
+    int32_t scene;
+    gsr_camera camera;
+    uint64_t target_seed;
+} gsr_request;
+
+typedef struct {
+    int64_t id;                  /* from gsr_server_submit, in submission order */
+    int32_t scene;
+    int32_t status;              /* gsr_status of the step */
+    int32_t batch_size, lane;    /* the batch that carried it */
+    int32_t step;                /* the scene's optimiser step count after this request */
+    float loss;                  /* mean |image - target| of the render before the step */
+    double t_arrival, t_start, t_done; /* seconds on the server clock (gsr_server_now) */
+} gsr_result;
+
+/* Resident bytes of a scene of n Gaussians at sh_degree (four flat blocks). */
+int64_t gsr_server_scene_bytes(int64_t n, int32_t sh_degree);
+
+gsr_status gsr_server_create(int device, const gsr_server_opts *opts, gsr_server **out);
+/* Drains every submitted request, stops the threads, frees everything. */
+void gsr_server_destroy(gsr_server *server);
+const char *gsr_server_last_error(const gsr_server *server);
+/* Seconds since the server was created (steady clock). */
+double gsr_server_now(const gsr_server *server);
+
+/* Make a scene resident: its arrays (device pointers, or NULL for zeros,
+ * e.g. to fill them later through gsr_server_scene_state) are copied into
+ * server memory, Adam moments zeroed, step 0. GSR_EBUDGET if the resident
+ * bytes would exceed the budget. Synchronises. */
+gsr_status gsr_server_add_scene(gsr_server *server, const gsr_scene *init, int32_t *scene_id);
+/* Waits for the scene's queued and in-flight requests, then frees it. */
+gsr_status gsr_server_remove_scene(gsr_server *server, int32_t scene_id);
+/* Device pointers of a resident scene's four flat blocks (valid until it is
+ * removed; touch them only while no request for it is queued or in flight)
+ * and its step count. Any output may be NULL. */
+gsr_status gsr_server_scene_state(gsr_server *server, int32_t scene_id, gsr_scene *params, gsr_grads *grads,
+                                  float **adam_m, float **adam_v, int32_t *step);
+gsr_status gsr_server_set_step(gsr_server *server, int32_t scene_id, int32_t step);
+/* Copy one flat block of a resident scene (block 0 parameters, 1 gradients,
+ * 2 Adam m, 3 Adam v; n*(11+3K) floats) to (to_host = 1) or from (0) the
+ * [host] buffer `host`, for checkpoints. Fails with GSR_ESTATE while a
+ * request for the scene is queued or in flight. Synchronises. */
+gsr_status gsr_server_scene_io(gsr_server *server, int32_t scene_id, int32_t block, float *host, int32_t to_host);
+
+/* Queue a request (thread-safe); *id receives its id. Requests for unknown
+ * scenes or with invalid cameras are rejected here. */
+gsr_status gsr_server_submit(gsr_server *server, const gsr_request *req, int64_t *id);
+/* Submit n requests at arrival_s[i] seconds after this call starts (an
+ * open-loop load generator; ascending times), returning once the last is
+ * submitted. ids (may be NULL) receives their ids. */
+gsr_status gsr_server_replay(gsr_server *server, int32_t n, const gsr_request *reqs, const double *arrival_s,
+                             int64_t *ids);
+/* Wait until every submitted request has completed. */
+gsr_status gsr_server_drain(gsr_server *server);
+/* Move up to max completed results (completion order) into out. */
+gsr_status gsr_server_results(gsr_server *server, gsr_result *out, int32_t max, int32_t *n);
+
 /* Release a forward state (its buffers return to the context's pool after
  * the stream reaches this point). */
 gsr_status gsr_fwd_release(gsr_ctx *ctx, gsr_fwd *state);
@@ -236,9 +426,20 @@ gsr_status gsr_ctx_stage_times(gsr_ctx *ctx, gsr_stage_times_t *out);
  * dl_dimage = sign(image - target) / count over `count` floats, sign(0) = 0. */
 gsr_status gsr_l1_grad(gsr_ctx *ctx, const float *image, const float *target, int64_t count, float *dl_dimage);
 
+/* Loss of the object-scene workload and its gradient (harness step, outside
+ * the timed backward): L = (1 - lambda) * mean|image - target| + lambda *
+ * (1 - SSIM(image, target)), SSIM with an 11x11 normalised Gaussian window
+ * (sigma 1.5) as a zero-padded same-size convolution per channel, C1 =
+ * 0.01^2, C2 = 0.03^2, averaged over the 3HW values. image, target,
+ * dl_dimage [3,H,W]; loss (device, may be NULL) receives L. lambda in [0, 1]
+ * (0.2 in 3D Gaussian Splatting). */
+gsr_status gsr_l1_dssim_grad(gsr_ctx *ctx, const float *image, const float *target, int32_t height, int32_t width,
+                             float lambda, float *dl_dimage, float *loss);
+
 /* Run the per-wave reduce-or-atomic primitive on synthetic data: wave w,
  * lane l contributes vals[(w*64+l)*9 + k] to sums[k] (k < 9) when
- * active[w*64+l] != 0. mode/threshold as in gsr_config. lane_atomics[0]
+ * active[w*64+l] != 0. mode (plain, wave or serial reduce; not block) and
+ * threshold as in gsr_config. lane_atomics[0]
  * receives the number of atomic lane-operations issued. sums [9] and
  * lane_atomics [1] are zeroed by the call. */
 gsr_status gsr_wave_reduce_selftest(gsr_ctx *ctx, const float *vals, const uint8_t *active, int32_t n_waves,

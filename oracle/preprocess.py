@@ -38,7 +38,7 @@ import torch
 
 DT = torch.float64
 LOWPASS = 0.3
-CLAMP_FOV = 1.3
+GUARD = 0.15   # the Jacobian's x/z, y/z are held within the image extended by 15 % of its size per side
 
 
 def sh_constants():
@@ -128,10 +128,11 @@ def splat_params(means, log_scales, quats, opacity_logits, sh, cam):
     o = torch.sigmoid(opacity_logits)
     Sigma = covariance3d(log_scales, quats)
 
-    limx = CLAMP_FOV * (cam.width / 2.0) / fx
-    limy = CLAMP_FOV * (cam.height / 2.0) / fy
-    xc = torch.clamp(tx / tz, -limx, limx) * tz
-    yc = torch.clamp(ty / tz, -limy, limy) * tz
+    # Guard band: with the principal point at the centre this is 3DGS's +-1.3 * half-extent / focal.
+    lox, hix = (-cx - GUARD * cam.width) / fx, (cam.width - cx + GUARD * cam.width) / fx
+    loy, hiy = (-cy - GUARD * cam.height) / fy, (cam.height - cy + GUARD * cam.height) / fy
+    xc = torch.clamp(tx / tz, lox, hix) * tz
+    yc = torch.clamp(ty / tz, loy, hiy) * tz
     zeros = torch.zeros_like(tz)
     J = torch.stack([
         torch.stack([fx / tz, zeros, -fx * xc / (tz * tz)], dim=1),
@@ -154,7 +155,7 @@ def splat_params(means, log_scales, quats, opacity_logits, sh, cam):
     Y = sh_basis(dirs, int(round(math.sqrt(sh.shape[1]))) - 1)
     rgb_raw = torch.einsum("mk,mkc->mc", Y, sh) + 0.5
     rgb = torch.clamp(rgb_raw, min=0.0)
-    fcl = ((tx / tz).abs() > limx).to(torch.uint8) + 2 * ((ty / tz).abs() > limy).to(torch.uint8)
+    fcl = (((tx / tz) < lox) | ((tx / tz) > hix)).to(torch.uint8) + 2 * (((ty / tz) < loy) | ((ty / tz) > hiy)).to(torch.uint8)
     return dict(u=u, v=v, a=a, b=b, c=c, det=det, A=A, B=B, C=C, o=o, rgb=rgb, rgb_raw=rgb_raw,
                 frustum_clamp=fcl)
 

@@ -30,7 +30,7 @@ struct DevCamera {
     float t[3];
     float centre[3];   // camera centre in world space, -R^T t
     float znear;
-    float limx, limy;  // guard band of the projection Jacobian: 1.3 * half-extent / focal
+    float lox, hix, loy, hiy; // guard band of the projection Jacobian's x/z and y/z
     float bg[3];
 };
 
@@ -103,40 +103,60 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream
 // out[0] = number of r[i] > 0.
 hipError_t launch_count_positive(const int32_t *r, int64_t n, uint32_t *out, hipStream_t st);
 
-// a5: forward composite.
-struct FwdArgs {
+// One view of a composite launch. A launch covers up to kMaxViews views (same
+// tile size and LDS batch): the views travel by value in the kernel
+// arguments and a work table gives each workgroup its (view, tile).
+constexpr int kMaxViews = 16;
+struct ViewDesc {
+    DevCamera cam;
     const uint2 *ranges;
-    const uint32_t *ids;
+    const uint32_t *ids;      // tile-sorted Gaussian ids
     const float4 *rec;
-    float *image;
+    float *image;             // forward outputs
     float *T_final;
     uint32_t *n_contrib;
-    const uint32_t *order; // block -> tile (nullptr: identity / XCD remap)
-    uint32_t *tile_walk;   // optional out: deepest n_contrib per tile
+    uint32_t *tile_walk;      // optional forward output: deepest n_contrib per tile
+    const float *dl_dimage;   // backward input / output
+    float *acc;
 };
-hipError_t launch_composite_fwd(const DevCamera &cam, int lds_batch, int remap, const FwdArgs &f, hipStream_t st);
+struct ViewBatch {
+    ViewDesc v[kMaxViews];
+    uint32_t base[kMaxViews + 1]; // base[i]: index of view i's first tile in the batch's tile numbering
+    int n;
+};
+enum { ORDER_IDENTITY = 0, ORDER_BY_LENGTH = 1, ORDER_BY_WALK = 2 };
 
-// Tiles ordered by decreasing work (tile_walk when given, else list length).
-hipError_t launch_order_tiles(const uint32_t *tile_walk, const uint2 *ranges, int64_t n_tiles, uint32_t *order,
-                              hipStream_t st);
+// a5: forward composite. work: per-workgroup (view, tile), base[n] entries; nullptr = one
+// view, tiles in index order (or XCD remap).
+hipError_t launch_composite_fwd(const ViewBatch &vb, int tile, int lds_batch, int remap, const uint2 *work,
+                                hipStream_t st);
+
+// The batch's (view, tile) pairs, base[n] of them: in index order (ORDER_IDENTITY) or by
+// decreasing work (list length, or each view's tile_walk).
+hipError_t launch_order_tiles(const ViewBatch &vb, int mode, uint2 *work, hipStream_t st);
 
 // a6: backward composite.
-struct BwdArgs {
-    const uint2 *ranges;
-    const uint32_t *sorted_ids;
-    const float4 *rec;
-    const float *dl_dimage;
-    const float *T_final;
-    const uint32_t *n_contrib;
-    float *acc;
-    unsigned long long *counters; // [7 + 65] when counting
+struct BwdParams {
+    unsigned long long *counters; // [7 + 65] when counting (one set for the launch)
     int threshold;                // effective: reduce iff active >= threshold (>= 1)
-    const uint32_t *order;        // block -> tile (nullptr: identity / XCD remap)
 };
-hipError_t launch_composite_bwd(const DevCamera &cam, int lds_batch, int remap, int mode, bool count,
-                                bool lane_split, const BwdArgs &a, hipStream_t st);
+hipError_t launch_composite_bwd(const ViewBatch &vb, int tile, int lds_batch, int remap, int mode, bool count,
+                                bool lane_split, const BwdParams &p, const uint2 *work, hipStream_t st);
 
 hipError_t launch_l1_grad(const float *image, const float *target, int64_t count, float *out, hipStream_t st);
+
+// Training-step kernels (k_train.hip): Adam on a flat block (step >= 1), a
+// SplitMix64 U[0,1) fill, and sum |a-b| added into *out.
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, int64_t count, float lr, float b1, float b2,
+                       float eps, int step, hipStream_t st);
+hipError_t launch_uniform(float *out, int64_t count, uint64_t seed, hipStream_t st);
+hipError_t launch_l1_sum(const float *a, const float *b, int64_t count, float *out, hipStream_t st);
+
+// (1 - lambda) L1 + lambda (1 - SSIM) of C-channel W x H images (k_loss.hip): dL/dimage into
+// out, the loss into *loss when loss != nullptr. dmu/dexx/dexy: C*W*H scratch floats each,
+// sums: 2 scratch floats.
+hipError_t launch_l1_dssim_grad(const float *img, const float *ref, int C, int W, int H, float lambda, float *dmu,
+                                float *dexx, float *dexy, float *sums, float *out, float *loss, hipStream_t st);
 hipError_t launch_wave_reduce_selftest(const float *vals, const uint8_t *active, int n_waves, int mode,
                                        int threshold, int lane_split, float *sums, unsigned long long *lane_atomics,
                                        hipStream_t st);
@@ -147,8 +167,7 @@ hipError_t launch_wave_reduce_selftest(const float *vals, const uint8_t *active,
 
 struct gsr_ctx {
     int device = 0;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
+    hipStream_t stream = nullptr; // nullptr = HIP's null stream
     std::string err;
     gsr::Pool *pool = nullptr;
     uint32_t *host_pinned = nullptr; // small readback area
@@ -172,7 +191,10 @@ struct gsr_fwd {
     uint32_t *pair_tile = nullptr, *pair_id = nullptr, *pair_tile_alt = nullptr, *pair_id_alt = nullptr;
     uint32_t *sorted_pair_id = nullptr; // points into pair_id or pair_id_alt
     uint2 *ranges = nullptr;
-    uint32_t *order_fwd = nullptr, *order_bwd = nullptr, *tile_walk = nullptr;
+    uint32_t *tile_walk = nullptr; // deepest n_contrib per tile (ordered renders)
+    uint2 *order_bwd = nullptr;    // this view's tiles by decreasing walk (single-view backward)
+    uint2 *batch_work = nullptr;   // (view, tile) table of a batched backward led by this state
+    int64_t batch_work_cap = 0;
     float *T_final = nullptr;
     uint32_t *n_contrib = nullptr;
     float *acc = nullptr;

@@ -54,6 +54,35 @@ __device__ __forceinline__ uint32_t emit9(bool active, float (&v)[9], float *dst
     }
     const uint64_t m = __ballot(active);
     const int cnt = __popcll(m);
+    if (MODE == GSR_BWD_SERIAL_REDUCE) {
+        if (cnt >= threshold) {
+            // Serialised leader: the nine sums are built one active lane at a time from that
+            // lane's registers (a uniform loop of readlanes over the ballot), then lanes 0..8
+            // issue them as one instruction.
+            reduced_mask_out = m;
+            float s[9];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) s[k] = 0.0f;
+            for (uint64_t rest = m; rest; rest &= rest - 1) {
+                const int l = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(rest));
+#pragma unroll
+                for (int k = 0; k < 9; ++k)
+                    s[k] += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[k]), l));
+            }
+            float mine = s[0];
+#pragma unroll
+            for (int k = 1; k < 9; ++k) mine = lane == k ? s[k] : mine;
+            if (lane < 9) {
+                atomic_add_f32(dst + lane, mine);
+                issued = 1;
+            }
+        } else if (active) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) atomic_add_f32(dst + k, v[k]);
+            issued = 9;
+        }
+        return issued;
+    }
     if (cnt >= threshold) { // threshold >= 1, so cnt > 0 here
         reduced_mask_out = m;
         if (SPLIT) {
@@ -79,18 +108,35 @@ __device__ __forceinline__ uint32_t emit9(bool active, float (&v)[9], float *dst
     return issued;
 }
 
+// The workgroup's (view, tile): from the work table, else view 0 with the
+// identity or XCD-banded tile order. Returns false for padding workgroups.
+__device__ __forceinline__ bool block_work(const ViewBatch &vb, int remap, const uint2 *work, int &view, int &tile) {
+    if (work) {
+        const uint2 w = work[blockIdx.x];
+        view = __builtin_amdgcn_readfirstlane((int)w.x);
+        tile = __builtin_amdgcn_readfirstlane((int)w.y);
+        return true;
+    }
+    const int n_tiles = vb.v[0].cam.grid_x * vb.v[0].cam.grid_y;
+    view = 0;
+    tile = tile_for_block(blockIdx.x, n_tiles, remap);
+    return tile < n_tiles;
+}
+
 template <int TILE, int BATCH>
-__global__ __launch_bounds__(TILE *TILE) void composite_fwd_kernel(DevCamera cam, int remap, int n_tiles,
-                                                                   FwdArgs f) {
+__global__ __launch_bounds__(TILE *TILE) void composite_fwd_kernel(ViewBatch vb, int remap,
+                                                                   const uint2 *__restrict__ work) {
     constexpr int NT = TILE * TILE;
     constexpr int QX = TILE / 8;
     __shared__ float4 s0[BATCH], s1[BATCH], s2[BATCH];
     __shared__ uint32_t s_deepest;
+    int view, tile;
+    if (!block_work(vb, remap, work, view, tile)) return;
+    const ViewDesc &f = vb.v[view];
+    const DevCamera &cam = f.cam;
     const uint2 *__restrict__ ranges = f.ranges;
     const uint32_t *__restrict__ ids = f.ids;
     const float4 *__restrict__ rec = f.rec;
-    const int tile = f.order ? (int)f.order[blockIdx.x] : tile_for_block(blockIdx.x, n_tiles, remap);
-    if (tile >= n_tiles) return;
     if (threadIdx.x == 0) s_deepest = 0;
     __syncthreads();
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -157,14 +203,22 @@ __global__ __launch_bounds__(TILE *TILE) void composite_fwd_kernel(DevCamera cam
 enum { CNT_EVAL = 0, CNT_ACTIVE, CNT_WAVE_ENTRIES, CNT_REDUCED, CNT_PLAIN_LANES, CNT_LANE_ATOMICS, CNT_INSTRS, CNT_HIST };
 
 template <int TILE, int BATCH, int MODE, bool COUNT, bool SPLIT>
-__global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(DevCamera cam, int remap, int n_tiles, BwdArgs a) {
+__global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(ViewBatch vb, int remap,
+                                                                   const uint2 *__restrict__ work, BwdParams p) {
     constexpr int QX = TILE / 8;
     __shared__ float4 s0[BATCH], s1[BATCH], s2[BATCH];
     __shared__ uint32_t sid[BATCH];
     __shared__ uint32_t s_walk;
     __shared__ unsigned long long s_cnt[COUNT ? CNT_HIST + 65 : 1];
-    const int tile = a.order ? (int)a.order[blockIdx.x] : tile_for_block(blockIdx.x, n_tiles, remap);
-    if (tile >= n_tiles) return;
+    // Block pre-reduction: the reduced sums of every wave land in LDS per batch entry, and the
+    // block issues one atomic per (tile, Gaussian, value) when the batch is done.
+    constexpr bool BLOCK = MODE == GSR_BWD_BLOCK_REDUCE;
+    __shared__ float s_acc[BLOCK ? BATCH * 9 : 1];
+    __shared__ uint32_t s_touch[BLOCK ? BATCH : 1];
+    int view, tile;
+    if (!block_work(vb, remap, work, view, tile)) return;
+    const ViewDesc &a = vb.v[view];
+    const DevCamera &cam = a.cam;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int qx0 = (tile % cam.grid_x) * TILE + (wave % QX) * 8;
     const int qy0 = (tile / cam.grid_x) * TILE + (wave / QX) * 8;
@@ -208,11 +262,15 @@ __global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(DevCamera cam
         const int cnt = end - start;
         __syncthreads();
         if (tid < cnt) {
-            const uint32_t g = a.sorted_ids[rg.x + start + tid];
+            const uint32_t g = a.ids[rg.x + start + tid];
             sid[tid] = g;
             s0[tid] = a.rec[3 * (size_t)g];
             s1[tid] = a.rec[3 * (size_t)g + 1];
             s2[tid] = a.rec[3 * (size_t)g + 2];
+        }
+        if (BLOCK) {
+            for (int i = tid; i < cnt * 9; i += TILE * TILE) s_acc[i] = 0.0f;
+            if (tid < cnt) s_touch[tid] = 0u;
         }
         __syncthreads();
         const int jtop = min(cnt, (int)wmax - start) - 1;
@@ -251,8 +309,22 @@ __global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(DevCamera cam
                 v[4] = -0.5f * dL_dp * e.dy * e.dy;
             }
             float *dst = a.acc + (size_t)sid[j] * GSR_ACC_STRIDE;
-            uint64_t red_mask;
-            issued += emit9<MODE, SPLIT>(active, v, dst, a.threshold, lane, red_mask);
+            uint64_t red_mask = 0;
+            if (BLOCK) {
+                const uint64_t m = __ballot(active);
+                if (__popcll(m) >= p.threshold) {
+                    red_mask = m;
+                    const float mine = wave_sum9_to_row_lanes(v, lane);
+                    if (lane < 9) atomicAdd(&s_acc[j * 9 + lane], mine);
+                    if (lane == 0) s_touch[j] = 1u;
+                } else if (active) {
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) atomic_add_f32(dst + k, v[k]);
+                    issued += 9;
+                }
+            } else {
+                issued += emit9<MODE, SPLIT>(active, v, dst, p.threshold, lane, red_mask);
+            }
             if (COUNT) {
                 const uint64_t ma = __ballot(active);
                 const int ca = __popcll(ma);
@@ -261,13 +333,27 @@ __global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(DevCamera cam
                     c_we += 1;
                     if (red_mask) {
                         c_red += 1;
-                        c_instr += SPLIT ? 1 : 9;
+                        c_instr += BLOCK ? 0 : ((SPLIT || MODE == GSR_BWD_SERIAL_REDUCE) ? 1 : 9);
                     } else {
                         c_plain += ca;
                         c_instr += 9;
                     }
                     if (lane == 0) atomicAdd(&s_cnt[CNT_HIST + ca], 1ull);
                 }
+            }
+        }
+        if (BLOCK) {
+            // Flush: consecutive lanes take consecutive values of one entry, so each wave-wide
+            // atomic instruction covers about seven entries' 36-byte runs.
+            __syncthreads();
+            for (int i = tid; i < cnt * 9; i += TILE * TILE) {
+                const int e = i / 9;
+                const bool f = s_touch[e] != 0u;
+                if (f) {
+                    atomic_add_f32(a.acc + (size_t)sid[e] * GSR_ACC_STRIDE + (i - 9 * e), s_acc[i]);
+                    ++issued;
+                }
+                if (COUNT && __ballot(f)) c_instr += 1;
             }
         }
     }
@@ -283,7 +369,7 @@ __global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(DevCamera cam
         }
         __syncthreads();
         for (int i = tid; i < CNT_HIST + 65; i += TILE * TILE)
-            if (s_cnt[i]) atomicAdd(&a.counters[i], s_cnt[i]);
+            if (s_cnt[i]) atomicAdd(&p.counters[i], s_cnt[i]);
     }
 }
 
@@ -310,21 +396,34 @@ __global__ __launch_bounds__(256) void l1_grad_kernel(const float *image, const 
     out[i] = d > 0.0f ? inv : (d < 0.0f ? -inv : 0.0f);
 }
 
-// Orders tiles by decreasing work (longest first, so the dispatcher's greedy
-// assignment of workgroups to free CUs approximates longest-processing-time
-// scheduling). work = tile_walk[t] when given, else the list length. Counting
-// sort on a log-scale bucket of the work (16 buckets per octave), one block.
-__global__ __launch_bounds__(1024) void order_tiles_kernel(const uint32_t *tile_walk, const uint2 *ranges, int n,
-                                                           uint32_t *order) {
+// The batch's (view, tile) pairs in index order, or ordered by decreasing
+// work (longest first, so the dispatcher's greedy assignment of workgroups to
+// free CUs approximates longest-processing-time scheduling; a batch of views
+// is one pool of tiles). Work = the tile's deepest n_contrib (tile_walk) or
+// its list length. Counting sort on a log-scale bucket of the work (16
+// buckets per octave), one block.
+__device__ __forceinline__ uint2 locate(const ViewBatch &vb, uint32_t i) {
+    int v = 0;
+    while (v + 1 < vb.n && i >= vb.base[v + 1]) ++v;
+    return make_uint2((uint32_t)v, i - vb.base[v]);
+}
+
+__global__ __launch_bounds__(1024) void order_tiles_kernel(ViewBatch vb, int mode, uint2 *work) {
     __shared__ uint32_t s_count[256];
+    const uint32_t n = vb.base[vb.n];
+    if (mode == ORDER_IDENTITY) {
+        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) work[i] = locate(vb, i);
+        return;
+    }
     if (threadIdx.x < 256) s_count[threadIdx.x] = 0;
     __syncthreads();
-    const auto bucket = [&](int t) -> uint32_t {
-        const uint32_t w = tile_walk ? tile_walk[t] : ranges[t].y - ranges[t].x;
+    const auto bucket = [&](uint2 vt) -> uint32_t {
+        const ViewDesc &d = vb.v[vt.x];
+        const uint32_t w = mode == ORDER_BY_WALK ? d.tile_walk[vt.y] : d.ranges[vt.y].y - d.ranges[vt.y].x;
         const int b = w ? min(255, 1 + (int)(16.0f * __log2f((float)w))) : 0;
         return 255u - (uint32_t)b; // ascending key = descending work
     };
-    for (int t = threadIdx.x; t < n; t += blockDim.x) atomicAdd(&s_count[bucket(t)], 1u);
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) atomicAdd(&s_count[bucket(locate(vb, i))], 1u);
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t run = 0;
@@ -335,26 +434,37 @@ __global__ __launch_bounds__(1024) void order_tiles_kernel(const uint32_t *tile_
         }
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < n; t += blockDim.x) order[atomicAdd(&s_count[bucket(t)], 1u)] = (uint32_t)t;
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const uint2 vt = locate(vb, i);
+        work[atomicAdd(&s_count[bucket(vt)], 1u)] = vt;
+    }
 }
 
 template <int TILE, int BATCH>
-hipError_t fwd_t(const DevCamera &cam, int remap, const FwdArgs &f, hipStream_t st) {
-    const int n_tiles = cam.grid_x * cam.grid_y;
-    composite_fwd_kernel<TILE, BATCH><<<f.order ? n_tiles : grid_for_tiles(n_tiles, remap), TILE * TILE, 0, st>>>(
-        cam, remap, n_tiles, f);
+hipError_t fwd_t(const ViewBatch &vb, int remap, const uint2 *work, hipStream_t st) {
+    const int n_tiles = vb.v[0].cam.grid_x * vb.v[0].cam.grid_y;
+    const unsigned grid = work ? vb.base[vb.n] : (unsigned)grid_for_tiles(n_tiles, remap);
+    if (grid == 0) return hipSuccess;
+    composite_fwd_kernel<TILE, BATCH><<<grid, TILE * TILE, 0, st>>>(vb, remap, work);
     return hipGetLastError();
 }
 
 template <int TILE, int BATCH>
-hipError_t bwd_t(const DevCamera &cam, int remap, int mode, bool count, bool split, const BwdArgs &a,
-                 hipStream_t st) {
-    const int n_tiles = cam.grid_x * cam.grid_y;
-    const dim3 grid(a.order ? n_tiles : grid_for_tiles(n_tiles, remap)), block(TILE * TILE);
-#define GSR_BWD(M, C, S) composite_bwd_kernel<TILE, BATCH, M, C, S><<<grid, block, 0, st>>>(cam, remap, n_tiles, a)
+hipError_t bwd_t(const ViewBatch &vb, int remap, int mode, bool count, bool split, const BwdParams &p,
+                 const uint2 *work, hipStream_t st) {
+    const int n_tiles = vb.v[0].cam.grid_x * vb.v[0].cam.grid_y;
+    const dim3 grid(work ? vb.base[vb.n] : (unsigned)grid_for_tiles(n_tiles, remap)), block(TILE * TILE);
+    if (grid.x == 0) return hipSuccess;
+#define GSR_BWD(M, C, S) composite_bwd_kernel<TILE, BATCH, M, C, S><<<grid, block, 0, st>>>(vb, remap, work, p)
     if (mode == GSR_BWD_PLAIN_ATOMIC) {
         if (count) GSR_BWD(GSR_BWD_PLAIN_ATOMIC, true, false);
         else GSR_BWD(GSR_BWD_PLAIN_ATOMIC, false, false);
+    } else if (mode == GSR_BWD_SERIAL_REDUCE) {
+        if (count) GSR_BWD(GSR_BWD_SERIAL_REDUCE, true, true);
+        else GSR_BWD(GSR_BWD_SERIAL_REDUCE, false, true);
+    } else if (mode == GSR_BWD_BLOCK_REDUCE) {
+        if (count) GSR_BWD(GSR_BWD_BLOCK_REDUCE, true, true);
+        else GSR_BWD(GSR_BWD_BLOCK_REDUCE, false, true);
     } else if (split) {
         if (count) GSR_BWD(GSR_BWD_WAVE_REDUCE, true, true);
         else GSR_BWD(GSR_BWD_WAVE_REDUCE, false, true);
@@ -368,16 +478,16 @@ hipError_t bwd_t(const DevCamera &cam, int remap, int mode, bool count, bool spl
 
 } // namespace
 
-hipError_t launch_order_tiles(const uint32_t *tile_walk, const uint2 *ranges, int64_t n_tiles, uint32_t *order,
-                              hipStream_t st) {
-    if (n_tiles <= 0) return hipSuccess;
-    order_tiles_kernel<<<1, 1024, 0, st>>>(tile_walk, ranges, (int)n_tiles, order);
+hipError_t launch_order_tiles(const ViewBatch &vb, int mode, uint2 *work, hipStream_t st) {
+    if (vb.n <= 0 || vb.base[vb.n] == 0) return hipSuccess;
+    order_tiles_kernel<<<1, 1024, 0, st>>>(vb, mode, work);
     return hipGetLastError();
 }
 
-hipError_t launch_composite_fwd(const DevCamera &cam, int lds_batch, int remap, const FwdArgs &f, hipStream_t st) {
-    const int t = cam.tile;
-#define GSR_F(T, B) return fwd_t<T, B>(cam, remap, f, st)
+hipError_t launch_composite_fwd(const ViewBatch &vb, int t, int lds_batch, int remap, const uint2 *work,
+                                hipStream_t st) {
+    if (vb.n <= 0 || (vb.n > 1 && !work)) return hipErrorInvalidValue;
+#define GSR_F(T, B) return fwd_t<T, B>(vb, remap, work, st)
     if (t == 8) GSR_F(8, 64);
     if (t == 16) {
         if (lds_batch == 64) GSR_F(16, 64);
@@ -390,10 +500,10 @@ hipError_t launch_composite_fwd(const DevCamera &cam, int lds_batch, int remap, 
 #undef GSR_F
 }
 
-hipError_t launch_composite_bwd(const DevCamera &cam, int lds_batch, int remap, int mode, bool count, bool lane_split,
-                                const BwdArgs &a, hipStream_t st) {
-    const int t = cam.tile;
-#define GSR_B(T, B) return bwd_t<T, B>(cam, remap, mode, count, lane_split, a, st)
+hipError_t launch_composite_bwd(const ViewBatch &vb, int t, int lds_batch, int remap, int mode, bool count,
+                                bool lane_split, const BwdParams &p, const uint2 *work, hipStream_t st) {
+    if (vb.n <= 0 || (vb.n > 1 && !work)) return hipErrorInvalidValue;
+#define GSR_B(T, B) return bwd_t<T, B>(vb, remap, mode, count, lane_split, p, work, st)
     if (t == 8) GSR_B(8, 64);
     if (t == 16) {
         if (lds_batch == 64) GSR_B(16, 64);
@@ -418,6 +528,9 @@ hipError_t launch_wave_reduce_selftest(const float *vals, const uint8_t *active,
     if (n_waves <= 0) return hipSuccess;
     if (mode == GSR_BWD_PLAIN_ATOMIC)
         wave_reduce_selftest_kernel<GSR_BWD_PLAIN_ATOMIC, false><<<n_waves, 64, 0, st>>>(vals, active, threshold,
+                                                                                         sums, lane_atomics);
+    else if (mode == GSR_BWD_SERIAL_REDUCE)
+        wave_reduce_selftest_kernel<GSR_BWD_SERIAL_REDUCE, true><<<n_waves, 64, 0, st>>>(vals, active, threshold,
                                                                                          sums, lane_atomics);
     else if (lane_split)
         wave_reduce_selftest_kernel<GSR_BWD_WAVE_REDUCE, true><<<n_waves, 64, 0, st>>>(vals, active, threshold, sums,

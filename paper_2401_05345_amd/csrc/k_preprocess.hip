@@ -56,12 +56,12 @@ __device__ __forceinline__ void project_splat(const DevCamera &cam, float mx, fl
     p.Sig[4] = M[3] * M[6] + M[4] * M[7] + M[5] * M[8];
     p.Sig[5] = M[6] * M[6] + M[7] * M[7] + M[8] * M[8];
 
-    // Jacobian of the pinhole map, x/z and y/z held inside a 1.3x guard band.
+    // Jacobian of the pinhole map, x/z and y/z held inside the guard band.
     const float txtz = p.tx / tz, tytz = p.ty / tz;
-    p.clx = txtz < -cam.limx || txtz > cam.limx;
-    p.cly = tytz < -cam.limy || tytz > cam.limy;
-    p.xc = fminf(cam.limx, fmaxf(-cam.limx, txtz)) * tz;
-    p.yc = fminf(cam.limy, fmaxf(-cam.limy, tytz)) * tz;
+    p.clx = txtz < cam.lox || txtz > cam.hix;
+    p.cly = tytz < cam.loy || tytz > cam.hiy;
+    p.xc = fminf(cam.hix, fmaxf(cam.lox, txtz)) * tz;
+    p.yc = fminf(cam.hiy, fmaxf(cam.loy, tytz)) * tz;
     const float itz = 1.0f / tz;
     const float J00 = cam.fx * itz, J02 = -cam.fx * p.xc * itz * itz;
     const float J11 = cam.fy * itz, J12 = -cam.fy * p.yc * itz * itz;

@@ -1,11 +1,13 @@
 // Host runtime of libgsr: the C ABI of gsr.h, argument checks, a caching
 // device-memory pool, and the orchestration of the kernels on the context's
 // stream.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "gsr_internal.hpp"
 
@@ -78,8 +80,12 @@ DevCamera make_dev_camera(const gsr_camera &c, int tile) {
         d.centre[k] = (float)(-s);
     }
     d.znear = c.znear;
-    d.limx = 1.3f * (0.5f * (float)c.width) / c.fx;
-    d.limy = 1.3f * (0.5f * (float)c.height) / c.fy;
+    // Guard band of the projection Jacobian: the image extended by 15 % of its size on each side
+    // (3DGS's +-1.3 * half-extent / focal when the principal point is at the centre).
+    d.lox = (-c.cx - 0.15f * (float)c.width) / c.fx;
+    d.hix = ((float)c.width - c.cx + 0.15f * (float)c.width) / c.fx;
+    d.loy = (-c.cy - 0.15f * (float)c.height) / c.fy;
+    d.hiy = ((float)c.height - c.cy + 0.15f * (float)c.height) / c.fy;
     for (int k = 0; k < 3; ++k) d.bg[k] = c.bg[k];
     return d;
 }
@@ -175,7 +181,7 @@ gsr_status gsr_validate_config(const gsr_config *cf, const gsr_camera *c) {
     if (cf->tile != 8 && cf->tile != 16 && cf->tile != 32) return GSR_EINVAL;
     if (cf->lds_batch != 64 && cf->lds_batch != 128 && cf->lds_batch != 256) return GSR_EINVAL;
     if (cf->lds_batch > cf->tile * cf->tile) return GSR_EINVAL;
-    if (cf->bwd_mode != GSR_BWD_PLAIN_ATOMIC && cf->bwd_mode != GSR_BWD_WAVE_REDUCE) return GSR_EINVAL;
+    if (cf->bwd_mode < GSR_BWD_PLAIN_ATOMIC || cf->bwd_mode > GSR_BWD_BLOCK_REDUCE) return GSR_EINVAL;
     if (cf->reduce_threshold < 0 || cf->reduce_threshold > 65) return GSR_EINVAL;
     if (cf->flags & ~(GSR_FLAG_DEBUG_COUNTERS | GSR_FLAG_XCD_REMAP | GSR_FLAG_STAGE_TIMING |
                       GSR_FLAG_LANE_SPLIT_ATOMICS | GSR_FLAG_NO_TILE_ORDER))
@@ -200,15 +206,9 @@ gsr_status gsr_ctx_create(gsr_ctx **out, int device, void *hip_stream) {
         delete ctx;
         return GSR_EHIP;
     }
-    if (hip_stream) {
-        ctx->stream = static_cast<hipStream_t>(hip_stream);
-    } else {
-        if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
-            delete ctx;
-            return GSR_EHIP;
-        }
-        ctx->own_stream = true;
-    }
+    // NULL is HIP's null stream: the stream a framework's default stream enqueues on, so work
+    // stays ordered with the caller's own kernels. The library never creates streams.
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
     ctx->pool = new (std::nothrow) Pool(device);
     void *hp = nullptr;
     if (!ctx->pool || hipHostMalloc(&hp, 256, hipHostMallocDefault) != hipSuccess) {
@@ -229,12 +229,11 @@ gsr_status gsr_ctx_create(gsr_ctx **out, int device, void *hip_stream) {
 void gsr_ctx_destroy(gsr_ctx *ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
-    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    (void)hipStreamSynchronize(ctx->stream);
     for (auto &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
     delete ctx->pool;
     if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
-    if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }
 
@@ -243,49 +242,74 @@ const char *gsr_ctx_last_error(const gsr_ctx *ctx) { return ctx ? ctx->err.c_str
 gsr_status gsr_ctx_set_stream(gsr_ctx *ctx, void *hip_stream) {
     if (!ctx) return GSR_EINVAL;
     GSR_HIP(ctx, hipSetDevice(ctx->device));
+    // Drain the old stream first: pooled buffers are only safe to reuse in one stream order.
     GSR_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    if (ctx->own_stream) {
-        if (hip_stream) {
-            (void)hipStreamDestroy(ctx->stream);
-            ctx->own_stream = false;
-            ctx->stream = static_cast<hipStream_t>(hip_stream);
-        }
-    } else if (hip_stream) {
-        ctx->stream = static_cast<hipStream_t>(hip_stream);
-    } else {
-        GSR_HIP(ctx, hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
-        ctx->own_stream = true;
-    }
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
     return GSR_OK;
 }
 
-gsr_status gsr_render(gsr_ctx *ctx, const gsr_scene *scene, const gsr_camera *camera, const gsr_config *config,
-                      float *image_chw, gsr_fwd **state_out) {
-    if (!ctx) return GSR_EINVAL;
-    ctx->err.clear();
-    if (!state_out) return fail(ctx, GSR_EINVAL, "state_out is null");
-    *state_out = nullptr;
-    if (gsr_validate_scene(scene) != GSR_OK) return fail(ctx, GSR_EINVAL, "invalid scene");
-    if (gsr_validate_camera(camera) != GSR_OK) return fail(ctx, GSR_EINVAL, "invalid camera");
-    if (gsr_validate_config(config, camera) != GSR_OK) return fail(ctx, GSR_EINVAL, "invalid config");
-    if (!image_chw) return fail(ctx, GSR_EINVAL, "image is null");
-    GSR_HIP(ctx, hipSetDevice(ctx->device));
+} // extern "C"
 
-    gsr_fwd *st = new (std::nothrow) gsr_fwd();
-    if (!st) return fail(ctx, GSR_ENOMEM, "host allocation failed");
-    st->scene = *scene;
-    st->camera = *camera;
-    st->config = *config;
-    st->dcam = make_dev_camera(*camera, config->tile);
-    st->n = scene->n;
-    st->n_tiles = (int64_t)st->dcam.grid_x * st->dcam.grid_y;
-    const int64_t n = st->n;
-    const int64_t hw = (int64_t)camera->width * camera->height;
+namespace {
+
+// Pool buffer that goes back to the pool when the scope ends. The pool hands
+// it out again only to later work on the same stream, so releasing it right
+// after the launches that use it are enqueued is safe.
+struct TempBuf {
+    gsr_ctx *ctx = nullptr;
+    void *p = nullptr;
+    ~TempBuf() {
+        if (ctx && p) ctx->pool->release(p);
+    }
+};
+
+template <typename T>
+gsr_status temp_alloc(gsr_ctx *ctx, TempBuf &t, T **p, size_t count) {
+    GSR_TRY(pool_alloc(ctx, nullptr, p, count));
+    t.ctx = ctx;
+    t.p = *p;
+    return GSR_OK;
+}
+
+ViewDesc desc_of(const gsr_fwd *st, float *image, const float *dl) {
+    ViewDesc d{};
+    d.cam = st->dcam;
+    d.ranges = st->ranges;
+    d.ids = st->sorted_pair_id;
+    d.rec = st->rec;
+    d.image = image;
+    d.T_final = st->T_final;
+    d.n_contrib = st->n_contrib;
+    d.tile_walk = st->tile_walk;
+    d.dl_dimage = dl;
+    d.acc = st->acc;
+    return d;
+}
+
+gsr_status check_view(gsr_ctx *ctx, int i, const gsr_scene *scene, const gsr_camera *camera,
+                      const gsr_config *config, const float *image) {
+    if (gsr_validate_scene(scene) != GSR_OK) return fail(ctx, GSR_EINVAL, "invalid scene (view %d)", i);
+    if (gsr_validate_camera(camera) != GSR_OK) return fail(ctx, GSR_EINVAL, "invalid camera (view %d)", i);
+    if (gsr_validate_config(config, camera) != GSR_OK) return fail(ctx, GSR_EINVAL, "invalid config (view %d)", i);
+    if (!image) return fail(ctx, GSR_EINVAL, "image is null (view %d)", i);
+    return GSR_OK;
+}
+
+// Renders nv validated views. Every stage runs for all views before the
+// next; one synchronisation reads back all pair counts; the composite is one
+// launch over all (view, tile) pairs.
+gsr_status render_views(gsr_ctx *ctx, int nv, const gsr_scene *scenes, const gsr_camera *cameras,
+                        const gsr_config *config, float *const *images, gsr_fwd **states_out) {
+    GSR_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
     const bool tm = (config->flags & GSR_FLAG_STAGE_TIMING) != 0;
     ctx->timing_render = tm;
-    auto bail = [&](gsr_status code) {
-        gsr_fwd_release(ctx, st);
+    gsr_fwd *sts[kMaxViews] = {};
+    uint32_t *totals[kMaxViews] = {};
+    uint32_t *sorted_tile[kMaxViews] = {};
+    const auto bail = [&](gsr_status code) {
+        for (int v = 0; v < nv; ++v)
+            if (sts[v]) gsr_fwd_release(ctx, sts[v]);
         return code;
     };
 #define GSR_RT(x)                                                                                                   \
@@ -299,147 +323,277 @@ gsr_status gsr_render(gsr_ctx *ctx, const gsr_scene *scene, const gsr_camera *ca
         if (e_ != hipSuccess) return bail(fail(ctx, GSR_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_)));      \
     } while (0)
 
-    const int64_t nn = n > 0 ? n : 1;
-    GSR_RT(pool_alloc(ctx, st, &st->rec, 3 * nn));
-    GSR_RT(pool_alloc(ctx, st, &st->radius, nn));
-    GSR_RT(pool_alloc(ctx, st, &st->tiles_touched, nn));
-    GSR_RT(pool_alloc(ctx, st, &st->clamp_mask, nn));
-    GSR_RT(pool_alloc(ctx, st, &st->depth_key, nn));
-    GSR_RT(pool_alloc(ctx, st, &st->ids, nn));
-    GSR_RT(pool_alloc(ctx, st, &st->key_alt, nn));
-    GSR_RT(pool_alloc(ctx, st, &st->ids_alt, nn));
-    GSR_RT(pool_alloc(ctx, st, &st->offsets, nn + 1));
-    GSR_RT(pool_alloc(ctx, st, &st->ranges, st->n_tiles));
-    GSR_RT(pool_alloc(ctx, st, &st->T_final, hw));
-    GSR_RT(pool_alloc(ctx, st, &st->n_contrib, hw));
-
-    uint32_t *hist = nullptr, *partials = nullptr, *total = nullptr;
-    GSR_RT(pool_alloc(ctx, st, &total, 4));
+    for (int v = 0; v < nv; ++v) {
+        gsr_fwd *st = new (std::nothrow) gsr_fwd();
+        if (!st) return bail(fail(ctx, GSR_ENOMEM, "host allocation failed"));
+        sts[v] = st;
+        st->scene = scenes[v];
+        st->camera = cameras[v];
+        st->config = *config;
+        st->dcam = make_dev_camera(cameras[v], config->tile);
+        st->n = scenes[v].n;
+        st->n_tiles = (int64_t)st->dcam.grid_x * st->dcam.grid_y;
+        const int64_t nn = st->n > 0 ? st->n : 1;
+        const int64_t hw = (int64_t)cameras[v].width * cameras[v].height;
+        GSR_RT(pool_alloc(ctx, st, &st->rec, 3 * nn));
+        GSR_RT(pool_alloc(ctx, st, &st->radius, nn));
+        GSR_RT(pool_alloc(ctx, st, &st->tiles_touched, nn));
+        GSR_RT(pool_alloc(ctx, st, &st->clamp_mask, nn));
+        GSR_RT(pool_alloc(ctx, st, &st->depth_key, nn));
+        GSR_RT(pool_alloc(ctx, st, &st->ids, nn));
+        GSR_RT(pool_alloc(ctx, st, &st->key_alt, nn));
+        GSR_RT(pool_alloc(ctx, st, &st->ids_alt, nn));
+        GSR_RT(pool_alloc(ctx, st, &st->offsets, nn + 1));
+        GSR_RT(pool_alloc(ctx, st, &st->ranges, st->n_tiles));
+        GSR_RT(pool_alloc(ctx, st, &st->T_final, hw));
+        GSR_RT(pool_alloc(ctx, st, &st->n_contrib, hw));
+        GSR_RT(pool_alloc(ctx, st, &totals[v], 4));
+    }
 
     mark(ctx, tm, EV_R0);
     // a1: projection
-    GSR_RH(launch_preprocess_fwd(*scene, st->dcam, st->rec, st->radius, st->tiles_touched, st->depth_key, st->ids,
-                                 st->clamp_mask, s));
+    for (int v = 0; v < nv; ++v) {
+        gsr_fwd *st = sts[v];
+        GSR_RH(launch_preprocess_fwd(st->scene, st->dcam, st->rec, st->radius, st->tiles_touched, st->depth_key,
+                                     st->ids, st->clamp_mask, s));
+    }
     mark(ctx, tm, EV_R1);
     // a2/a3 (depth digits): sort Gaussians by fp32 depth; stable, so ties keep index order.
-    int which = 0;
-    if (n > 1) {
-        const size_t hc = radix_hist_count(n), pc = scan_partial_count((int64_t)hc);
-        GSR_RT(pool_alloc(ctx, st, &hist, hc));
-        GSR_RT(pool_alloc(ctx, st, &partials, pc));
-        GSR_RH(radix_sort_pairs(st->depth_key, st->ids, st->key_alt, st->ids_alt, n, 32, hist, partials, &which, s));
+    for (int v = 0; v < nv; ++v) {
+        gsr_fwd *st = sts[v];
+        const int64_t n = st->n;
+        int which = 0;
+        if (n > 1) {
+            const size_t hc = radix_hist_count(n), pc = scan_partial_count((int64_t)hc);
+            uint32_t *hist = nullptr, *partials = nullptr;
+            GSR_RT(pool_alloc(ctx, st, &hist, hc));
+            GSR_RT(pool_alloc(ctx, st, &partials, pc));
+            GSR_RH(radix_sort_pairs(st->depth_key, st->ids, st->key_alt, st->ids_alt, n, 32, hist, partials, &which,
+                                    s));
+        }
+        st->sorted_ids_by_depth = which ? st->ids_alt : st->ids;
     }
-    st->sorted_ids_by_depth = which ? st->ids_alt : st->ids;
     mark(ctx, tm, EV_R2);
-    // a2: pair offsets in depth order, total P read back to size the pair buffers.
-    {
+    // a2: pair offsets in depth order; the totals P of all views are read back at once to size
+    // the pair buffers.
+    for (int v = 0; v < nv; ++v) {
+        gsr_fwd *st = sts[v];
+        const int64_t n = st->n, nn = n > 0 ? n : 1;
         uint32_t *sp = nullptr;
         GSR_RT(pool_alloc(ctx, st, &sp, scan_partial_count(nn) + 8));
-        GSR_RH(device_exclusive_scan(st->tiles_touched, st->sorted_ids_by_depth, st->offsets, n, total, sp, s));
-        GSR_RH(launch_count_positive(st->radius, n, total + 1, s));
-        GSR_RH(hipMemcpyAsync(ctx->host_pinned, total, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-        GSR_RH(hipStreamSynchronize(s));
-        st->P = n > 0 ? (int64_t)ctx->host_pinned[0] : 0;
-        st->n_visible = n > 0 ? (int64_t)ctx->host_pinned[1] : 0;
+        GSR_RH(device_exclusive_scan(st->tiles_touched, st->sorted_ids_by_depth, st->offsets, n, totals[v], sp, s));
+        GSR_RH(launch_count_positive(st->radius, n, totals[v] + 1, s));
+        GSR_RH(hipMemcpyAsync(ctx->host_pinned + 2 * v, totals[v], 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     }
-    const int64_t P = st->P;
-    const int64_t PP = P > 0 ? P : 1;
-    GSR_RT(pool_alloc(ctx, st, &st->pair_tile, PP));
-    GSR_RT(pool_alloc(ctx, st, &st->pair_id, PP));
-    GSR_RT(pool_alloc(ctx, st, &st->pair_tile_alt, PP));
-    GSR_RT(pool_alloc(ctx, st, &st->pair_id_alt, PP));
-    GSR_RH(launch_emit_pairs(n, st->sorted_ids_by_depth, st->offsets, st->rec, st->radius, st->dcam, st->pair_tile,
-                             st->pair_id, s));
+    GSR_RH(hipStreamSynchronize(s));
+    for (int v = 0; v < nv; ++v) {
+        gsr_fwd *st = sts[v];
+        st->P = st->n > 0 ? (int64_t)ctx->host_pinned[2 * v] : 0;
+        st->n_visible = st->n > 0 ? (int64_t)ctx->host_pinned[2 * v + 1] : 0;
+        const int64_t PP = st->P > 0 ? st->P : 1;
+        GSR_RT(pool_alloc(ctx, st, &st->pair_tile, PP));
+        GSR_RT(pool_alloc(ctx, st, &st->pair_id, PP));
+        GSR_RT(pool_alloc(ctx, st, &st->pair_tile_alt, PP));
+        GSR_RT(pool_alloc(ctx, st, &st->pair_id_alt, PP));
+        GSR_RH(launch_emit_pairs(st->n, st->sorted_ids_by_depth, st->offsets, st->rec, st->radius, st->dcam,
+                                 st->pair_tile, st->pair_id, s));
+    }
     mark(ctx, tm, EV_R3);
     // a3 (tile digits): stable sort of the pairs by tile.
-    which = 0;
-    if (P > 1) {
-        const size_t hc = radix_hist_count(P), pc = scan_partial_count((int64_t)hc);
-        uint32_t *h2 = nullptr, *p2 = nullptr;
-        GSR_RT(pool_alloc(ctx, st, &h2, hc));
-        GSR_RT(pool_alloc(ctx, st, &p2, pc));
-        GSR_RH(radix_sort_pairs(st->pair_tile, st->pair_id, st->pair_tile_alt, st->pair_id_alt, P,
-                                bits_for(st->n_tiles), h2, p2, &which, s));
+    for (int v = 0; v < nv; ++v) {
+        gsr_fwd *st = sts[v];
+        const int64_t P = st->P;
+        int which = 0;
+        if (P > 1) {
+            const size_t hc = radix_hist_count(P), pc = scan_partial_count((int64_t)hc);
+            uint32_t *h2 = nullptr, *p2 = nullptr;
+            GSR_RT(pool_alloc(ctx, st, &h2, hc));
+            GSR_RT(pool_alloc(ctx, st, &p2, pc));
+            GSR_RH(radix_sort_pairs(st->pair_tile, st->pair_id, st->pair_tile_alt, st->pair_id_alt, P,
+                                    bits_for(st->n_tiles), h2, p2, &which, s));
+        }
+        sorted_tile[v] = which ? st->pair_tile_alt : st->pair_tile;
+        st->sorted_pair_id = which ? st->pair_id_alt : st->pair_id;
     }
-    uint32_t *sorted_tile = which ? st->pair_tile_alt : st->pair_tile;
-    st->sorted_pair_id = which ? st->pair_id_alt : st->pair_id;
     mark(ctx, tm, EV_R4);
     // a4: per-tile ranges
-    GSR_RH(launch_tile_ranges(P, sorted_tile, st->ranges, st->n_tiles, s));
+    for (int v = 0; v < nv; ++v) GSR_RH(launch_tile_ranges(sts[v]->P, sorted_tile[v], sts[v]->ranges, sts[v]->n_tiles, s));
     mark(ctx, tm, EV_R5);
-    // a5: forward composite, tiles launched longest list first; it records each tile's
-    // deepest n_contrib, which orders the backward's tiles the same way.
+    // a5: one forward composite over every (view, tile) pair, longest list first; it records
+    // each tile's deepest n_contrib, which orders the backward's tiles the same way.
     const bool ordered = !(config->flags & (GSR_FLAG_XCD_REMAP | GSR_FLAG_NO_TILE_ORDER));
-    if (ordered) {
-        GSR_RT(pool_alloc(ctx, st, &st->order_fwd, st->n_tiles));
-        GSR_RT(pool_alloc(ctx, st, &st->order_bwd, st->n_tiles));
-        GSR_RT(pool_alloc(ctx, st, &st->tile_walk, st->n_tiles));
-        GSR_RH(launch_order_tiles(nullptr, st->ranges, st->n_tiles, st->order_fwd, s));
+    ViewBatch vb{};
+    vb.n = nv;
+    for (int v = 0; v < nv; ++v) {
+        gsr_fwd *st = sts[v];
+        if (ordered) GSR_RT(pool_alloc(ctx, st, &st->tile_walk, st->n_tiles));
+        vb.v[v] = desc_of(st, images[v], nullptr);
+        vb.base[v + 1] = vb.base[v] + (uint32_t)st->n_tiles;
     }
-    FwdArgs fa{st->ranges, st->sorted_pair_id, st->rec, image_chw, st->T_final, st->n_contrib,
-               ordered ? st->order_fwd : nullptr, ordered ? st->tile_walk : nullptr};
-    GSR_RH(launch_composite_fwd(st->dcam, config->lds_batch, (config->flags & GSR_FLAG_XCD_REMAP) ? 1 : 0, fa, s));
-    if (ordered) GSR_RH(launch_order_tiles(st->tile_walk, nullptr, st->n_tiles, st->order_bwd, s));
+    {
+        TempBuf tb;
+        uint2 *work = nullptr;
+        if (nv > 1 || ordered) {
+            GSR_RT(temp_alloc(ctx, tb, &work, vb.base[nv]));
+            GSR_RH(launch_order_tiles(vb, ordered ? ORDER_BY_LENGTH : ORDER_IDENTITY, work, s));
+        }
+        const int remap = (nv == 1 && (config->flags & GSR_FLAG_XCD_REMAP)) ? 1 : 0;
+        GSR_RH(launch_composite_fwd(vb, config->tile, config->lds_batch, remap, work, s));
+    }
+    if (ordered && nv == 1) {
+        gsr_fwd *st = sts[0];
+        GSR_RT(pool_alloc(ctx, st, &st->order_bwd, st->n_tiles));
+        GSR_RH(launch_order_tiles(vb, ORDER_BY_WALK, st->order_bwd, s));
+    }
     mark(ctx, tm, EV_R6);
 #undef GSR_RT
 #undef GSR_RH
-    *state_out = st;
+    for (int v = 0; v < nv; ++v) states_out[v] = sts[v];
     return GSR_OK;
 }
 
-static gsr_status bwd_composite(gsr_ctx *ctx, gsr_fwd *st, const float *dl, const gsr_config *cfg, bool tm) {
-    const int64_t n = st->n;
-    const int64_t nn = n > 0 ? n : 1;
-    hipStream_t s = ctx->stream;
-    if (!st->acc) GSR_TRY(pool_alloc(ctx, st, &st->acc, (size_t)nn * GSR_ACC_STRIDE));
+// Backward composite over nv checked states, in two parts so that the second
+// can be captured in a graph: bwd_prepare makes every buffer exist (and
+// computes a single view's cached tile order once), bwd_enqueue only launches
+// kernels (accumulators zeroed by fill kernels, one composite launch over
+// every (view, tile) pair).
+struct BwdPlan {
+    ViewBatch vb{};
+    int order_mode = ORDER_IDENTITY;
+    uint2 *work = nullptr;   // table the composite reads (nullptr: identity / XCD remap, one view)
+    bool build_work = false; // recompute `work` before the composite
+    int remap = 0;
+};
+
+gsr_status bwd_prepare(gsr_ctx *ctx, int nv, gsr_fwd *const *sts, const float *const *dls, const gsr_config *cfg,
+                       BwdPlan &plan) {
     const bool count = (cfg->flags & GSR_FLAG_DEBUG_COUNTERS) != 0;
-    if (count && !st->counters) GSR_TRY(pool_alloc(ctx, st, &st->counters, 80));
-    mark(ctx, tm, EV_B0);
-    GSR_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t *>(st->acc), 0u, nn * GSR_ACC_STRIDE, s));
-    if (count) GSR_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t *>(st->counters), 0u, 160, s));
-    mark(ctx, tm, EV_B1);
-    BwdArgs a{};
-    a.ranges = st->ranges;
-    a.sorted_ids = st->sorted_pair_id;
-    a.rec = st->rec;
-    a.dl_dimage = dl;
-    a.T_final = st->T_final;
-    a.n_contrib = st->n_contrib;
-    a.acc = st->acc;
-    a.counters = st->counters;
-    a.threshold = cfg->reduce_threshold < 1 ? 1 : cfg->reduce_threshold;
-    a.order = (cfg->flags & (GSR_FLAG_XCD_REMAP | GSR_FLAG_NO_TILE_ORDER)) ? nullptr : st->order_bwd;
-    GSR_HIP(ctx, launch_composite_bwd(st->dcam, cfg->lds_batch, (cfg->flags & GSR_FLAG_XCD_REMAP) ? 1 : 0,
-                                      cfg->bwd_mode, count, (cfg->flags & GSR_FLAG_LANE_SPLIT_ATOMICS) != 0, a, s));
-    mark(ctx, tm, EV_B2);
-    st->counters_valid = count;
+    for (int v = 0; v < nv; ++v) {
+        gsr_fwd *st = sts[v];
+        if (!st->acc) GSR_TRY(pool_alloc(ctx, st, &st->acc, (size_t)(st->n > 0 ? st->n : 1) * GSR_ACC_STRIDE));
+    }
+    if (count && !sts[0]->counters) GSR_TRY(pool_alloc(ctx, sts[0], &sts[0]->counters, 80));
+    ViewBatch &vb = plan.vb;
+    vb = ViewBatch{};
+    vb.n = nv;
+    bool walks = true;
+    for (int v = 0; v < nv; ++v) {
+        vb.v[v] = desc_of(sts[v], nullptr, dls[v]);
+        vb.base[v + 1] = vb.base[v] + (uint32_t)sts[v]->n_tiles;
+        walks = walks && sts[v]->tile_walk != nullptr;
+    }
+    const bool ordered = !(cfg->flags & (GSR_FLAG_XCD_REMAP | GSR_FLAG_NO_TILE_ORDER));
+    plan.order_mode = ordered ? (walks ? ORDER_BY_WALK : ORDER_BY_LENGTH) : ORDER_IDENTITY;
+    plan.remap = (nv == 1 && (cfg->flags & GSR_FLAG_XCD_REMAP)) ? 1 : 0;
+    plan.work = nullptr;
+    plan.build_work = false;
+    if (nv == 1) {
+        if (ordered) {
+            gsr_fwd *st = sts[0];
+            if (!st->order_bwd) {
+                GSR_TRY(pool_alloc(ctx, st, &st->order_bwd, st->n_tiles));
+                GSR_HIP(ctx, launch_order_tiles(vb, plan.order_mode, st->order_bwd, ctx->stream));
+            }
+            plan.work = st->order_bwd;
+        }
+    } else {
+        gsr_fwd *lead = sts[0];
+        if (lead->batch_work_cap < (int64_t)vb.base[nv]) {
+            GSR_TRY(pool_alloc(ctx, lead, &lead->batch_work, vb.base[nv]));
+            lead->batch_work_cap = vb.base[nv];
+        }
+        plan.work = lead->batch_work;
+        plan.build_work = true;
+    }
     return GSR_OK;
 }
 
-static gsr_status check_bwd_args(gsr_ctx *ctx, gsr_fwd *st, const float *dl, const gsr_config **cfg) {
-    if (!ctx) return GSR_EINVAL;
-    ctx->err.clear();
+gsr_status bwd_enqueue(gsr_ctx *ctx, int nv, gsr_fwd *const *sts, const gsr_config *cfg, const BwdPlan &plan,
+                       bool tm) {
+    hipStream_t s = ctx->stream;
+    const bool count = (cfg->flags & GSR_FLAG_DEBUG_COUNTERS) != 0;
+    for (int v = 0; v < nv; ++v) sts[v]->counters_valid = false;
+    mark(ctx, tm, EV_B0);
+    for (int v = 0; v < nv; ++v) {
+        const int64_t nn = sts[v]->n > 0 ? sts[v]->n : 1;
+        GSR_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t *>(sts[v]->acc), 0u, nn * GSR_ACC_STRIDE, s));
+    }
+    if (count) GSR_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t *>(sts[0]->counters), 0u, 160, s));
+    mark(ctx, tm, EV_B1);
+    if (plan.build_work) GSR_HIP(ctx, launch_order_tiles(plan.vb, plan.order_mode, plan.work, s));
+    BwdParams p{};
+    p.counters = count ? sts[0]->counters : nullptr;
+    p.threshold = cfg->reduce_threshold < 1 ? 1 : cfg->reduce_threshold;
+    GSR_HIP(ctx, launch_composite_bwd(plan.vb, cfg->tile, cfg->lds_batch, plan.remap, cfg->bwd_mode, count,
+                                      (cfg->flags & GSR_FLAG_LANE_SPLIT_ATOMICS) != 0, p, plan.work, s));
+    mark(ctx, tm, EV_B2);
+    sts[0]->counters_valid = count;
+    return GSR_OK;
+}
+
+gsr_status bwd_views(gsr_ctx *ctx, int nv, gsr_fwd *const *sts, const float *const *dls, const gsr_config *cfg,
+                     bool tm) {
+    BwdPlan plan;
+    GSR_TRY(bwd_prepare(ctx, nv, sts, dls, cfg, plan));
+    return bwd_enqueue(ctx, nv, sts, cfg, plan, tm);
+}
+
+gsr_status check_bwd_args(gsr_ctx *ctx, gsr_fwd *st, const float *dl, const gsr_config **cfg) {
     if (!st) return fail(ctx, GSR_EINVAL, "state is null");
     if (!dl) return fail(ctx, GSR_EINVAL, "dl_dimage is null");
     if (!*cfg) *cfg = &st->config;
     if ((*cfg)->tile != st->config.tile) return fail(ctx, GSR_EINVAL, "backward tile differs from the render's");
     if (gsr_validate_config(*cfg, &st->camera) != GSR_OK) return fail(ctx, GSR_EINVAL, "invalid config");
-    GSR_HIP(ctx, hipSetDevice(ctx->device));
     return GSR_OK;
 }
 
-static gsr_status check_grads(gsr_ctx *ctx, const gsr_fwd *st, const gsr_grads *out) {
+gsr_status check_grads(gsr_ctx *ctx, const gsr_fwd *st, const gsr_grads *out) {
     if (!out) return fail(ctx, GSR_EINVAL, "grads is null");
     if (st->n > 0 && (!out->means3d || !out->log_scales || !out->quats || !out->opacity_logits || !out->sh))
         return fail(ctx, GSR_EINVAL, "a gradient pointer is null");
     return GSR_OK;
 }
 
+// 0: no pointer shared, 1: all five equal, -1: some but not all.
+int grads_alias(const gsr_grads &a, const gsr_grads &b) {
+    const int eq = (a.means3d == b.means3d) + (a.log_scales == b.log_scales) + (a.quats == b.quats) +
+                   (a.opacity_logits == b.opacity_logits) + (a.sh == b.sh);
+    return eq == 5 ? 1 : (eq == 0 ? 0 : -1);
+}
+
+} // namespace
+
+extern "C" {
+
+gsr_status gsr_render(gsr_ctx *ctx, const gsr_scene *scene, const gsr_camera *camera, const gsr_config *config,
+                      float *image_chw, gsr_fwd **state_out) {
+    if (!ctx) return GSR_EINVAL;
+    ctx->err.clear();
+    if (!state_out) return fail(ctx, GSR_EINVAL, "state_out is null");
+    *state_out = nullptr;
+    GSR_TRY(check_view(ctx, 0, scene, camera, config, image_chw));
+    return render_views(ctx, 1, scene, camera, config, &image_chw, state_out);
+}
+
+gsr_status gsr_render_batch(gsr_ctx *ctx, int32_t n_views, const gsr_scene *scenes, const gsr_camera *cameras,
+                            const gsr_config *config, float *const *images_chw, gsr_fwd **states_out) {
+    if (!ctx) return GSR_EINVAL;
+    ctx->err.clear();
+    if (n_views < 1 || n_views > GSR_MAX_BATCH) return fail(ctx, GSR_EINVAL, "n_views %d outside 1..16", n_views);
+    if (!scenes || !cameras || !images_chw || !states_out) return fail(ctx, GSR_EINVAL, "null array argument");
+    for (int v = 0; v < n_views; ++v) states_out[v] = nullptr;
+    for (int v = 0; v < n_views; ++v) GSR_TRY(check_view(ctx, v, &scenes[v], &cameras[v], config, images_chw[v]));
+    return render_views(ctx, n_views, scenes, cameras, config, images_chw, states_out);
+}
+
 gsr_status gsr_backward_composite(gsr_ctx *ctx, gsr_fwd *st, const float *dl_dimage_chw, const gsr_config *config) {
+    if (!ctx) return GSR_EINVAL;
+    ctx->err.clear();
     GSR_TRY(check_bwd_args(ctx, st, dl_dimage_chw, &config));
+    GSR_HIP(ctx, hipSetDevice(ctx->device));
     const bool tm = (config->flags & GSR_FLAG_STAGE_TIMING) != 0;
     ctx->timing_bwd = false;
-    return bwd_composite(ctx, st, dl_dimage_chw, config, tm);
+    return bwd_views(ctx, 1, &st, &dl_dimage_chw, config, tm);
 }
 
 gsr_status gsr_backward_params(gsr_ctx *ctx, gsr_fwd *st, const gsr_grads *out, int accumulate) {
@@ -456,15 +610,153 @@ gsr_status gsr_backward_params(gsr_ctx *ctx, gsr_fwd *st, const gsr_grads *out, 
 
 gsr_status gsr_backward(gsr_ctx *ctx, gsr_fwd *st, const float *dl_dimage_chw, const gsr_grads *out, int accumulate,
                         const gsr_config *config) {
+    if (!ctx) return GSR_EINVAL;
+    ctx->err.clear();
     GSR_TRY(check_bwd_args(ctx, st, dl_dimage_chw, &config));
     GSR_TRY(check_grads(ctx, st, out));
+    GSR_HIP(ctx, hipSetDevice(ctx->device));
     const bool tm = (config->flags & GSR_FLAG_STAGE_TIMING) != 0;
-    GSR_TRY(bwd_composite(ctx, st, dl_dimage_chw, config, tm));
+    GSR_TRY(bwd_views(ctx, 1, &st, &dl_dimage_chw, config, tm));
     GSR_HIP(ctx, launch_preprocess_bwd(st->scene, st->dcam, st->radius, st->acc, *out, accumulate ? 1 : 0,
                                        ctx->stream));
     mark(ctx, tm, EV_B3);
     ctx->timing_bwd = tm;
     return GSR_OK;
+}
+
+} // extern "C"
+
+namespace {
+
+// Argument checks shared by the batched backward and its graph capture. adds[v]: view v's
+// per-Gaussian part adds to its outputs (accumulate, or outputs shared with an earlier view).
+gsr_status check_batch_bwd(gsr_ctx *ctx, int32_t n_views, gsr_fwd *const *states, const float *const *dls,
+                           const gsr_grads *outs, int accumulate, const gsr_config **config, int *adds) {
+    if (n_views < 1 || n_views > GSR_MAX_BATCH) return fail(ctx, GSR_EINVAL, "n_views %d outside 1..16", n_views);
+    if (!states || !dls || !outs) return fail(ctx, GSR_EINVAL, "null array argument");
+    if (!states[0]) return fail(ctx, GSR_EINVAL, "state 0 is null");
+    if (!*config) *config = &states[0]->config;
+    for (int v = 0; v < n_views; ++v) {
+        const gsr_config *c = *config;
+        GSR_TRY(check_bwd_args(ctx, states[v], dls[v], &c));
+        GSR_TRY(check_grads(ctx, states[v], &outs[v]));
+        adds[v] = accumulate ? 1 : 0;
+        for (int u = 0; u < v; ++u) {
+            if (states[u] == states[v]) return fail(ctx, GSR_EINVAL, "views %d and %d share a state", u, v);
+            const int al = grads_alias(outs[u], outs[v]);
+            if (al < 0) return fail(ctx, GSR_EINVAL, "outputs of views %d and %d partly overlap", u, v);
+            if (al > 0) adds[v] = 1;
+        }
+    }
+    return GSR_OK;
+}
+
+gsr_status enqueue_params(gsr_ctx *ctx, int nv, gsr_fwd *const *states, const gsr_grads *outs, const int *adds) {
+    for (int v = 0; v < nv; ++v) {
+        gsr_fwd *st = states[v];
+        GSR_HIP(ctx, launch_preprocess_bwd(st->scene, st->dcam, st->radius, st->acc, outs[v], adds[v], ctx->stream));
+    }
+    return GSR_OK;
+}
+
+} // namespace
+
+struct gsr_graph {
+    int device = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+gsr_status gsr_backward_batch(gsr_ctx *ctx, int32_t n_views, gsr_fwd *const *states,
+                              const float *const *dl_dimages_chw, const gsr_grads *outs, int accumulate,
+                              const gsr_config *config) {
+    if (!ctx) return GSR_EINVAL;
+    ctx->err.clear();
+    int adds[kMaxViews] = {};
+    GSR_TRY(check_batch_bwd(ctx, n_views, states, dl_dimages_chw, outs, accumulate, &config, adds));
+    GSR_HIP(ctx, hipSetDevice(ctx->device));
+    const bool tm = (config->flags & GSR_FLAG_STAGE_TIMING) != 0;
+    GSR_TRY(bwd_views(ctx, n_views, states, dl_dimages_chw, config, tm));
+    GSR_TRY(enqueue_params(ctx, n_views, states, outs, adds));
+    mark(ctx, tm, EV_B3);
+    ctx->timing_bwd = tm;
+    return GSR_OK;
+}
+
+gsr_status gsr_graph_capture_backward(gsr_ctx *ctx, int32_t n_views, gsr_fwd *const *states,
+                                      const float *const *dl_dimages_chw, const gsr_grads *outs, int accumulate,
+                                      const gsr_config *config, gsr_graph **graph_out) {
+    if (!ctx) return GSR_EINVAL;
+    ctx->err.clear();
+    if (!graph_out) return fail(ctx, GSR_EINVAL, "graph_out is null");
+    *graph_out = nullptr;
+    int adds[kMaxViews] = {};
+    GSR_TRY(check_batch_bwd(ctx, n_views, states, dl_dimages_chw, outs, accumulate, &config, adds));
+    gsr_config cfg = *config;
+    cfg.flags &= ~GSR_FLAG_STAGE_TIMING;
+    GSR_HIP(ctx, hipSetDevice(ctx->device));
+    // Every buffer is allocated (and a single view's tile order computed) before the capture,
+    // so the captured work is kernels only.
+    BwdPlan plan;
+    GSR_TRY(bwd_prepare(ctx, n_views, states, dl_dimages_chw, &cfg, plan));
+    // Capture needs a stream other than the null stream.
+    hipStream_t saved = ctx->stream, cs = ctx->stream;
+    const bool own = cs == nullptr;
+    if (own) GSR_HIP(ctx, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    gsr_status st = GSR_OK;
+    if (e == hipSuccess) {
+        ctx->stream = cs;
+        st = bwd_enqueue(ctx, n_views, states, &cfg, plan, false);
+        if (st == GSR_OK) st = enqueue_params(ctx, n_views, states, outs, adds);
+        ctx->stream = saved;
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = e == hipSuccess ? hipStreamEndCapture(cs, &g) : e;
+    if (own) (void)hipStreamDestroy(cs);
+    if (st != GSR_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e2 != hipSuccess) return fail(ctx, GSR_EHIP, "stream capture failed: %s", hipGetErrorString(e2));
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(ctx, GSR_EHIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+    }
+    gsr_graph *gr = new (std::nothrow) gsr_graph();
+    if (!gr) {
+        (void)hipGraphExecDestroy(ex);
+        (void)hipGraphDestroy(g);
+        return fail(ctx, GSR_ENOMEM, "host allocation failed");
+    }
+    gr->device = ctx->device;
+    gr->graph = g;
+    gr->exec = ex;
+    *graph_out = gr;
+    return GSR_OK;
+}
+
+gsr_status gsr_graph_launch(gsr_ctx *ctx, gsr_graph *graph) {
+    if (!ctx) return GSR_EINVAL;
+    ctx->err.clear();
+    if (!graph) return fail(ctx, GSR_EINVAL, "graph is null");
+    if (graph->device != ctx->device) return fail(ctx, GSR_EINVAL, "graph was captured on another device");
+    GSR_HIP(ctx, hipSetDevice(ctx->device));
+    GSR_HIP(ctx, hipGraphLaunch(graph->exec, ctx->stream));
+    return GSR_OK;
+}
+
+void gsr_graph_destroy(gsr_ctx *ctx, gsr_graph *graph) {
+    if (!graph) return;
+    (void)hipSetDevice(graph->device);
+    if (ctx) (void)hipStreamSynchronize(ctx->stream);
+    if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+    if (graph->graph) (void)hipGraphDestroy(graph->graph);
+    delete graph;
 }
 
 gsr_status gsr_fwd_release(gsr_ctx *ctx, gsr_fwd *st) {
@@ -585,6 +877,26 @@ gsr_status gsr_l1_grad(gsr_ctx *ctx, const float *image, const float *target, in
     return GSR_OK;
 }
 
+gsr_status gsr_l1_dssim_grad(gsr_ctx *ctx, const float *image, const float *target, int32_t height, int32_t width,
+                             float lambda, float *dl_dimage, float *loss) {
+    if (!ctx) return GSR_EINVAL;
+    ctx->err.clear();
+    if (height < 1 || width < 1 || height > 16384 || width > 16384 || !image || !target || !dl_dimage)
+        return fail(ctx, GSR_EINVAL, "bad arguments");
+    if (!(lambda >= 0.0f && lambda <= 1.0f)) return fail(ctx, GSR_EINVAL, "lambda outside [0, 1]");
+    GSR_HIP(ctx, hipSetDevice(ctx->device));
+    const size_t n = 3 * (size_t)height * width;
+    TempBuf t0, t1, t2, t3;
+    float *dmu = nullptr, *dexx = nullptr, *dexy = nullptr, *sums = nullptr;
+    GSR_TRY(temp_alloc(ctx, t0, &dmu, n));
+    GSR_TRY(temp_alloc(ctx, t1, &dexx, n));
+    GSR_TRY(temp_alloc(ctx, t2, &dexy, n));
+    GSR_TRY(temp_alloc(ctx, t3, &sums, 2));
+    GSR_HIP(ctx, launch_l1_dssim_grad(image, target, 3, width, height, lambda, dmu, dexx, dexy, sums, dl_dimage, loss,
+                                      ctx->stream));
+    return GSR_OK;
+}
+
 gsr_status gsr_wave_reduce_selftest(gsr_ctx *ctx, const float *vals, const uint8_t *active, int32_t n_waves,
                                     int32_t mode, int32_t threshold, int32_t lane_split, float *sums,
                                     uint64_t *lane_atomics) {
@@ -592,7 +904,8 @@ gsr_status gsr_wave_reduce_selftest(gsr_ctx *ctx, const float *vals, const uint8
     ctx->err.clear();
     if (n_waves < 0 || n_waves > (1 << 24) || (n_waves > 0 && (!vals || !active)) || !sums || !lane_atomics)
         return fail(ctx, GSR_EINVAL, "bad arguments");
-    if (mode != GSR_BWD_PLAIN_ATOMIC && mode != GSR_BWD_WAVE_REDUCE) return fail(ctx, GSR_EINVAL, "bad mode");
+    if (mode != GSR_BWD_PLAIN_ATOMIC && mode != GSR_BWD_WAVE_REDUCE && mode != GSR_BWD_SERIAL_REDUCE)
+        return fail(ctx, GSR_EINVAL, "bad mode");
     if (threshold < 0 || threshold > 65) return fail(ctx, GSR_EINVAL, "bad threshold");
     GSR_HIP(ctx, hipSetDevice(ctx->device));
     GSR_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t *>(sums), 0u, 9, ctx->stream));
@@ -604,3 +917,216 @@ gsr_status gsr_wave_reduce_selftest(gsr_ctx *ctx, const float *vals, const uint8
 }
 
 } // extern "C"
+
+namespace {
+
+gsr_status check_space(gsr_ctx *ctx, const gsr_tune_space *sp) {
+    if (!sp) return fail(ctx, GSR_EINVAL, "tune space is null");
+    if (sp->n_tiles < 1 || sp->n_tiles > 3 || sp->n_batches < 1 || sp->n_batches > 3 || sp->n_thresholds < 1 ||
+        sp->n_thresholds > 8 || sp->reps < 1 || sp->reps > 100)
+        return fail(ctx, GSR_EINVAL, "tune space sizes out of range");
+    for (int i = 0; i < sp->n_tiles; ++i)
+        if (sp->tiles[i] != 8 && sp->tiles[i] != 16 && sp->tiles[i] != 32)
+            return fail(ctx, GSR_EINVAL, "tile %d not in {8,16,32}", sp->tiles[i]);
+    for (int i = 0; i < sp->n_batches; ++i)
+        if (sp->batches[i] != 64 && sp->batches[i] != 128 && sp->batches[i] != 256)
+            return fail(ctx, GSR_EINVAL, "lds batch %d not in {64,128,256}", sp->batches[i]);
+    for (int i = 0; i < sp->n_thresholds; ++i)
+        if (sp->thresholds[i] < 1 || sp->thresholds[i] > 65)
+            return fail(ctx, GSR_EINVAL, "threshold %d outside 1..65", sp->thresholds[i]);
+    bool any = false;
+    for (int i = 0; i < sp->n_tiles; ++i)
+        for (int j = 0; j < sp->n_batches; ++j) any = any || sp->batches[j] <= sp->tiles[i] * sp->tiles[i];
+    if (!any) return fail(ctx, GSR_EINVAL, "no (tile, lds batch) pair with batch <= tile*tile");
+    return GSR_OK;
+}
+
+float median_of(std::vector<float> v) {
+    std::sort(v.begin(), v.end());
+    return v[v.size() / 2];
+}
+
+// Pool buffers and events of one tuning run, returned when it ends.
+struct TuneScratch {
+    gsr_ctx *ctx;
+    std::vector<void *> bufs;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    gsr_fwd *sts[kMaxViews] = {};
+    int nv = 0;
+    explicit TuneScratch(gsr_ctx *c) : ctx(c) {}
+    void release_states() {
+        for (int v = 0; v < nv; ++v)
+            if (sts[v]) gsr_fwd_release(ctx, sts[v]);
+        for (auto &p : sts) p = nullptr;
+    }
+    ~TuneScratch() {
+        release_states();
+        for (void *p : bufs) ctx->pool->release(p);
+        for (auto e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+    template <typename T>
+    gsr_status alloc(T **p, size_t count) {
+        GSR_TRY(pool_alloc(ctx, nullptr, p, count));
+        bufs.push_back(*p);
+        return GSR_OK;
+    }
+};
+
+} // namespace
+
+struct gsr_tuner {
+    gsr_tune_space space{};
+    int32_t every = 1;
+    int64_t iter = 0;
+    gsr_config best{};
+};
+
+extern "C" {
+
+gsr_status gsr_autotune(gsr_ctx *ctx, int32_t n_views, const gsr_scene *scenes, const gsr_camera *cameras,
+                        const float *const *dl_dimages_chw, const gsr_tune_space *space, gsr_config *best,
+                        gsr_tune_entry *entries, int32_t max_entries, int32_t *n_entries) {
+    if (!ctx) return GSR_EINVAL;
+    ctx->err.clear();
+    if (n_views < 1 || n_views > GSR_MAX_BATCH) return fail(ctx, GSR_EINVAL, "n_views %d outside 1..16", n_views);
+    if (!scenes || !cameras || !best) return fail(ctx, GSR_EINVAL, "null argument");
+    if (max_entries < 0 || (max_entries > 0 && !entries)) return fail(ctx, GSR_EINVAL, "bad entries buffer");
+    GSR_TRY(check_space(ctx, space));
+    const int32_t flags = space->flags & ~(GSR_FLAG_STAGE_TIMING | GSR_FLAG_DEBUG_COUNTERS);
+    for (int v = 0; v < n_views; ++v) {
+        if (gsr_validate_scene(&scenes[v]) != GSR_OK) return fail(ctx, GSR_EINVAL, "invalid scene (view %d)", v);
+        if (gsr_validate_camera(&cameras[v]) != GSR_OK) return fail(ctx, GSR_EINVAL, "invalid camera (view %d)", v);
+        for (int i = 0; i < space->n_tiles; ++i) {
+            const gsr_config c{space->tiles[i], 64, GSR_BWD_WAVE_REDUCE, 1, flags};
+            if (gsr_validate_config(&c, &cameras[v]) != GSR_OK)
+                return fail(ctx, GSR_EINVAL, "tune flags or tile %d invalid for view %d", space->tiles[i], v);
+        }
+    }
+    GSR_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    TuneScratch sc(ctx);
+    sc.nv = n_views;
+    for (auto &e : sc.ev) GSR_HIP(ctx, hipEventCreate(&e));
+    // Scratch images, gradient images and outputs (views of one scene share outputs, which
+    // sums their gradients as a training step over the batch would).
+    float *images[kMaxViews] = {};
+    const float *dls[kMaxViews] = {};
+    gsr_grads outs[kMaxViews] = {};
+    int adds[kMaxViews] = {};
+    for (int v = 0; v < n_views; ++v) {
+        const size_t hw = (size_t)cameras[v].width * cameras[v].height;
+        GSR_TRY(sc.alloc(&images[v], 3 * hw));
+        if (dl_dimages_chw && dl_dimages_chw[v]) {
+            dls[v] = dl_dimages_chw[v];
+        } else {
+            float *d = nullptr;
+            GSR_TRY(sc.alloc(&d, 3 * hw));
+            const float c = 1e-3f;
+            uint32_t bits;
+            std::memcpy(&bits, &c, 4);
+            GSR_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t *>(d), bits, 3 * hw, s));
+            dls[v] = d;
+        }
+        int shared = -1;
+        for (int u = 0; u < v; ++u)
+            if (scenes[u].means3d == scenes[v].means3d && scenes[u].n == scenes[v].n &&
+                scenes[u].sh_degree == scenes[v].sh_degree)
+                shared = u;
+        if (shared >= 0) {
+            outs[v] = outs[shared];
+            adds[v] = 1;
+            continue;
+        }
+        const size_t n = scenes[v].n > 0 ? scenes[v].n : 1, K = (size_t)(scenes[v].sh_degree + 1) * (scenes[v].sh_degree + 1);
+        GSR_TRY(sc.alloc(&outs[v].means3d, 3 * n));
+        GSR_TRY(sc.alloc(&outs[v].log_scales, 3 * n));
+        GSR_TRY(sc.alloc(&outs[v].quats, 4 * n));
+        GSR_TRY(sc.alloc(&outs[v].opacity_logits, n));
+        GSR_TRY(sc.alloc(&outs[v].sh, 3 * K * n));
+    }
+    const auto timed = [&](float *ms, auto &&work) -> gsr_status {
+        GSR_HIP(ctx, hipEventRecord(sc.ev[0], s));
+        GSR_TRY(work());
+        GSR_HIP(ctx, hipEventRecord(sc.ev[1], s));
+        GSR_HIP(ctx, hipEventSynchronize(sc.ev[1]));
+        GSR_HIP(ctx, hipEventElapsedTime(ms, sc.ev[0], sc.ev[1]));
+        return GSR_OK;
+    };
+    int32_t count = 0;
+    float best_ms = 0.0f;
+    bool have = false;
+    for (int ti = 0; ti < space->n_tiles; ++ti) {
+        for (int bi = 0; bi < space->n_batches; ++bi) {
+            const int tile = space->tiles[ti], lb = space->batches[bi];
+            if (lb > tile * tile) continue;
+            gsr_config cfg{tile, lb, GSR_BWD_WAVE_REDUCE, 1, flags};
+            // One untimed run first: it fills the pool for this tile size.
+            std::vector<float> rt;
+            for (int r = 0; r <= space->reps; ++r) {
+                sc.release_states();
+                float ms = 0.0f;
+                GSR_TRY(timed(&ms, [&] { return render_views(ctx, n_views, scenes, cameras, &cfg, images, sc.sts); }));
+                if (r > 0) rt.push_back(ms);
+            }
+            const float render_ms = median_of(rt);
+            for (int hi = 0; hi < space->n_thresholds; ++hi) {
+                cfg.reduce_threshold = space->thresholds[hi];
+                std::vector<float> bt;
+                for (int r = 0; r <= space->reps; ++r) {
+                    float ms = 0.0f;
+                    GSR_TRY(timed(&ms, [&] {
+                        GSR_TRY(bwd_views(ctx, n_views, sc.sts, dls, &cfg, false));
+                        return enqueue_params(ctx, n_views, sc.sts, outs, adds);
+                    }));
+                    if (r > 0) bt.push_back(ms);
+                }
+                const float bwd_ms = median_of(bt);
+                if (count < max_entries) entries[count] = gsr_tune_entry{cfg, render_ms, bwd_ms};
+                ++count;
+                if (!have || render_ms + bwd_ms < best_ms) {
+                    have = true;
+                    best_ms = render_ms + bwd_ms;
+                    *best = cfg;
+                }
+            }
+        }
+    }
+    if (n_entries) *n_entries = count < max_entries ? count : max_entries;
+    return GSR_OK;
+}
+
+gsr_status gsr_tuner_create(const gsr_tune_space *space, int32_t every, gsr_tuner **out) {
+    if (!out) return GSR_EINVAL;
+    *out = nullptr;
+    if (every < 1 || check_space(nullptr, space) != GSR_OK) return GSR_EINVAL;
+    gsr_tuner *t = new (std::nothrow) gsr_tuner();
+    if (!t) return GSR_ENOMEM;
+    t->space = *space;
+    t->every = every;
+    *out = t;
+    return GSR_OK;
+}
+
+gsr_status gsr_tuner_next(gsr_ctx *ctx, gsr_tuner *tuner, int32_t n_views, const gsr_scene *scenes,
+                          const gsr_camera *cameras, const float *const *dl_dimages_chw, gsr_config *config_out,
+                          int32_t *retuned) {
+    if (!ctx) return GSR_EINVAL;
+    ctx->err.clear();
+    if (!tuner || !config_out) return fail(ctx, GSR_EINVAL, "null argument");
+    int32_t did = 0;
+    if (tuner->iter % tuner->every == 0) {
+        GSR_TRY(gsr_autotune(ctx, n_views, scenes, cameras, dl_dimages_chw, &tuner->space, &tuner->best, nullptr, 0,
+                             nullptr));
+        did = 1;
+    }
+    ++tuner->iter;
+    *config_out = tuner->best;
+    if (retuned) *retuned = did;
+    return GSR_OK;
+}
+
+void gsr_tuner_destroy(gsr_tuner *tuner) { delete tuner; }
+
+} // extern "C"
+

@@ -8,6 +8,8 @@ library is not built: there is no fallback path.
 from __future__ import annotations
 
 import ctypes
+
+import numpy as np
 import os
 from dataclasses import dataclass
 
@@ -15,12 +17,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "_lib", "libgsr.so")
 
 GSR_OK, GSR_EINVAL, GSR_ENOMEM, GSR_EHIP, GSR_ESTATE = 0, -1, -2, -3, -4
-GSR_BWD_PLAIN_ATOMIC, GSR_BWD_WAVE_REDUCE = 0, 1
+GSR_BWD_PLAIN_ATOMIC, GSR_BWD_WAVE_REDUCE, GSR_BWD_SERIAL_REDUCE, GSR_BWD_BLOCK_REDUCE = 0, 1, 2, 3
 GSR_FLAG_DEBUG_COUNTERS = 1
 GSR_FLAG_XCD_REMAP = 2
 GSR_FLAG_STAGE_TIMING = 4
 GSR_FLAG_LANE_SPLIT_ATOMICS = 8
 GSR_FLAG_NO_TILE_ORDER = 16
+GSR_MAX_BATCH = 16
+GSR_EBUDGET = -5
 GSR_ACC_STRIDE = 16
 
 c_void_p = ctypes.c_void_p
@@ -71,6 +75,30 @@ class gsr_stage_times_t(ctypes.Structure):
                                              "composite_fwd", "zero_acc", "composite_bwd", "preprocess_bwd")]
 
 
+class gsr_tune_space(ctypes.Structure):
+    _fields_ = [("n_tiles", c_int32), ("tiles", c_int32 * 3), ("n_batches", c_int32), ("batches", c_int32 * 3),
+                ("n_thresholds", c_int32), ("thresholds", c_int32 * 8), ("reps", c_int32), ("flags", c_int32)]
+
+
+class gsr_tune_entry(ctypes.Structure):
+    _fields_ = [("config", gsr_config), ("render_ms", ctypes.c_float), ("backward_ms", ctypes.c_float)]
+
+
+class gsr_server_opts(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", c_int64), ("max_batch", c_int32), ("lanes", c_int32), ("config", gsr_config),
+                ("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
+
+
+class gsr_request(ctypes.Structure):
+    _fields_ = [("scene", c_int32), ("camera", gsr_camera), ("target_seed", ctypes.c_uint64)]
+
+
+class gsr_result(ctypes.Structure):
+    _fields_ = [("id", c_int64), ("scene", c_int32), ("status", c_int32), ("batch_size", c_int32), ("lane", c_int32),
+                ("step", c_int32), ("loss", ctypes.c_float), ("t_arrival", ctypes.c_double),
+                ("t_start", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
 class GsrError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"gsr status {status}: {msg}")
@@ -92,6 +120,40 @@ _PROTOS = {
                              ctypes.POINTER(gsr_config), c_void_p, ctypes.POINTER(c_void_p)]),
     "gsr_backward": (c_int32, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(gsr_grads), c_int32,
                                ctypes.POINTER(gsr_config)]),
+    "gsr_render_batch": (c_int32, [c_void_p, c_int32, ctypes.POINTER(gsr_scene), ctypes.POINTER(gsr_camera),
+                                   ctypes.POINTER(gsr_config), ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p)]),
+    "gsr_backward_batch": (c_int32, [c_void_p, c_int32, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p),
+                                     ctypes.POINTER(gsr_grads), c_int32, ctypes.POINTER(gsr_config)]),
+    "gsr_graph_capture_backward": (c_int32, [c_void_p, c_int32, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p),
+                                             ctypes.POINTER(gsr_grads), c_int32, ctypes.POINTER(gsr_config),
+                                             ctypes.POINTER(c_void_p)]),
+    "gsr_graph_launch": (c_int32, [c_void_p, c_void_p]),
+    "gsr_graph_destroy": (None, [c_void_p, c_void_p]),
+    "gsr_autotune": (c_int32, [c_void_p, c_int32, ctypes.POINTER(gsr_scene), ctypes.POINTER(gsr_camera),
+                               ctypes.POINTER(c_void_p), ctypes.POINTER(gsr_tune_space), ctypes.POINTER(gsr_config),
+                               ctypes.POINTER(gsr_tune_entry), c_int32, ctypes.POINTER(c_int32)]),
+    "gsr_tuner_create": (c_int32, [ctypes.POINTER(gsr_tune_space), c_int32, ctypes.POINTER(c_void_p)]),
+    "gsr_tuner_next": (c_int32, [c_void_p, c_void_p, c_int32, ctypes.POINTER(gsr_scene), ctypes.POINTER(gsr_camera),
+                                 ctypes.POINTER(c_void_p), ctypes.POINTER(gsr_config), ctypes.POINTER(c_int32)]),
+    "gsr_tuner_destroy": (None, [c_void_p]),
+    "gsr_server_scene_bytes": (c_int64, [c_int64, c_int32]),
+    "gsr_server_create": (c_int32, [c_int32, ctypes.POINTER(gsr_server_opts), ctypes.POINTER(c_void_p)]),
+    "gsr_server_destroy": (None, [c_void_p]),
+    "gsr_server_last_error": (ctypes.c_char_p, [c_void_p]),
+    "gsr_server_now": (ctypes.c_double, [c_void_p]),
+    "gsr_server_add_scene": (c_int32, [c_void_p, ctypes.POINTER(gsr_scene), ctypes.POINTER(c_int32)]),
+    "gsr_server_remove_scene": (c_int32, [c_void_p, c_int32]),
+    "gsr_server_scene_state": (c_int32, [c_void_p, c_int32, ctypes.POINTER(gsr_scene), ctypes.POINTER(gsr_grads),
+                                         ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p), ctypes.POINTER(c_int32)]),
+    "gsr_server_set_step": (c_int32, [c_void_p, c_int32, c_int32]),
+    "gsr_server_scene_io": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_int32]),
+    "gsr_server_submit": (c_int32, [c_void_p, ctypes.POINTER(gsr_request), ctypes.POINTER(c_int64)]),
+    "gsr_server_replay": (c_int32, [c_void_p, c_int32, ctypes.POINTER(gsr_request), ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(c_int64)]),
+    "gsr_server_drain": (c_int32, [c_void_p]),
+    "gsr_server_results": (c_int32, [c_void_p, ctypes.POINTER(gsr_result), c_int32, ctypes.POINTER(c_int32)]),
+    "gsr_l1_dssim_grad": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, ctypes.c_float, c_void_p,
+                                    c_void_p]),
     "gsr_backward_composite": (c_int32, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(gsr_config)]),
     "gsr_backward_params": (c_int32, [c_void_p, c_void_p, ctypes.POINTER(gsr_grads), c_int32]),
     "gsr_fwd_release": (c_int32, [c_void_p, c_void_p]),
@@ -206,6 +268,188 @@ def gsr_backward(ctx, state, dl_dimage, grads: gsr_grads, accumulate: int = 0, c
                                     ctypes.byref(cfg) if cfg is not None else None))
 
 
+def gsr_render_batch(ctx, scenes, cams, cfg: gsr_config, images):
+    """Render len(scenes) views in one call; returns the list of their states."""
+    n = len(scenes)
+    states = (c_void_p * n)()
+    _check(ctx, load().gsr_render_batch(ctx, n, (gsr_scene * n)(*scenes), (gsr_camera * n)(*cams),
+                                        ctypes.byref(cfg), (c_void_p * n)(*[im.data_ptr() for im in images]),
+                                        states))
+    return [c_void_p(s) for s in states]
+
+
+def gsr_backward_batch(ctx, states, dl_dimages, grads, accumulate: int = 0, cfg: gsr_config | None = None):
+    n = len(states)
+    _check(ctx, load().gsr_backward_batch(ctx, n, (c_void_p * n)(*[s.value for s in states]),
+                                          (c_void_p * n)(*[d.data_ptr() for d in dl_dimages]),
+                                          (gsr_grads * n)(*grads), int(accumulate),
+                                          ctypes.byref(cfg) if cfg is not None else None))
+
+
+def gsr_graph_capture_backward(ctx, states, dl_dimages, grads, accumulate: int = 0, cfg: gsr_config | None = None):
+    n = len(states)
+    graph = c_void_p()
+    _check(ctx, load().gsr_graph_capture_backward(ctx, n, (c_void_p * n)(*[s.value for s in states]),
+                                                  (c_void_p * n)(*[d.data_ptr() for d in dl_dimages]),
+                                                  (gsr_grads * n)(*grads), int(accumulate),
+                                                  ctypes.byref(cfg) if cfg is not None else None,
+                                                  ctypes.byref(graph)))
+    return graph
+
+
+def gsr_graph_launch(ctx, graph):
+    _check(ctx, load().gsr_graph_launch(ctx, graph))
+
+
+def gsr_graph_destroy(ctx, graph):
+    load().gsr_graph_destroy(ctx, graph)
+
+
+def make_tune_space(tiles=(8, 16, 32), batches=(64, 128, 256), thresholds=(8, 16, 24, 32, 48, 64), reps=3,
+                    flags=0) -> gsr_tune_space:
+    sp = gsr_tune_space()
+    sp.n_tiles, sp.n_batches, sp.n_thresholds = len(tiles), len(batches), len(thresholds)
+    for i, v in enumerate(tiles):
+        sp.tiles[i] = v
+    for i, v in enumerate(batches):
+        sp.batches[i] = v
+    for i, v in enumerate(thresholds):
+        sp.thresholds[i] = v
+    sp.reps, sp.flags = reps, flags
+    return sp
+
+
+def _dl_array(n, dl_dimages):
+    if dl_dimages is None:
+        return None
+    return (c_void_p * n)(*[None if d is None else d.data_ptr() for d in dl_dimages])
+
+
+def gsr_autotune(ctx, scenes, cams, space: gsr_tune_space, dl_dimages=None, max_entries=64):
+    """Returns (best config, list of gsr_tune_entry)."""
+    n = len(scenes)
+    best = gsr_config()
+    entries = (gsr_tune_entry * max_entries)()
+    count = c_int32()
+    _check(ctx, load().gsr_autotune(ctx, n, (gsr_scene * n)(*scenes), (gsr_camera * n)(*cams),
+                                    _dl_array(n, dl_dimages), ctypes.byref(space), ctypes.byref(best), entries,
+                                    max_entries, ctypes.byref(count)))
+    return best, list(entries[: count.value])
+
+
+def gsr_tuner_create(space: gsr_tune_space, every: int):
+    t = c_void_p()
+    st = load().gsr_tuner_create(ctypes.byref(space), int(every), ctypes.byref(t))
+    if st != GSR_OK:
+        raise GsrError(st, "gsr_tuner_create: invalid space or period")
+    return t
+
+
+def gsr_tuner_next(ctx, tuner, scenes, cams, dl_dimages=None):
+    """Returns (config for this iteration, whether it re-tuned)."""
+    n = len(scenes)
+    cfg = gsr_config()
+    did = c_int32()
+    _check(ctx, load().gsr_tuner_next(ctx, tuner, n, (gsr_scene * n)(*scenes), (gsr_camera * n)(*cams),
+                                      _dl_array(n, dl_dimages), ctypes.byref(cfg), ctypes.byref(did)))
+    return cfg, bool(did.value)
+
+
+def gsr_tuner_destroy(tuner):
+    load().gsr_tuner_destroy(tuner)
+
+
+# ---------------------------------------------------------------- serving
+
+def _scheck(server, status):
+    if status != GSR_OK:
+        msg = _lib.gsr_server_last_error(server).decode() if server else ""
+        raise GsrError(status, msg)
+
+
+def make_server_opts(budget_bytes, max_batch=16, lanes=2, config=None, lr=1e-3, beta1=0.9, beta2=0.999,
+                     eps=1e-15) -> gsr_server_opts:
+    return gsr_server_opts(int(budget_bytes), max_batch, lanes, config if config is not None else make_config(),
+                           lr, beta1, beta2, eps)
+
+
+def gsr_server_scene_bytes(n: int, sh_degree: int) -> int:
+    return int(load().gsr_server_scene_bytes(n, sh_degree))
+
+
+def gsr_server_create(opts: gsr_server_opts, device: int = 0):
+    srv = c_void_p()
+    st = load().gsr_server_create(device, ctypes.byref(opts), ctypes.byref(srv))
+    if st != GSR_OK:
+        raise GsrError(st, "gsr_server_create failed")
+    return srv
+
+
+def gsr_server_destroy(server):
+    load().gsr_server_destroy(server)
+
+
+def gsr_server_now(server) -> float:
+    return float(load().gsr_server_now(server))
+
+
+def gsr_server_add_scene(server, scene: gsr_scene) -> int:
+    sid = c_int32()
+    _scheck(server, load().gsr_server_add_scene(server, ctypes.byref(scene), ctypes.byref(sid)))
+    return sid.value
+
+
+def gsr_server_remove_scene(server, sid: int):
+    _scheck(server, load().gsr_server_remove_scene(server, sid))
+
+
+def gsr_server_scene_state(server, sid: int):
+    """Returns (params gsr_scene, grads gsr_grads, adam_m ptr, adam_v ptr, step)."""
+    p, g, m, v, step = gsr_scene(), gsr_grads(), c_void_p(), c_void_p(), c_int32()
+    _scheck(server, load().gsr_server_scene_state(server, sid, ctypes.byref(p), ctypes.byref(g), ctypes.byref(m),
+                                                  ctypes.byref(v), ctypes.byref(step)))
+    return p, g, m.value, v.value, step.value
+
+
+def gsr_server_set_step(server, sid: int, step: int):
+    _scheck(server, load().gsr_server_set_step(server, sid, step))
+
+
+SCENE_BLOCKS = ("params", "grads", "adam_m", "adam_v")
+
+
+def gsr_server_scene_io(server, sid: int, block: str, host: np.ndarray, to_host: bool):
+    """Copy a scene's flat block to/from the contiguous fp32 numpy array `host`."""
+    assert host.dtype == np.float32 and host.flags.c_contiguous
+    _scheck(server, load().gsr_server_scene_io(server, sid, SCENE_BLOCKS.index(block),
+                                               host.ctypes.data_as(c_void_p), 1 if to_host else 0))
+
+
+def gsr_server_submit(server, req: gsr_request) -> int:
+    rid = c_int64()
+    _scheck(server, load().gsr_server_submit(server, ctypes.byref(req), ctypes.byref(rid)))
+    return rid.value
+
+
+def gsr_server_replay(server, reqs, arrival_s):
+    n = len(reqs)
+    ids = (c_int64 * n)()
+    _scheck(server, load().gsr_server_replay(server, n, (gsr_request * n)(*reqs),
+                                             (ctypes.c_double * n)(*[float(t) for t in arrival_s]), ids))
+    return list(ids)
+
+
+def gsr_server_drain(server):
+    _scheck(server, load().gsr_server_drain(server))
+
+
+def gsr_server_results(server, max_results: int = 4096):
+    out = (gsr_result * max_results)()
+    n = c_int32()
+    _scheck(server, load().gsr_server_results(server, out, max_results, ctypes.byref(n)))
+    return list(out[: n.value])
+
+
 def gsr_backward_composite(ctx, state, dl_dimage, cfg: gsr_config | None = None):
     _check(ctx, load().gsr_backward_composite(ctx, state, _ptr(dl_dimage),
                                               ctypes.byref(cfg) if cfg is not None else None))
@@ -248,6 +492,12 @@ def gsr_ctx_stage_times(ctx) -> gsr_stage_times_t:
 
 def gsr_l1_grad(ctx, image, target, dl_dimage):
     _check(ctx, load().gsr_l1_grad(ctx, _ptr(image), _ptr(target), int(image.numel()), _ptr(dl_dimage)))
+
+
+def gsr_l1_dssim_grad(ctx, image, target, dl_dimage, lam: float = 0.2, loss=None):
+    _, h, w = image.shape
+    _check(ctx, load().gsr_l1_dssim_grad(ctx, _ptr(image), _ptr(target), h, w, float(lam), _ptr(dl_dimage),
+                                         _ptr(loss)))
 
 
 def gsr_wave_reduce_selftest(ctx, vals, active, mode, threshold, lane_split, sums, lane_atomics):

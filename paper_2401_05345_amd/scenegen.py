@@ -219,8 +219,97 @@ def single_gaussian_at_pixel(px: int, py: int, width=32, height=32, log_scale=-2
     return Workload("single", sc, cam, 16)
 
 
+@dataclass
+class MultiView:
+    """Several scenes, each seen by several cameras: views[i] = (scene index, camera, target)."""
+    name: str
+    scenes: list
+    views: list
+    loss: str = "l1"
+
+
+C4_RESOLUTIONS = ((512, 512), (800, 800), (1280, 720), (1600, 1200), (1920, 1080))
+
+
+def multi_view(seed: int = 4, sizes=(50_000, 200_000, 500_000, 1_500_000), views_per_scene: int = 4,
+               resolutions=C4_RESOLUTIONS, sh_degree: int = 3, radius: float = 4.0) -> MultiView:
+    """Scenes of uneven size (clustered in [-2,2]^3 like object_100k), each seen from
+    `views_per_scene` eyes drawn uniformly on the sphere of `radius`, each view at a
+    resolution drawn uniformly from `resolutions`; targets U(0,1), L1. The defaults are
+    the 16-view, four-scene batch workload."""
+    rng = np.random.default_rng(seed)
+    scenes = [random_scene(rng, n, means="clustered", half=2.0, log_scale=(-4.0, 0.5), opacity=(0.0, 1.0),
+                           sh_degree=sh_degree, sh_rest_sigma=0.1) for n in sizes]
+    views = []
+    for si in range(len(scenes)):
+        for _ in range(views_per_scene):
+            w, h = resolutions[int(rng.integers(len(resolutions)))]
+            g = rng.standard_normal(3)
+            cam = make_camera(w, h, radius * g / np.linalg.norm(g))
+            views.append((si, cam, rng.uniform(0.0, 1.0, size=(3, h, w)).astype(F32)))
+    tag = "_".join(f"{n // 1000}k" if n >= 1000 else str(n) for n in sizes)
+    return MultiView(f"multi_view_{len(views)}v_{tag}", scenes, views)
+
+
+def multi_view_small(seed: int = 5) -> MultiView:
+    """A small instance of the batch workload for parity against the oracle: four scenes of
+    uneven size (one empty), two views each, ragged resolutions."""
+    return multi_view(seed, sizes=(600, 2500, 6000, 0), views_per_scene=2,
+                      resolutions=((64, 64), (100, 75), (128, 72), (160, 120)), radius=4.0)
+
+
 WORKLOADS = {
     "tiny_1k": tiny_1k,
     "object_100k": object_100k,
     "large_3m": large_3m,
 }
+
+
+# ---------------------------------------------------------------- device-drawn targets
+
+_GOLDEN_GAMMA = np.uint64(0x9E3779B97F4A7C15)
+
+
+def splitmix64(seed: int, index: np.ndarray) -> np.ndarray:
+    """SplitMix64 (Steele, Lea and Flood, 2014): output number index+1 of the generator
+    started at `seed` (state seed + (index+1) * golden gamma, then the variant-13 mix)."""
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + (index.astype(np.uint64) + np.uint64(1)) * _GOLDEN_GAMMA
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def request_target(seed: int, height: int, width: int) -> np.ndarray:
+    """The [3,H,W] U[0,1) target a serving request draws on the device: value i is the top 24
+    bits of SplitMix64 output i, times 2^-24."""
+    i = np.arange(3 * height * width, dtype=np.uint64)
+    return ((splitmix64(seed, i) >> np.uint64(40)).astype(np.float32) * np.float32(2.0 ** -24)).reshape(
+        3, height, width)
+
+
+def serving_scenes(seed: int = 6, count: int = 10, n_min: int = 100_000, n_max: int = 2_000_000,
+                   sh_degree: int = 3) -> list:
+    """Resident scenes of the serving stream: sizes log-uniform in [n_min, n_max], clustered
+    in [-2,2]^3 like object_100k."""
+    rng = np.random.default_rng(seed)
+    sizes = np.exp(rng.uniform(np.log(n_min), np.log(n_max), size=count)).astype(np.int64)
+    return [random_scene(rng, int(n), means="clustered", half=2.0, log_scale=(-4.0, 0.5), opacity=(0.0, 1.0),
+                         sh_degree=sh_degree, sh_rest_sigma=0.1) for n in sizes]
+
+
+def serving_requests(seed: int, n_scenes: int, count: int, rate_hz: float, resolutions=C4_RESOLUTIONS,
+                     radius: float = 4.0):
+    """Poisson arrivals at rate_hz: (arrival seconds, scene index, Camera, target seed) per
+    request, each with a uniform scene, a random eye on the sphere and a resolution drawn
+    uniformly from `resolutions`."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate_hz, size=count))
+    out = []
+    for k in range(count):
+        si = int(rng.integers(n_scenes))
+        w, h = resolutions[int(rng.integers(len(resolutions)))]
+        g = rng.standard_normal(3)
+        cam = make_camera(w, h, radius * g / np.linalg.norm(g))
+        out.append((float(t[k]), si, cam, int(rng.integers(0, 2 ** 63))))
+    return out

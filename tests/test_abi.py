@@ -32,9 +32,10 @@ def lib():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for must in ("gsr_ctx_create", "gsr_render", "gsr_backward", "gsr_fwd_release", "gsr_validate_scene",
-                 "gsr_wave_reduce_selftest", "gsr_fwd_export", "gsr_bwd_counters"):
+                 "gsr_wave_reduce_selftest", "gsr_fwd_export", "gsr_bwd_counters", "gsr_render_batch",
+                 "gsr_backward_batch"):
         assert must in names
-    assert len(names) >= 19
+    assert len(names) >= 21
 
 
 def test_library_exports_every_declared_symbol(lib):
@@ -88,7 +89,10 @@ def test_validate_config_modes_and_thresholds(lib):
         assert gsr.gsr_validate_config(gsr.make_config(reduce_threshold=thr)) == gsr.GSR_OK
     for thr in (-1, 66):
         assert gsr.gsr_validate_config(gsr.make_config(reduce_threshold=thr)) == gsr.GSR_EINVAL
-    assert gsr.gsr_validate_config(gsr.make_config(bwd_mode=2)) == gsr.GSR_EINVAL
+    for mode in (0, 1, 2, 3):
+        assert gsr.gsr_validate_config(gsr.make_config(bwd_mode=mode)) == gsr.GSR_OK
+    for mode in (-1, 4):
+        assert gsr.gsr_validate_config(gsr.make_config(bwd_mode=mode)) == gsr.GSR_EINVAL
     assert gsr.gsr_validate_config(gsr.make_config(flags=1 << 10)) == gsr.GSR_EINVAL
 
 
@@ -99,3 +103,21 @@ def test_ctx_create_without_gpu_reports_error(lib):
     out = ctypes.c_void_p()
     st = lib.gsr_ctx_create(ctypes.byref(out), 0, None)
     assert st != gsr.GSR_OK and not out.value
+
+
+def test_server_scene_bytes(lib):
+    # params, gradients and the two Adam moments: 4 x (3+3+4+1+3K) floats per Gaussian
+    assert gsr.gsr_server_scene_bytes(1000, 3) == 1000 * 944
+    assert gsr.gsr_server_scene_bytes(10, 0) == 10 * 4 * 14 * 4
+    assert gsr.gsr_server_scene_bytes(-1, 0) == -1 and gsr.gsr_server_scene_bytes(5, 4) == -1
+
+
+def test_server_rejects_bad_options_without_device(lib):
+    # option checks run before any device call
+    for bad in (dict(max_batch=0), dict(max_batch=17), dict(lanes=0), dict(lanes=5), dict(lr=0.0),
+                dict(beta1=1.0), dict(eps=-1.0)):
+        kw = dict(max_batch=4, lanes=2, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-15)
+        kw.update(bad)
+        opts = gsr.make_server_opts(1 << 30, **kw)
+        with pytest.raises(gsr.GsrError):
+            gsr.gsr_server_create(opts)

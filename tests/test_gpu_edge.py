@@ -140,8 +140,8 @@ def test_wave_reduce_primitive_sums_and_atomic_counts(renderer, split):
     sums = torch.zeros(9, device="cuda:0")
     cnt = torch.zeros(1, dtype=torch.int64, device="cuda:0")
     scale = np.abs(vals).sum() / 9
-    for mode in (gsr.GSR_BWD_PLAIN_ATOMIC, gsr.GSR_BWD_WAVE_REDUCE):
-        for thr in (range(0, 66) if mode == gsr.GSR_BWD_WAVE_REDUCE else [0]):
+    for mode in (gsr.GSR_BWD_PLAIN_ATOMIC, gsr.GSR_BWD_WAVE_REDUCE, gsr.GSR_BWD_SERIAL_REDUCE):
+        for thr in (range(0, 66) if mode != gsr.GSR_BWD_PLAIN_ATOMIC else [0]):
             gsr.gsr_wave_reduce_selftest(renderer.ctx, dv, da, mode, thr, split, sums, cnt)
             torch.cuda.synchronize()
             got = sums.cpu().numpy().astype(np.float64)
@@ -160,7 +160,9 @@ def test_backward_counters_match_the_atomic_count_model(renderer):
     dl = np.random.default_rng(1).standard_normal((3, cam.height, cam.width)).astype(np.float32)
     for mode, thr, flags in [(gsr.GSR_BWD_PLAIN_ATOMIC, 0, 0), (gsr.GSR_BWD_WAVE_REDUCE, 1, 0),
                              (gsr.GSR_BWD_WAVE_REDUCE, 24, 0), (gsr.GSR_BWD_WAVE_REDUCE, 65, 0),
-                             (gsr.GSR_BWD_WAVE_REDUCE, 16, gsr.GSR_FLAG_LANE_SPLIT_ATOMICS)]:
+                             (gsr.GSR_BWD_WAVE_REDUCE, 16, gsr.GSR_FLAG_LANE_SPLIT_ATOMICS),
+                             (gsr.GSR_BWD_SERIAL_REDUCE, 8, 0), (gsr.GSR_BWD_BLOCK_REDUCE, 1, 0),
+                             (gsr.GSR_BWD_BLOCK_REDUCE, 24, 0)]:
         cfg = gsr.make_config(16, 256, mode, thr, gsr.GSR_FLAG_DEBUG_COUNTERS | flags)
         st, out = run_render(renderer, gs, cfg)
         try:
@@ -180,10 +182,20 @@ def test_backward_counters_match_the_atomic_count_model(renderer):
             if mode == gsr.GSR_BWD_PLAIN_ATOMIC:
                 assert c.reduced == 0 and c.plain_lanes == c.active
                 assert c.lane_atomics == 9 * c.active and c.atomic_instrs == 9 * c.wave_entries
+            elif mode == gsr.GSR_BWD_BLOCK_REDUCE:
+                # reduced waves add into LDS; each (tile, Gaussian) touched by at least one of
+                # them is flushed once: between a quarter of the reduced wave-entries (four
+                # waves per 16x16 tile) and all of them.
+                assert c.reduced == hist[t:].sum()
+                assert c.plain_lanes == (hist[1:t] * lanes[1:t]).sum()
+                flush = int(c.lane_atomics) - 9 * int(c.plain_lanes)
+                assert flush % 9 == 0 and -(-int(c.reduced) // 4) <= flush // 9 <= int(c.reduced)
+                flush_instrs = int(c.atomic_instrs) - 9 * int(c.wave_entries - c.reduced)
+                assert -(-flush // 64) <= flush_instrs <= flush
             else:
                 assert c.reduced == hist[t:].sum()
                 assert c.plain_lanes == (hist[1:t] * lanes[1:t]).sum()
-                per = 1 if flags else 9
+                per = 1 if (flags or mode == gsr.GSR_BWD_SERIAL_REDUCE) else 9
                 assert c.lane_atomics == 9 * c.reduced + 9 * c.plain_lanes
                 assert c.atomic_instrs == per * c.reduced + 9 * (c.wave_entries - c.reduced)
             say(f"[gpu] counters mode={mode} thr={thr}: E={c.evaluated} A={c.active} WE={c.wave_entries} "

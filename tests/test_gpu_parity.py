@@ -98,6 +98,10 @@ def _workload_tiny():
     (gsr.GSR_BWD_WAVE_REDUCE, 65, 0),
     (gsr.GSR_BWD_WAVE_REDUCE, 8, gsr.GSR_FLAG_LANE_SPLIT_ATOMICS),
     (gsr.GSR_BWD_WAVE_REDUCE, 16, gsr.GSR_FLAG_XCD_REMAP),
+    (gsr.GSR_BWD_SERIAL_REDUCE, 1, 0),
+    (gsr.GSR_BWD_SERIAL_REDUCE, 24, 0),
+    (gsr.GSR_BWD_BLOCK_REDUCE, 1, 0),
+    (gsr.GSR_BWD_BLOCK_REDUCE, 32, 0),
 ])
 def test_tiny_parity(renderer, mode, thr, flags):
     say(f"[gpu] tiny_1k parity mode={mode} thr={thr} flags={flags}")
@@ -126,7 +130,8 @@ def test_tiles_and_batches_ragged_image(renderer, tile, batch):
     dl = oracle_dl_dimage(rr, wl.target, "l1")
     acc_ref, grads_ref = oracle.backward(wl.scene, rr, dl.astype(np.float64))
     gs = GpuScene(wl.scene, cam)
-    for mode in (gsr.GSR_BWD_PLAIN_ATOMIC, gsr.GSR_BWD_WAVE_REDUCE):
+    for mode in (gsr.GSR_BWD_PLAIN_ATOMIC, gsr.GSR_BWD_WAVE_REDUCE, gsr.GSR_BWD_SERIAL_REDUCE,
+                 gsr.GSR_BWD_BLOCK_REDUCE):
         cfg = gsr.make_config(tile, batch, mode, 24, 0)
         st, out = run_render(renderer, gs, cfg)
         try:
@@ -175,7 +180,8 @@ def test_object_100k_parity_and_modes(renderer):
         img_err, ties = _check_forward(out, rr, 16)
         say(f"[gpu] object_100k image rel-L2 {img_err:.3e}, tie pixels {ties.sum()}")
         for mode, thr, flags in [(gsr.GSR_BWD_WAVE_REDUCE, 32, 0), (gsr.GSR_BWD_PLAIN_ATOMIC, 0, 0),
-                                 (gsr.GSR_BWD_WAVE_REDUCE, 1, gsr.GSR_FLAG_LANE_SPLIT_ATOMICS)]:
+                                 (gsr.GSR_BWD_WAVE_REDUCE, 1, gsr.GSR_FLAG_LANE_SPLIT_ATOMICS),
+                                 (gsr.GSR_BWD_SERIAL_REDUCE, 1, 0), (gsr.GSR_BWD_BLOCK_REDUCE, 1, 0)]:
             grads, acc, _ = run_backward(renderer, gs, st, dl, gsr.make_config(16, 256, mode, thr, flags))
             errs = _check_grads(grads, acc, acc_ref, grads_ref)
             say(f"[gpu] object_100k mode={mode} thr={thr} grad rel-L2 {errs}")
