@@ -47,6 +47,9 @@ BYTES_PER_PIXEL = 20              # dL/dI (12) + T_final (4) + n_contrib (4)
 BYTES_PER_VISIBLE = 2 * 36        # accumulators written back once (zero-fill excluded) and read by a7
 
 
+MODES = {"reduce": 1, "plain": 0, "serial": 2, "block": 3}   # gsr_bwd_mode values
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -61,7 +64,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--threshold", type=int, default=None, help="fix the threshold (skip the sweep)")
     p.add_argument("--profile-only", action="store_true", help="only the timed steps (for rocprofv3 runs)")
-    p.add_argument("--mode", default="reduce", choices=["reduce", "plain"], help="backward mode of --profile-only")
+    p.add_argument("--mode", default="reduce", choices=list(MODES), help="backward mode of --profile-only")
     p.add_argument("--no-lane-split", action="store_true",
                    help="reduced sums issued by one lane (default: lanes 0..8, one instruction)")
     p.add_argument("--no-batch", action="store_true", help="skip the 16-view batched leg")
@@ -158,9 +161,10 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel_hash):
-    """HBM bytes per launch of the backward composite from committed rocprofv3 counter runs,
-    or None when the kernel changed since they were taken."""
+def measured_traffic(kernel_hash, workload):
+    """HBM bytes per launch of the backward composite from committed rocprofv3 counter runs
+    (FETCH_SIZE and WRITE_SIZE scaled by the copy calibration), or None when the kernel changed
+    since they were taken."""
     path = os.path.join(ROOT, "profiles", "composite_bwd_traffic.json")
     if not os.path.exists(path):
         return None
@@ -168,7 +172,9 @@ def measured_traffic(kernel_hash):
         d = json.load(f)
     if d.get("kernel_source_hash") != kernel_hash:
         return None
-    return d.get("bytes_per_launch")
+    key = "object" if workload.startswith("object") else "large"
+    w = d.get("workloads", {}).get(key)
+    return w.get("bytes_per_launch") if w else None
 
 
 def timed_ms(torch, fn, reps):
@@ -399,7 +405,7 @@ def main():
         # Profiled runs launch only the configuration they measure.
         thr = args.threshold if args.threshold is not None else 32
 
-    cfg_r = b.cfg(gsr.GSR_BWD_WAVE_REDUCE if args.mode == "reduce" else gsr.GSR_BWD_PLAIN_ATOMIC, thr)
+    cfg_r = b.cfg(MODES[args.mode], thr)
     for _ in range(args.warmup):
         b.step(cfg_r)
     torch.cuda.synchronize()
@@ -424,8 +430,11 @@ def main():
     iters = max(10, args.steps)
     p6, p7 = b.backward_only(fr, b.cfg(gsr.GSR_BWD_PLAIN_ATOMIC, 0), iters)
     r6, r7 = b.backward_only(fr, cfg_r, iters)
+    s6, _ = b.backward_only(fr, b.cfg(gsr.GSR_BWD_SERIAL_REDUCE, thr), iters)
+    k6, _ = b.backward_only(fr, b.cfg(gsr.GSR_BWD_BLOCK_REDUCE, thr), iters)
     cp = b.counters(fr, gsr.GSR_BWD_PLAIN_ATOMIC, 0)
     cr = b.counters(fr, gsr.GSR_BWD_WAVE_REDUCE, thr)
+    ck = b.counters(fr, gsr.GSR_BWD_BLOCK_REDUCE, thr)
     b.r.release(fr)
     log(f"[bench] A/B a6: plain {np.median(p6):.3f} ms, reduce {np.median(r6):.3f} ms")
 
@@ -439,7 +448,7 @@ def main():
     hw = wl.camera.width * wl.camera.height
     alg_bytes = BYTES_PER_PIXEL * hw + BYTES_PER_VISIBLE * n_vis + BYTES_PER_RECORD * int(stats.n_pairs)
     khash = source_hash()
-    traffic = measured_traffic(khash)
+    traffic = measured_traffic(khash, wl.name)
     roofline = {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": PEAK_FP32_VALU_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_FP32_VALU_TFLOPS, 4),
                 "traffic": traffic, "kernel": "composite_bwd_kernel<16,256,wave_reduce>",
@@ -478,6 +487,11 @@ def main():
             "evaluated_E": int(cr.evaluated), "active_A": int(cr.active), "wave_entries": int(cr.wave_entries),
             "reduced_W_R": int(cr.reduced), "plain_lanes_A_lt": int(cr.plain_lanes),
             "threshold_sweep_ms": sweep,
+            "composite_bwd_by_mode_ms": {"wave_reduce": round(float(np.median(r6)), 4),
+                                         "serial_leader": round(float(np.median(s6)), 4),
+                                         "block_lds": round(float(np.median(k6)), 4),
+                                         "plain_atomic": round(float(np.median(p6)), 4)},
+            "lane_atomics_block_lds": int(ck.lane_atomics), "atomic_instrs_block_lds": int(ck.atomic_instrs),
         },
         "forward_ms": round(float(fwd.mean()), 4),
         "p99_step_ms": None,
@@ -507,12 +521,21 @@ def main():
         b3.r.release(fr3)
         b3.r.close()
 
+    # The extra legs report their own failure instead of losing the line.
     if not args.no_batch and not args.profile_only:
-        out["multi_view_16"] = bench_multi_view(Bench.extra_flags)
+        try:
+            out["multi_view_16"] = bench_multi_view(Bench.extra_flags)
+        except Exception as e:  # noqa: BLE001
+            log(f"[bench] multi-view leg failed: {e!r}")
+            out["multi_view_16"] = {"error": repr(e)}
 
     if not args.no_serve and not args.profile_only:
-        out["serving"] = bench_serving(Bench.extra_flags, args.serve_seconds)
-        out["p99_step_ms"] = out["serving"]["rates"]["200"]["batched_reduce"]["p99_ms"]
+        try:
+            out["serving"] = bench_serving(Bench.extra_flags, args.serve_seconds)
+            out["p99_step_ms"] = out["serving"]["rates"]["200"]["batched_reduce"]["p99_ms"]
+        except Exception as e:  # noqa: BLE001
+            log(f"[bench] serving leg failed: {e!r}")
+            out["serving"] = {"error": repr(e)}
 
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")

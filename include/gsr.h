@@ -58,7 +58,10 @@ enum {
     GSR_FLAG_XCD_REMAP = 2,      /* composite kernels map consecutive blocks of one XCD to neighbouring tiles */
     GSR_FLAG_STAGE_TIMING = 4,   /* record HIP events around each stage (gsr_ctx_stage_times) */
     GSR_FLAG_LANE_SPLIT_ATOMICS = 8, /* reduce path: lanes 0..8 each issue one of the 9 sums in one instruction */
-    GSR_FLAG_NO_TILE_ORDER = 16      /* launch tiles in index order instead of longest-work first */
+    GSR_FLAG_NO_TILE_ORDER = 16,     /* launch tiles in index order instead of longest-work first */
+    GSR_FLAG_ACC_F64 = 32            /* backward accumulators in fp64: per-wave sums stay fp32, each value is
+                                        one fp64 atomic add (plain and wave-reduce modes; the reduced
+                                        sums are issued by lanes 0..8). Removes fp32 atomic-order noise. */
 };
 
 /* Number of floats reserved per Gaussian in the backward accumulators:
@@ -403,6 +406,42 @@ gsr_status gsr_server_replay(gsr_server *server, int32_t n, const gsr_request *r
 gsr_status gsr_server_drain(gsr_server *server);
 /* Move up to max completed results (completion order) into out. */
 gsr_status gsr_server_results(gsr_server *server, gsr_result *out, int32_t max, int32_t *n);
+
+/* Capacity mode: re-render n_views (1..GSR_MAX_BATCH) existing states
+ * (each state's scene arrays, read again - their contents may have changed,
+ * their sizes not - and its camera) into images_chw[i] without any host
+ * synchronisation, reusing the states' buffers. Each state's pair buffers
+ * hold pair_capacity = P + P/4 + 4096 entries of the P of the gsr_render
+ * that created it; the whole capacity is sorted, entries past the current
+ * pair count carrying a sentinel tile that sorts last. A view whose pairs
+ * exceed the capacity loses the excess and sets an overflow flag
+ * (gsr_fwd_sync). config NULL = states[0]'s render config; its tile must
+ * equal the render's. Afterwards the state's pair count is unknown on the
+ * host (gsr_fwd_stats reports -1) until gsr_fwd_sync. */
+gsr_status gsr_rerender_batch(gsr_ctx *ctx, int32_t n_views, gsr_fwd *const *states, float *const *images_chw,
+                              const gsr_config *config);
+
+/* Read back a state's pair count after capacity-mode renders or graph
+ * replays of them (synchronises; reads the device's count every time once a
+ * state has been re-rendered in capacity mode). *overflowed = 1 when the last render's pairs exceeded
+ * the capacity: its image and gradients are then incomplete, and the view
+ * must be rendered again with gsr_render. Either output may be NULL. */
+gsr_status gsr_fwd_sync(gsr_ctx *ctx, gsr_fwd *state, int64_t *n_pairs, int32_t *overflowed);
+
+/* A whole batched training step captured in a HIP graph: capacity-mode
+ * re-render of the states into images_chw, the loss gradient against
+ * targets_chw into dl_dimages_chw ((1 - loss_lambda) L1 + loss_lambda
+ * D-SSIM as gsr_l1_dssim_grad; loss_lambda = 0 is L1), and the batched
+ * backward into outs (same rules as gsr_backward_batch). Replays read the
+ * scenes' arrays, the cameras and the targets at capture time's addresses;
+ * update parameters in place between replays (e.g. an optimiser step) and
+ * check gsr_fwd_sync for overflow when the geometry changes a lot. Buffers
+ * only the replays use belong to the graph; states, images, targets,
+ * dL/dimage buffers, outputs and the context must outlive it. */
+gsr_status gsr_graph_capture_step(gsr_ctx *ctx, int32_t n_views, gsr_fwd *const *states, float *const *images_chw,
+                                  const float *const *targets_chw, float loss_lambda, float *const *dl_dimages_chw,
+                                  const gsr_grads *outs, int accumulate, const gsr_config *config,
+                                  gsr_graph **graph_out);
 
 /* Release a forward state (its buffers return to the context's pool after
  * the stream reaches this point). */

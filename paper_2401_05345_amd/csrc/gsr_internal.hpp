@@ -73,9 +73,12 @@ hipError_t launch_preprocess_fwd(const gsr_scene &s, const DevCamera &cam, float
                                  uint32_t *tiles_touched, uint32_t *depth_key, uint32_t *ids, uint8_t *clamp_mask,
                                  hipStream_t st);
 
-// a7: raw-parameter gradients from the accumulators.
-hipError_t launch_preprocess_bwd(const gsr_scene &s, const DevCamera &cam, const int32_t *radius, const float *acc,
-                                 const gsr_grads &out, int accumulate, hipStream_t st);
+// a7: raw-parameter gradients from the accumulators (float or, acc_f64, double rows).
+hipError_t launch_preprocess_bwd(const gsr_scene &s, const DevCamera &cam, const int32_t *radius, const void *acc,
+                                 bool acc_f64, const gsr_grads &out, int accumulate, hipStream_t st);
+
+// dst[i] = (float)src[i] for count values.
+hipError_t launch_f64_to_f32(const double *src, float *dst, int64_t count, hipStream_t st);
 
 // Exclusive scan of n uint32 values (in[gather[i]] when gather != nullptr).
 // total (device, may be nullptr) receives the sum. Scratch sized by scan_scratch_count.
@@ -90,12 +93,19 @@ size_t radix_hist_count(int64_t n);
 hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n, int bits,
                             uint32_t *hist, uint32_t *partials, int *which, hipStream_t st);
 
-// a2: expand each depth-ordered Gaussian into its (tile, id) pairs.
+// a2: expand each depth-ordered Gaussian into its (tile, id) pairs; pairs at positions >= cap
+// are dropped.
 hipError_t launch_emit_pairs(int64_t n, const uint32_t *sorted_ids, const uint32_t *offsets, const float4 *rec,
                              const int32_t *radius, const DevCamera &cam, uint32_t *pair_tile, uint32_t *pair_id,
-                             hipStream_t st);
+                             int64_t cap, hipStream_t st);
 
-// a4: per-tile [start, end) ranges from tile-sorted pairs (ranges zero-filled first).
+// Capacity mode: positions [*total, cap) get tile `sentinel` (>= every tile index); overflow[0]
+// = (*total > cap).
+hipError_t launch_pad_pairs(const uint32_t *total, int64_t cap, uint32_t sentinel, uint32_t *pair_tile,
+                            uint32_t *pair_id, uint32_t *overflow, hipStream_t st);
+
+// a4: per-tile [start, end) ranges from tile-sorted pairs (ranges zero-filled first; entries
+// with tile >= n_tiles are ignored).
 hipError_t launch_tile_ranges(int64_t P, const uint32_t *sorted_tile, uint2 *ranges, int64_t n_tiles, hipStream_t st);
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream_t st);
@@ -117,7 +127,7 @@ struct ViewDesc {
     uint32_t *n_contrib;
     uint32_t *tile_walk;      // optional forward output: deepest n_contrib per tile
     const float *dl_dimage;   // backward input / output
-    float *acc;
+    void *acc;                // [n][GSR_ACC_STRIDE] float or double rows
 };
 struct ViewBatch {
     ViewDesc v[kMaxViews];
@@ -141,7 +151,8 @@ struct BwdParams {
     int threshold;                // effective: reduce iff active >= threshold (>= 1)
 };
 hipError_t launch_composite_bwd(const ViewBatch &vb, int tile, int lds_batch, int remap, int mode, bool count,
-                                bool lane_split, const BwdParams &p, const uint2 *work, hipStream_t st);
+                                bool lane_split, bool acc_f64, const BwdParams &p, const uint2 *work,
+                                hipStream_t st);
 
 hipError_t launch_l1_grad(const float *image, const float *target, int64_t count, float *out, hipStream_t st);
 
@@ -190,6 +201,14 @@ struct gsr_fwd {
     uint32_t *offsets = nullptr;
     uint32_t *pair_tile = nullptr, *pair_id = nullptr, *pair_tile_alt = nullptr, *pair_id_alt = nullptr;
     uint32_t *sorted_pair_id = nullptr; // points into pair_id or pair_id_alt
+    int64_t pair_cap = 0;               // entries of each pair buffer
+    bool p_known = true;                // P and n_visible hold this render's values
+    bool overflowed = false;            // the last capacity-mode render dropped pairs
+    bool capacity_mode = false;         // re-rendered in capacity mode (counts live on the device)
+    // Scratch kept for re-renders without reallocation (capacity mode, graph capture).
+    uint32_t *totals = nullptr;         // [0] P, [1] n_visible, [2] overflow flag
+    uint32_t *dsort_hist = nullptr, *dsort_partials = nullptr, *scan_partials = nullptr;
+    uint32_t *tsort_hist = nullptr, *tsort_partials = nullptr;
     uint2 *ranges = nullptr;
     uint32_t *tile_walk = nullptr; // deepest n_contrib per tile (ordered renders)
     uint2 *order_bwd = nullptr;    // this view's tiles by decreasing walk (single-view backward)
@@ -197,7 +216,8 @@ struct gsr_fwd {
     int64_t batch_work_cap = 0;
     float *T_final = nullptr;
     uint32_t *n_contrib = nullptr;
-    float *acc = nullptr;
+    void *acc = nullptr;                // n rows of GSR_ACC_STRIDE values, room for doubles
+    bool acc_f64 = false;               // precision of the last backward composite's accumulators
     unsigned long long *counters = nullptr;
     bool counters_valid = false;
     std::vector<void *> owned; // every pool buffer of this state

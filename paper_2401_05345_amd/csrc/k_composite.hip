@@ -34,20 +34,22 @@ __host__ __device__ __forceinline__ int grid_for_tiles(int n_tiles, int remap) {
     return remap ? ((n_tiles + 7) / 8) * 8 : n_tiles;
 }
 
-__device__ __forceinline__ void atomic_add_f32(float *p, float v) { unsafeAtomicAdd(p, v); }
+// Accumulator add in the accumulator's precision (fp32 or fp64 rows).
+__device__ __forceinline__ void atomic_acc(float *p, float v) { unsafeAtomicAdd(p, v); }
+__device__ __forceinline__ void atomic_acc(double *p, float v) { unsafeAtomicAdd(p, (double)v); }
 
 // Per-wave update of the nine values of one Gaussian. Every lane of the wave
 // must call it (uniform control flow). Returns the atomic lane-operations
 // this lane issued.
-template <int MODE, bool SPLIT>
-__device__ __forceinline__ uint32_t emit9(bool active, float (&v)[9], float *dst, int threshold, int lane,
+template <int MODE, bool SPLIT, typename AccT>
+__device__ __forceinline__ uint32_t emit9(bool active, float (&v)[9], AccT *dst, int threshold, int lane,
                                           uint64_t &reduced_mask_out) {
     uint32_t issued = 0;
     reduced_mask_out = 0;
     if (MODE == GSR_BWD_PLAIN_ATOMIC) {
         if (active) {
 #pragma unroll
-            for (int k = 0; k < 9; ++k) atomic_add_f32(dst + k, v[k]);
+            for (int k = 0; k < 9; ++k) atomic_acc(dst + k, v[k]);
             issued = 9;
         }
         return issued;
@@ -73,12 +75,12 @@ __device__ __forceinline__ uint32_t emit9(bool active, float (&v)[9], float *dst
 #pragma unroll
             for (int k = 1; k < 9; ++k) mine = lane == k ? s[k] : mine;
             if (lane < 9) {
-                atomic_add_f32(dst + lane, mine);
+                atomic_acc(dst + lane, mine);
                 issued = 1;
             }
         } else if (active) {
 #pragma unroll
-            for (int k = 0; k < 9; ++k) atomic_add_f32(dst + k, v[k]);
+            for (int k = 0; k < 9; ++k) atomic_acc(dst + k, v[k]);
             issued = 9;
         }
         return issued;
@@ -88,7 +90,7 @@ __device__ __forceinline__ uint32_t emit9(bool active, float (&v)[9], float *dst
         if (SPLIT) {
             const float mine = wave_sum9_to_row_lanes(v, lane);
             if (lane < 9) {
-                atomic_add_f32(dst + lane, mine);
+                atomic_acc(dst + lane, mine);
                 issued = 1;
             }
             return issued;
@@ -97,15 +99,37 @@ __device__ __forceinline__ uint32_t emit9(bool active, float (&v)[9], float *dst
         for (int k = 0; k < 9; ++k) v[k] = wave_sum_to_lane63(v[k]);
         if (lane == 63) {
 #pragma unroll
-            for (int k = 0; k < 9; ++k) atomic_add_f32(dst + k, v[k]);
+            for (int k = 0; k < 9; ++k) atomic_acc(dst + k, v[k]);
             issued = 9;
         }
     } else if (active) {
 #pragma unroll
-        for (int k = 0; k < 9; ++k) atomic_add_f32(dst + k, v[k]);
+        for (int k = 0; k < 9; ++k) atomic_acc(dst + k, v[k]);
         issued = 9;
     }
     return issued;
+}
+
+// Entries of a staged LDS batch this wave has to visit, as wave-uniform bit
+// masks (bit j % 64 of mask[j / 64] for entry j < limit): the splat's
+// alpha >= 1/255 box (centre (u, v), half-extents in s2.zw) meets the wave's
+// 8x8 sample points (centre qc, 3.5 px half-width, plus 1 px margin). No lane
+// of the wave can pass an entry outside it. Lane l tests entries l, l+64, ...
+// so the walk loops need no per-entry test and skip culled entries with
+// scalar bit scans.
+template <int BATCH>
+__device__ __forceinline__ void wave_visit_masks(const float4 *s0, const float4 *s2, int limit, float qcx, float qcy,
+                                                 int lane, uint64_t (&mask)[BATCH / 64]) {
+#pragma unroll
+    for (int q = 0; q < BATCH / 64; ++q) {
+        const int j = q * 64 + lane;
+        bool vis = false;
+        if (j < limit) {
+            const float4 a = s0[j], c = s2[j];
+            vis = !(fabsf(a.x - qcx) > c.z + 4.5f || fabsf(a.y - qcy) > c.w + 4.5f);
+        }
+        mask[q] = __ballot(vis);
+    }
 }
 
 // The workgroup's (view, tile): from the work table, else view 0 with the
@@ -161,25 +185,29 @@ __global__ __launch_bounds__(TILE *TILE) void composite_fwd_kernel(ViewBatch vb,
         }
         __syncthreads();
         const int cnt = min(BATCH, (int)(rg.y - start));
-        for (int j = 0; j < cnt && !done; ++j) {
-            const float4 a = s0[j], c = s2[j];
-            // No sample point of this wave lies inside the splat's alpha >= 1/255 box (3.5 px half-width
-            // plus 1 px margin): every lane would skip it.
-            if (fabsf(a.x - qcx) > c.z + 4.5f || fabsf(a.y - qcy) > c.w + 4.5f) continue;
-            const float4 b = s1[j];
-            const SplatEval e = eval_splat(fpx, fpy, a.x, a.y, a.z, a.w, b.x, b.y);
-            if (!e.pass) continue;
-            const float Tn = T * (1.0f - e.alpha);
-            if (Tn < kTStop) {
-                done = true;
-                break;
+        uint64_t vis[BATCH / 64];
+        wave_visit_masks<BATCH>(s0, s2, cnt, qcx, qcy, lane, vis);
+#pragma unroll
+        for (int q = 0; q < BATCH / 64; ++q) {
+            for (uint64_t mq = vis[q]; mq && !done;) {
+                const int j = q * 64 + __builtin_ctzll(mq);
+                mq &= mq - 1;
+                const float4 a = s0[j], c = s2[j];
+                const float4 b = s1[j];
+                const SplatEval e = eval_splat(fpx, fpy, a.x, a.y, a.z, a.w, b.x, b.y);
+                if (!e.pass) continue;
+                const float Tn = T * (1.0f - e.alpha);
+                if (Tn < kTStop) {
+                    done = true;
+                    break;
+                }
+                const float w = e.alpha * T;
+                c0 = fmaf(w, b.z, c0);
+                c1 = fmaf(w, b.w, c1);
+                c2 = fmaf(w, c.x, c2);
+                T = Tn;
+                last = start - rg.x + (uint32_t)j + 1;
             }
-            const float w = e.alpha * T;
-            c0 = fmaf(w, b.z, c0);
-            c1 = fmaf(w, b.w, c1);
-            c2 = fmaf(w, c.x, c2);
-            T = Tn;
-            last = start - rg.x + (uint32_t)j + 1;
         }
     }
     if (inside) {
@@ -202,7 +230,7 @@ __global__ __launch_bounds__(TILE *TILE) void composite_fwd_kernel(ViewBatch vb,
 
 enum { CNT_EVAL = 0, CNT_ACTIVE, CNT_WAVE_ENTRIES, CNT_REDUCED, CNT_PLAIN_LANES, CNT_LANE_ATOMICS, CNT_INSTRS, CNT_HIST };
 
-template <int TILE, int BATCH, int MODE, bool COUNT, bool SPLIT>
+template <int TILE, int BATCH, int MODE, bool COUNT, bool SPLIT, typename AccT>
 __global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(ViewBatch vb, int remap,
                                                                    const uint2 *__restrict__ work, BwdParams p) {
     constexpr int QX = TILE / 8;
@@ -274,71 +302,78 @@ __global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(ViewBatch vb,
         }
         __syncthreads();
         const int jtop = min(cnt, (int)wmax - start) - 1;
-        for (int j = jtop; j >= 0; --j) {
-            const uint32_t pos = (uint32_t)(start + j + 1);
-            const float4 r0 = s0[j], r2 = s2[j];
-            // Same conservative skip as the forward: no lane of this wave can pass this entry.
-            if (fabsf(r0.x - qcx) > r2.z + 4.5f || fabsf(r0.y - qcy) > r2.w + 4.5f) continue;
-            const float4 r1 = s1[j];
-            const float rb = r2.x;
-            const SplatEval e = eval_splat(fpx, fpy, r0.x, r0.y, r0.z, r0.w, r1.x, r1.y);
-            const bool walked = pos <= nc;
-            const bool active = walked && e.pass;
-            float v[9];
+        // Entries this wave must visit (at or below its walk bound, not culled), one bit each.
+        uint64_t vis[BATCH / 64];
+        wave_visit_masks<BATCH>(s0, s2, jtop + 1, qcx, qcy, lane, vis);
 #pragma unroll
-            for (int k = 0; k < 9; ++k) v[k] = 0.0f;
-            if (active) {
-                // Transmittance in front of this entry; hardware reciprocal (1 ulp) instead of the
-                // IEEE division sequence.
-                T = T * __builtin_amdgcn_rcpf(1.0f - e.alpha);
-                const float w = e.alpha * T;
-                v[6] = w * G0;
-                v[7] = w * G1;
-                v[8] = w * G2;
-                const float dL_dalpha = T * ((r1.z - Q0) * G0 + (r1.w - Q1) * G1 + (rb - Q2) * G2);
-                Q0 = fmaf(e.alpha, r1.z - Q0, Q0);
-                Q1 = fmaf(e.alpha, r1.w - Q1, Q1);
-                Q2 = fmaf(e.alpha, rb - Q2, Q2);
-                const float dL_doG = e.raw > kAlphaMax ? 0.0f : dL_dalpha; // alpha = min(0.99, o G)
-                v[5] = e.G * dL_doG;
-                const float dL_dp = e.raw * dL_doG;
-                v[0] = dL_dp * (r0.z * e.dx + r0.w * e.dy);
-                v[1] = dL_dp * (r0.w * e.dx + r1.x * e.dy);
-                v[2] = -0.5f * dL_dp * e.dx * e.dx;
-                v[3] = -dL_dp * e.dx * e.dy;
-                v[4] = -0.5f * dL_dp * e.dy * e.dy;
-            }
-            float *dst = a.acc + (size_t)sid[j] * GSR_ACC_STRIDE;
-            uint64_t red_mask = 0;
-            if (BLOCK) {
-                const uint64_t m = __ballot(active);
-                if (__popcll(m) >= p.threshold) {
-                    red_mask = m;
-                    const float mine = wave_sum9_to_row_lanes(v, lane);
-                    if (lane < 9) atomicAdd(&s_acc[j * 9 + lane], mine);
-                    if (lane == 0) s_touch[j] = 1u;
-                } else if (active) {
-#pragma unroll
-                    for (int k = 0; k < 9; ++k) atomic_add_f32(dst + k, v[k]);
-                    issued += 9;
+        for (int q = BATCH / 64 - 1; q >= 0; --q) {
+            for (uint64_t mq = vis[q]; mq;) {
+                const int b = 63 - __builtin_clzll(mq);
+                mq ^= 1ull << b;
+                const int j = q * 64 + b;
+                const uint32_t pos = (uint32_t)(start + j + 1);
+                const float4 r0 = s0[j], r2 = s2[j];
+                const float4 r1 = s1[j];
+                const float rb = r2.x;
+                const SplatEval e = eval_splat(fpx, fpy, r0.x, r0.y, r0.z, r0.w, r1.x, r1.y);
+                const bool walked = pos <= nc;
+                const bool active = walked && e.pass;
+                float v[9];
+    #pragma unroll
+                for (int k = 0; k < 9; ++k) v[k] = 0.0f;
+                if (active) {
+                    // Transmittance in front of this entry; hardware reciprocal (1 ulp) instead of the
+                    // IEEE division sequence.
+                    T = T * __builtin_amdgcn_rcpf(1.0f - e.alpha);
+                    const float w = e.alpha * T;
+                    v[6] = w * G0;
+                    v[7] = w * G1;
+                    v[8] = w * G2;
+                    const float dL_dalpha = T * ((r1.z - Q0) * G0 + (r1.w - Q1) * G1 + (rb - Q2) * G2);
+                    Q0 = fmaf(e.alpha, r1.z - Q0, Q0);
+                    Q1 = fmaf(e.alpha, r1.w - Q1, Q1);
+                    Q2 = fmaf(e.alpha, rb - Q2, Q2);
+                    const float dL_doG = e.raw > kAlphaMax ? 0.0f : dL_dalpha; // alpha = min(0.99, o G)
+                    v[5] = e.G * dL_doG;
+                    const float dL_dp = e.raw * dL_doG;
+                    v[0] = dL_dp * (r0.z * e.dx + r0.w * e.dy);
+                    v[1] = dL_dp * (r0.w * e.dx + r1.x * e.dy);
+                    v[2] = -0.5f * dL_dp * e.dx * e.dx;
+                    v[3] = -dL_dp * e.dx * e.dy;
+                    v[4] = -0.5f * dL_dp * e.dy * e.dy;
                 }
-            } else {
-                issued += emit9<MODE, SPLIT>(active, v, dst, p.threshold, lane, red_mask);
-            }
-            if (COUNT) {
-                const uint64_t ma = __ballot(active);
-                const int ca = __popcll(ma);
-                c_active += ca;
-                if (ca) {
-                    c_we += 1;
-                    if (red_mask) {
-                        c_red += 1;
-                        c_instr += BLOCK ? 0 : ((SPLIT || MODE == GSR_BWD_SERIAL_REDUCE) ? 1 : 9);
-                    } else {
-                        c_plain += ca;
-                        c_instr += 9;
+                AccT *dst = static_cast<AccT *>(a.acc) + (size_t)sid[j] * GSR_ACC_STRIDE;
+                uint64_t red_mask = 0;
+                if (BLOCK) {
+                    const uint64_t m = __ballot(active);
+                    if (__popcll(m) >= p.threshold) {
+                        red_mask = m;
+                        const float mine = wave_sum9_to_row_lanes(v, lane);
+                        if (lane < 9) atomicAdd(&s_acc[j * 9 + lane], mine);
+                        if (lane == 0) s_touch[j] = 1u;
+                    } else if (active) {
+    #pragma unroll
+                        for (int k = 0; k < 9; ++k) atomic_acc(dst + k, v[k]);
+                        issued += 9;
                     }
-                    if (lane == 0) atomicAdd(&s_cnt[CNT_HIST + ca], 1ull);
+                } else {
+                    issued += emit9<MODE, SPLIT>(active, v, dst, p.threshold, lane, red_mask);
+                }
+                if (COUNT) {
+                    const uint64_t ma = __ballot(active);
+                    const int ca = __popcll(ma);
+                    c_active += ca;
+                    if (ca) {
+                        c_we += 1;
+                        if (red_mask) {
+                            c_red += 1;
+                            c_instr += BLOCK ? 0 : ((SPLIT || MODE == GSR_BWD_SERIAL_REDUCE) ? 1 : 9);
+                        } else {
+                            c_plain += ca;
+                            c_instr += 9;
+                        }
+                        if (lane == 0) atomicAdd(&s_cnt[CNT_HIST + ca], 1ull);
+                    }
                 }
             }
         }
@@ -350,7 +385,7 @@ __global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(ViewBatch vb,
                 const int e = i / 9;
                 const bool f = s_touch[e] != 0u;
                 if (f) {
-                    atomic_add_f32(a.acc + (size_t)sid[e] * GSR_ACC_STRIDE + (i - 9 * e), s_acc[i]);
+                    atomic_acc(static_cast<AccT *>(a.acc) + (size_t)sid[e] * GSR_ACC_STRIDE + (i - 9 * e), s_acc[i]);
                     ++issued;
                 }
                 if (COUNT && __ballot(f)) c_instr += 1;
@@ -384,7 +419,7 @@ __global__ __launch_bounds__(64) void wave_reduce_selftest_kernel(const float *v
 #pragma unroll
     for (int k = 0; k < 9; ++k) v[k] = act ? vals[i * 9 + k] : 0.0f;
     uint64_t red;
-    const uint32_t issued = emit9<MODE, SPLIT>(act, v, sums, threshold, lane, red);
+    const uint32_t issued = emit9<MODE, SPLIT, float>(act, v, sums, threshold, lane, red);
     if (issued) atomicAdd(lane_atomics, (unsigned long long)issued);
 }
 
@@ -450,27 +485,36 @@ hipError_t fwd_t(const ViewBatch &vb, int remap, const uint2 *work, hipStream_t 
 }
 
 template <int TILE, int BATCH>
-hipError_t bwd_t(const ViewBatch &vb, int remap, int mode, bool count, bool split, const BwdParams &p,
+hipError_t bwd_t(const ViewBatch &vb, int remap, int mode, bool count, bool split, bool f64, const BwdParams &p,
                  const uint2 *work, hipStream_t st) {
     const int n_tiles = vb.v[0].cam.grid_x * vb.v[0].cam.grid_y;
     const dim3 grid(work ? vb.base[vb.n] : (unsigned)grid_for_tiles(n_tiles, remap)), block(TILE * TILE);
     if (grid.x == 0) return hipSuccess;
-#define GSR_BWD(M, C, S) composite_bwd_kernel<TILE, BATCH, M, C, S><<<grid, block, 0, st>>>(vb, remap, work, p)
-    if (mode == GSR_BWD_PLAIN_ATOMIC) {
-        if (count) GSR_BWD(GSR_BWD_PLAIN_ATOMIC, true, false);
-        else GSR_BWD(GSR_BWD_PLAIN_ATOMIC, false, false);
+#define GSR_BWD(M, C, S, A) composite_bwd_kernel<TILE, BATCH, M, C, S, A><<<grid, block, 0, st>>>(vb, remap, work, p)
+    if (f64) {
+        // fp64 accumulators: plain atomics, or the butterfly with lanes 0..8 issuing.
+        if (mode == GSR_BWD_PLAIN_ATOMIC) {
+            if (count) GSR_BWD(GSR_BWD_PLAIN_ATOMIC, true, false, double);
+            else GSR_BWD(GSR_BWD_PLAIN_ATOMIC, false, false, double);
+        } else {
+            if (count) GSR_BWD(GSR_BWD_WAVE_REDUCE, true, true, double);
+            else GSR_BWD(GSR_BWD_WAVE_REDUCE, false, true, double);
+        }
+    } else if (mode == GSR_BWD_PLAIN_ATOMIC) {
+        if (count) GSR_BWD(GSR_BWD_PLAIN_ATOMIC, true, false, float);
+        else GSR_BWD(GSR_BWD_PLAIN_ATOMIC, false, false, float);
     } else if (mode == GSR_BWD_SERIAL_REDUCE) {
-        if (count) GSR_BWD(GSR_BWD_SERIAL_REDUCE, true, true);
-        else GSR_BWD(GSR_BWD_SERIAL_REDUCE, false, true);
+        if (count) GSR_BWD(GSR_BWD_SERIAL_REDUCE, true, true, float);
+        else GSR_BWD(GSR_BWD_SERIAL_REDUCE, false, true, float);
     } else if (mode == GSR_BWD_BLOCK_REDUCE) {
-        if (count) GSR_BWD(GSR_BWD_BLOCK_REDUCE, true, true);
-        else GSR_BWD(GSR_BWD_BLOCK_REDUCE, false, true);
+        if (count) GSR_BWD(GSR_BWD_BLOCK_REDUCE, true, true, float);
+        else GSR_BWD(GSR_BWD_BLOCK_REDUCE, false, true, float);
     } else if (split) {
-        if (count) GSR_BWD(GSR_BWD_WAVE_REDUCE, true, true);
-        else GSR_BWD(GSR_BWD_WAVE_REDUCE, false, true);
+        if (count) GSR_BWD(GSR_BWD_WAVE_REDUCE, true, true, float);
+        else GSR_BWD(GSR_BWD_WAVE_REDUCE, false, true, float);
     } else {
-        if (count) GSR_BWD(GSR_BWD_WAVE_REDUCE, true, false);
-        else GSR_BWD(GSR_BWD_WAVE_REDUCE, false, false);
+        if (count) GSR_BWD(GSR_BWD_WAVE_REDUCE, true, false, float);
+        else GSR_BWD(GSR_BWD_WAVE_REDUCE, false, false, float);
     }
 #undef GSR_BWD
     return hipGetLastError();
@@ -501,9 +545,10 @@ hipError_t launch_composite_fwd(const ViewBatch &vb, int t, int lds_batch, int r
 }
 
 hipError_t launch_composite_bwd(const ViewBatch &vb, int t, int lds_batch, int remap, int mode, bool count,
-                                bool lane_split, const BwdParams &p, const uint2 *work, hipStream_t st) {
+                                bool lane_split, bool acc_f64, const BwdParams &p, const uint2 *work,
+                                hipStream_t st) {
     if (vb.n <= 0 || (vb.n > 1 && !work)) return hipErrorInvalidValue;
-#define GSR_B(T, B) return bwd_t<T, B>(vb, remap, mode, count, lane_split, p, work, st)
+#define GSR_B(T, B) return bwd_t<T, B>(vb, remap, mode, count, lane_split, acc_f64, p, work, st)
     if (t == 8) GSR_B(8, 64);
     if (t == 16) {
         if (lds_batch == 64) GSR_B(16, 64);

@@ -190,24 +190,24 @@ __global__ __launch_bounds__(256) void preprocess_fwd_kernel(int n, const float 
     clamp_mask[i] = cm;
 }
 
-template <int DEG>
+template <int DEG, typename AccT>
 __device__ __forceinline__ void preprocess_bwd_one(int i, const float *__restrict__ means,
                                                    const float *__restrict__ log_scales,
                                                    const float *__restrict__ quats,
                                                    const float *__restrict__ opacity_logits,
                                                    const float *__restrict__ sh, const DevCamera &cam,
                                                    const int32_t *__restrict__ radius,
-                                                   const float *__restrict__ acc, const gsr_grads &out,
+                                                   const AccT *__restrict__ acc, const gsr_grads &out,
                                                    int accumulate, float *Ysh, float *gsh);
 
-template <int DEG>
+template <int DEG, typename AccT>
 __global__ __launch_bounds__(256) void preprocess_bwd_kernel(int n, const float *__restrict__ means,
                                                              const float *__restrict__ log_scales,
                                                              const float *__restrict__ quats,
                                                              const float *__restrict__ opacity_logits,
                                                              const float *__restrict__ sh, DevCamera cam,
                                                              const int32_t *__restrict__ radius,
-                                                             const float *__restrict__ acc, gsr_grads out,
+                                                             const AccT *__restrict__ acc, gsr_grads out,
                                                              int accumulate) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     constexpr int NS = 3 * K;      // SH gradient floats per Gaussian
@@ -221,7 +221,7 @@ __global__ __launch_bounds__(256) void preprocess_bwd_kernel(int n, const float 
 #pragma unroll
     for (int k = 0; k < K; ++k) Ysh[k] = 0.0f;
     gsh[0] = gsh[1] = gsh[2] = 0.0f;
-    if (i < n) preprocess_bwd_one<DEG>(i, means, log_scales, quats, opacity_logits, sh, cam, radius, acc, out,
+    if (i < n) preprocess_bwd_one<DEG, AccT>(i, means, log_scales, quats, opacity_logits, sh, cam, radius, acc, out,
                                        accumulate, Ysh, gsh);
     // SH gradients (Y_k * dL/drgb_c, zero for culled Gaussians) leave through LDS so that the
     // wave's 64 x 3K floats are written with consecutive lanes on consecutive addresses.
@@ -244,14 +244,14 @@ __global__ __launch_bounds__(256) void preprocess_bwd_kernel(int n, const float 
 // Everything of one Gaussian except the SH gradient, which the caller writes
 // (Y receives the basis values, g the dL/drgb passed through the clamp; both
 // stay zero for a culled Gaussian).
-template <int DEG>
+template <int DEG, typename AccT>
 __device__ __forceinline__ void preprocess_bwd_one(int i, const float *__restrict__ means,
                                                    const float *__restrict__ log_scales,
                                                    const float *__restrict__ quats,
                                                    const float *__restrict__ opacity_logits,
                                                    const float *__restrict__ sh, const DevCamera &cam,
                                                    const int32_t *__restrict__ radius,
-                                                   const float *__restrict__ acc, const gsr_grads &out,
+                                                   const AccT *__restrict__ acc, const gsr_grads &out,
                                                    int accumulate, float *Ysh, float *gsh) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     float *o_m = out.means3d + 3 * (int64_t)i;
@@ -266,9 +266,10 @@ __device__ __forceinline__ void preprocess_bwd_one(int i, const float *__restric
         }
         return;
     }
-    const float *g = acc + (int64_t)i * GSR_ACC_STRIDE;
-    const float gu = g[0], gv = g[1], gA = g[2], gB = g[3], gC = g[4], go = g[5];
-    const float grgb[3] = {g[6], g[7], g[8]};
+    const AccT *g = acc + (int64_t)i * GSR_ACC_STRIDE;
+    const float gu = (float)g[0], gv = (float)g[1], gA = (float)g[2], gB = (float)g[3], gC = (float)g[4],
+                go = (float)g[5];
+    const float grgb[3] = {(float)g[6], (float)g[7], (float)g[8]};
 
     const float mx = means[3 * i], my = means[3 * i + 1], mz = means[3 * i + 2];
     const float tz = depth_of(cam, mx, my, mz);
@@ -420,20 +421,43 @@ hipError_t launch_preprocess_fwd(const gsr_scene &s, const DevCamera &cam, float
     return hipGetLastError();
 }
 
-hipError_t launch_preprocess_bwd(const gsr_scene &s, const DevCamera &cam, const int32_t *radius, const float *acc,
-                                 const gsr_grads &out, int accumulate, hipStream_t st) {
+hipError_t launch_preprocess_bwd(const gsr_scene &s, const DevCamera &cam, const int32_t *radius, const void *acc,
+                                 bool acc_f64, const gsr_grads &out, int accumulate, hipStream_t st) {
     if (s.n <= 0) return hipSuccess;
     const unsigned blocks = (unsigned)((s.n + 255) / 256);
-#define GSR_PB(D)                                                                                                  \
-    preprocess_bwd_kernel<D><<<blocks, 256, 0, st>>>(s.n, s.means3d, s.log_scales, s.quats, s.opacity_logits, s.sh, \
-                                                      cam, radius, acc, out, accumulate)
-    switch (s.sh_degree) {
-    case 0: GSR_PB(0); break;
-    case 1: GSR_PB(1); break;
-    case 2: GSR_PB(2); break;
-    default: GSR_PB(3); break;
+#define GSR_PB(D, A)                                                                                               \
+    preprocess_bwd_kernel<D, A><<<blocks, 256, 0, st>>>(s.n, s.means3d, s.log_scales, s.quats, s.opacity_logits,  \
+                                                         s.sh, cam, radius, static_cast<const A *>(acc), out,     \
+                                                         accumulate)
+    if (acc_f64) {
+        switch (s.sh_degree) {
+        case 0: GSR_PB(0, double); break;
+        case 1: GSR_PB(1, double); break;
+        case 2: GSR_PB(2, double); break;
+        default: GSR_PB(3, double); break;
+        }
+    } else {
+        switch (s.sh_degree) {
+        case 0: GSR_PB(0, float); break;
+        case 1: GSR_PB(1, float); break;
+        case 2: GSR_PB(2, float); break;
+        default: GSR_PB(3, float); break;
+        }
     }
 #undef GSR_PB
+    return hipGetLastError();
+}
+
+namespace {
+__global__ __launch_bounds__(256) void f64_to_f32_kernel(const double *src, float *dst, int64_t count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) dst[i] = (float)src[i];
+}
+} // namespace
+
+hipError_t launch_f64_to_f32(const double *src, float *dst, int64_t count, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    f64_to_f32_kernel<<<(unsigned)((count + 255) / 256), 256, 0, st>>>(src, dst, count);
     return hipGetLastError();
 }
 

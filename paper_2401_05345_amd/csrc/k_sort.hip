@@ -265,7 +265,7 @@ namespace {
 __global__ __launch_bounds__(256) void emit_pairs_kernel(int64_t n, const uint32_t *sorted_ids,
                                                           const uint32_t *offsets, const float4 *rec,
                                                           const int32_t *radius, DevCamera cam, uint32_t *pair_tile,
-                                                          uint32_t *pair_id) {
+                                                          uint32_t *pair_id, uint32_t cap) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint32_t g = sorted_ids[i];
@@ -277,10 +277,25 @@ __global__ __launch_bounds__(256) void emit_pairs_kernel(int64_t n, const uint32
     uint32_t o = offsets[i];
     for (int ty = y0; ty < y1; ++ty)
         for (int tx = x0; tx < x1; ++tx) {
-            pair_tile[o] = (uint32_t)(ty * cam.grid_x + tx);
-            pair_id[o] = g;
+            if (o < cap) { // pairs past the buffer's capacity are dropped (and flagged by pad_pairs)
+                pair_tile[o] = (uint32_t)(ty * cam.grid_x + tx);
+                pair_id[o] = g;
+            }
             ++o;
         }
+}
+
+// Capacity mode: entries [total, cap) get the sentinel tile (sorted last, ignored by the
+// range kernel); overflow[0] = 1 when the pairs did not fit.
+__global__ __launch_bounds__(256) void pad_pairs_kernel(const uint32_t *total, uint32_t cap, uint32_t sentinel,
+                                                         uint32_t *pair_tile, uint32_t *pair_id, uint32_t *overflow) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t t = total[0];
+    if (i == 0) overflow[0] = t > cap ? 1u : 0u;
+    if (i < cap && i >= t) {
+        pair_tile[i] = sentinel;
+        pair_id[i] = 0u;
+    }
 }
 
 __global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t *p, uint32_t value, int64_t count) {
@@ -288,10 +303,12 @@ __global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t *p, uint32_t val
     if (i < count) p[i] = value;
 }
 
-__global__ __launch_bounds__(256) void tile_ranges_kernel(int64_t P, const uint32_t *tile, uint2 *ranges) {
+__global__ __launch_bounds__(256) void tile_ranges_kernel(int64_t P, const uint32_t *tile, uint2 *ranges,
+                                                           uint32_t n_tiles) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= P) return;
     const uint32_t t = tile[i];
+    if (t >= n_tiles) return; // capacity-mode sentinel
     if (i == 0 || tile[i - 1] != t) ranges[t].x = (uint32_t)i;
     if (i == P - 1 || tile[i + 1] != t) ranges[t].y = (uint32_t)(i + 1);
 }
@@ -300,10 +317,18 @@ __global__ __launch_bounds__(256) void tile_ranges_kernel(int64_t P, const uint3
 
 hipError_t launch_emit_pairs(int64_t n, const uint32_t *sorted_ids, const uint32_t *offsets, const float4 *rec,
                              const int32_t *radius, const DevCamera &cam, uint32_t *pair_tile, uint32_t *pair_id,
-                             hipStream_t st) {
+                             int64_t cap, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     emit_pairs_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, sorted_ids, offsets, rec, radius, cam,
-                                                                   pair_tile, pair_id);
+                                                                   pair_tile, pair_id, (uint32_t)cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_pad_pairs(const uint32_t *total, int64_t cap, uint32_t sentinel, uint32_t *pair_tile,
+                            uint32_t *pair_id, uint32_t *overflow, hipStream_t st) {
+    const int64_t threads = cap > 1 ? cap : 1;
+    pad_pairs_kernel<<<(unsigned)((threads + 255) / 256), 256, 0, st>>>(total, (uint32_t)cap, sentinel, pair_tile,
+                                                                        pair_id, overflow);
     return hipGetLastError();
 }
 
@@ -317,7 +342,7 @@ hipError_t launch_tile_ranges(int64_t P, const uint32_t *sorted_tile, uint2 *ran
                               hipStream_t st) {
     hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), 0u, 2 * n_tiles, st);
     if (e != hipSuccess || P <= 0) return e;
-    tile_ranges_kernel<<<(unsigned)((P + 255) / 256), 256, 0, st>>>(P, sorted_tile, ranges);
+    tile_ranges_kernel<<<(unsigned)((P + 255) / 256), 256, 0, st>>>(P, sorted_tile, ranges, (uint32_t)n_tiles);
     return hipGetLastError();
 }
 

@@ -184,7 +184,10 @@ gsr_status gsr_validate_config(const gsr_config *cf, const gsr_camera *c) {
     if (cf->bwd_mode < GSR_BWD_PLAIN_ATOMIC || cf->bwd_mode > GSR_BWD_BLOCK_REDUCE) return GSR_EINVAL;
     if (cf->reduce_threshold < 0 || cf->reduce_threshold > 65) return GSR_EINVAL;
     if (cf->flags & ~(GSR_FLAG_DEBUG_COUNTERS | GSR_FLAG_XCD_REMAP | GSR_FLAG_STAGE_TIMING |
-                      GSR_FLAG_LANE_SPLIT_ATOMICS | GSR_FLAG_NO_TILE_ORDER))
+                      GSR_FLAG_LANE_SPLIT_ATOMICS | GSR_FLAG_NO_TILE_ORDER | GSR_FLAG_ACC_F64))
+        return GSR_EINVAL;
+    // fp64 accumulators exist for the plain and the butterfly modes.
+    if ((cf->flags & GSR_FLAG_ACC_F64) && cf->bwd_mode != GSR_BWD_PLAIN_ATOMIC && cf->bwd_mode != GSR_BWD_WAVE_REDUCE)
         return GSR_EINVAL;
     if (c) {
         const int64_t tiles = (int64_t)((c->width + cf->tile - 1) / cf->tile) * ((c->height + cf->tile - 1) / cf->tile);
@@ -295,6 +298,112 @@ gsr_status check_view(gsr_ctx *ctx, int i, const gsr_scene *scene, const gsr_cam
     return GSR_OK;
 }
 
+// Pair buffers get headroom, so that a later re-render in capacity mode (no host sync) holds
+// pair counts up to a quarter (plus 4096) above this render's.
+int64_t pair_capacity(int64_t P) { return P + P / 4 + 4096; }
+
+gsr_status alloc_view(gsr_ctx *ctx, gsr_fwd *st) {
+    const int64_t n = st->n, nn = n > 0 ? n : 1;
+    const int64_t hw = (int64_t)st->camera.width * st->camera.height;
+    GSR_TRY(pool_alloc(ctx, st, &st->rec, 3 * nn));
+    GSR_TRY(pool_alloc(ctx, st, &st->radius, nn));
+    GSR_TRY(pool_alloc(ctx, st, &st->tiles_touched, nn));
+    GSR_TRY(pool_alloc(ctx, st, &st->clamp_mask, nn));
+    GSR_TRY(pool_alloc(ctx, st, &st->depth_key, nn));
+    GSR_TRY(pool_alloc(ctx, st, &st->ids, nn));
+    GSR_TRY(pool_alloc(ctx, st, &st->key_alt, nn));
+    GSR_TRY(pool_alloc(ctx, st, &st->ids_alt, nn));
+    GSR_TRY(pool_alloc(ctx, st, &st->offsets, nn + 1));
+    GSR_TRY(pool_alloc(ctx, st, &st->ranges, st->n_tiles));
+    GSR_TRY(pool_alloc(ctx, st, &st->T_final, hw));
+    GSR_TRY(pool_alloc(ctx, st, &st->n_contrib, hw));
+    GSR_TRY(pool_alloc(ctx, st, &st->totals, 4));
+    if (n > 1) {
+        const size_t hc = radix_hist_count(n);
+        GSR_TRY(pool_alloc(ctx, st, &st->dsort_hist, hc));
+        GSR_TRY(pool_alloc(ctx, st, &st->dsort_partials, scan_partial_count((int64_t)hc)));
+    }
+    GSR_TRY(pool_alloc(ctx, st, &st->scan_partials, scan_partial_count(nn) + 8));
+    return GSR_OK;
+}
+
+gsr_status alloc_pairs(gsr_ctx *ctx, gsr_fwd *st, int64_t cap) {
+    GSR_TRY(pool_alloc(ctx, st, &st->pair_tile, cap));
+    GSR_TRY(pool_alloc(ctx, st, &st->pair_id, cap));
+    GSR_TRY(pool_alloc(ctx, st, &st->pair_tile_alt, cap));
+    GSR_TRY(pool_alloc(ctx, st, &st->pair_id_alt, cap));
+    const size_t hc = radix_hist_count(cap);
+    GSR_TRY(pool_alloc(ctx, st, &st->tsort_hist, hc));
+    GSR_TRY(pool_alloc(ctx, st, &st->tsort_partials, scan_partial_count((int64_t)hc)));
+    st->pair_cap = cap;
+    return GSR_OK;
+}
+
+// a1 and the depth-digit sort for every view.
+gsr_status enqueue_project_and_depth_sort(gsr_ctx *ctx, int nv, gsr_fwd *const *sts, bool tm) {
+    hipStream_t s = ctx->stream;
+    mark(ctx, tm, EV_R0);
+    for (int v = 0; v < nv; ++v) {
+        gsr_fwd *st = sts[v];
+        GSR_HIP(ctx, launch_preprocess_fwd(st->scene, st->dcam, st->rec, st->radius, st->tiles_touched, st->depth_key,
+                                           st->ids, st->clamp_mask, s));
+    }
+    mark(ctx, tm, EV_R1);
+    // a2/a3 (depth digits): sort Gaussians by fp32 depth; stable, so ties keep index order.
+    for (int v = 0; v < nv; ++v) {
+        gsr_fwd *st = sts[v];
+        int which = 0;
+        if (st->n > 1)
+            GSR_HIP(ctx, radix_sort_pairs(st->depth_key, st->ids, st->key_alt, st->ids_alt, st->n, 32, st->dsort_hist,
+                                          st->dsort_partials, &which, s));
+        st->sorted_ids_by_depth = which ? st->ids_alt : st->ids;
+    }
+    mark(ctx, tm, EV_R2);
+    // a2: pair offsets in depth order, their total P and the visible count.
+    for (int v = 0; v < nv; ++v) {
+        gsr_fwd *st = sts[v];
+        GSR_HIP(ctx, device_exclusive_scan(st->tiles_touched, st->sorted_ids_by_depth, st->offsets, st->n,
+                                           st->totals, st->scan_partials, s));
+        GSR_HIP(ctx, launch_count_positive(st->radius, st->n, st->totals + 1, s));
+    }
+    return GSR_OK;
+}
+
+// a5 for every view in one launch (longest list first), then each view's tile_walk orders
+// its backward. work: a table of base[nv] entries for the launch (nullptr: a pool temp).
+gsr_status enqueue_composite_fwd(gsr_ctx *ctx, int nv, gsr_fwd *const *sts, float *const *images,
+                                 const gsr_config *config, uint2 *work_buf, bool tm) {
+    hipStream_t s = ctx->stream;
+    const bool ordered = !(config->flags & (GSR_FLAG_XCD_REMAP | GSR_FLAG_NO_TILE_ORDER));
+    ViewBatch vb{};
+    vb.n = nv;
+    for (int v = 0; v < nv; ++v) {
+        gsr_fwd *st = sts[v];
+        if (ordered && !st->tile_walk) GSR_TRY(pool_alloc(ctx, st, &st->tile_walk, st->n_tiles));
+        if (!ordered) st->tile_walk = nullptr;
+        vb.v[v] = desc_of(st, images[v], nullptr);
+        vb.base[v + 1] = vb.base[v] + (uint32_t)st->n_tiles;
+    }
+    {
+        TempBuf tb;
+        uint2 *work = nullptr;
+        if (nv > 1 || ordered) {
+            work = work_buf;
+            if (!work) GSR_TRY(temp_alloc(ctx, tb, &work, vb.base[nv]));
+            GSR_HIP(ctx, launch_order_tiles(vb, ordered ? ORDER_BY_LENGTH : ORDER_IDENTITY, work, s));
+        }
+        const int remap = (nv == 1 && (config->flags & GSR_FLAG_XCD_REMAP)) ? 1 : 0;
+        GSR_HIP(ctx, launch_composite_fwd(vb, config->tile, config->lds_batch, remap, work, s));
+    }
+    if (ordered && nv == 1) {
+        gsr_fwd *st = sts[0];
+        if (!st->order_bwd) GSR_TRY(pool_alloc(ctx, st, &st->order_bwd, st->n_tiles));
+        GSR_HIP(ctx, launch_order_tiles(vb, ORDER_BY_WALK, st->order_bwd, s));
+    }
+    mark(ctx, tm, EV_R6);
+    return GSR_OK;
+}
+
 // Renders nv validated views. Every stage runs for all views before the
 // next; one synchronisation reads back all pair counts; the composite is one
 // launch over all (view, tile) pairs.
@@ -305,7 +414,6 @@ gsr_status render_views(gsr_ctx *ctx, int nv, const gsr_scene *scenes, const gsr
     const bool tm = (config->flags & GSR_FLAG_STAGE_TIMING) != 0;
     ctx->timing_render = tm;
     gsr_fwd *sts[kMaxViews] = {};
-    uint32_t *totals[kMaxViews] = {};
     uint32_t *sorted_tile[kMaxViews] = {};
     const auto bail = [&](gsr_status code) {
         for (int v = 0; v < nv; ++v)
@@ -333,85 +441,31 @@ gsr_status render_views(gsr_ctx *ctx, int nv, const gsr_scene *scenes, const gsr
         st->dcam = make_dev_camera(cameras[v], config->tile);
         st->n = scenes[v].n;
         st->n_tiles = (int64_t)st->dcam.grid_x * st->dcam.grid_y;
-        const int64_t nn = st->n > 0 ? st->n : 1;
-        const int64_t hw = (int64_t)cameras[v].width * cameras[v].height;
-        GSR_RT(pool_alloc(ctx, st, &st->rec, 3 * nn));
-        GSR_RT(pool_alloc(ctx, st, &st->radius, nn));
-        GSR_RT(pool_alloc(ctx, st, &st->tiles_touched, nn));
-        GSR_RT(pool_alloc(ctx, st, &st->clamp_mask, nn));
-        GSR_RT(pool_alloc(ctx, st, &st->depth_key, nn));
-        GSR_RT(pool_alloc(ctx, st, &st->ids, nn));
-        GSR_RT(pool_alloc(ctx, st, &st->key_alt, nn));
-        GSR_RT(pool_alloc(ctx, st, &st->ids_alt, nn));
-        GSR_RT(pool_alloc(ctx, st, &st->offsets, nn + 1));
-        GSR_RT(pool_alloc(ctx, st, &st->ranges, st->n_tiles));
-        GSR_RT(pool_alloc(ctx, st, &st->T_final, hw));
-        GSR_RT(pool_alloc(ctx, st, &st->n_contrib, hw));
-        GSR_RT(pool_alloc(ctx, st, &totals[v], 4));
+        GSR_RT(alloc_view(ctx, st));
     }
-
-    mark(ctx, tm, EV_R0);
-    // a1: projection
-    for (int v = 0; v < nv; ++v) {
-        gsr_fwd *st = sts[v];
-        GSR_RH(launch_preprocess_fwd(st->scene, st->dcam, st->rec, st->radius, st->tiles_touched, st->depth_key,
-                                     st->ids, st->clamp_mask, s));
-    }
-    mark(ctx, tm, EV_R1);
-    // a2/a3 (depth digits): sort Gaussians by fp32 depth; stable, so ties keep index order.
-    for (int v = 0; v < nv; ++v) {
-        gsr_fwd *st = sts[v];
-        const int64_t n = st->n;
-        int which = 0;
-        if (n > 1) {
-            const size_t hc = radix_hist_count(n), pc = scan_partial_count((int64_t)hc);
-            uint32_t *hist = nullptr, *partials = nullptr;
-            GSR_RT(pool_alloc(ctx, st, &hist, hc));
-            GSR_RT(pool_alloc(ctx, st, &partials, pc));
-            GSR_RH(radix_sort_pairs(st->depth_key, st->ids, st->key_alt, st->ids_alt, n, 32, hist, partials, &which,
-                                    s));
-        }
-        st->sorted_ids_by_depth = which ? st->ids_alt : st->ids;
-    }
-    mark(ctx, tm, EV_R2);
-    // a2: pair offsets in depth order; the totals P of all views are read back at once to size
-    // the pair buffers.
-    for (int v = 0; v < nv; ++v) {
-        gsr_fwd *st = sts[v];
-        const int64_t n = st->n, nn = n > 0 ? n : 1;
-        uint32_t *sp = nullptr;
-        GSR_RT(pool_alloc(ctx, st, &sp, scan_partial_count(nn) + 8));
-        GSR_RH(device_exclusive_scan(st->tiles_touched, st->sorted_ids_by_depth, st->offsets, n, totals[v], sp, s));
-        GSR_RH(launch_count_positive(st->radius, n, totals[v] + 1, s));
-        GSR_RH(hipMemcpyAsync(ctx->host_pinned + 2 * v, totals[v], 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    }
+    GSR_RT(enqueue_project_and_depth_sort(ctx, nv, sts, tm));
+    // The totals P of all views are read back at once to size the pair buffers.
+    for (int v = 0; v < nv; ++v)
+        GSR_RH(hipMemcpyAsync(ctx->host_pinned + 2 * v, sts[v]->totals, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                              s));
     GSR_RH(hipStreamSynchronize(s));
     for (int v = 0; v < nv; ++v) {
         gsr_fwd *st = sts[v];
         st->P = st->n > 0 ? (int64_t)ctx->host_pinned[2 * v] : 0;
         st->n_visible = st->n > 0 ? (int64_t)ctx->host_pinned[2 * v + 1] : 0;
-        const int64_t PP = st->P > 0 ? st->P : 1;
-        GSR_RT(pool_alloc(ctx, st, &st->pair_tile, PP));
-        GSR_RT(pool_alloc(ctx, st, &st->pair_id, PP));
-        GSR_RT(pool_alloc(ctx, st, &st->pair_tile_alt, PP));
-        GSR_RT(pool_alloc(ctx, st, &st->pair_id_alt, PP));
+        st->p_known = true;
+        GSR_RT(alloc_pairs(ctx, st, pair_capacity(st->P)));
         GSR_RH(launch_emit_pairs(st->n, st->sorted_ids_by_depth, st->offsets, st->rec, st->radius, st->dcam,
-                                 st->pair_tile, st->pair_id, s));
+                                 st->pair_tile, st->pair_id, st->pair_cap, s));
     }
     mark(ctx, tm, EV_R3);
-    // a3 (tile digits): stable sort of the pairs by tile.
+    // a3 (tile digits): stable sort of the P pairs by tile.
     for (int v = 0; v < nv; ++v) {
         gsr_fwd *st = sts[v];
-        const int64_t P = st->P;
         int which = 0;
-        if (P > 1) {
-            const size_t hc = radix_hist_count(P), pc = scan_partial_count((int64_t)hc);
-            uint32_t *h2 = nullptr, *p2 = nullptr;
-            GSR_RT(pool_alloc(ctx, st, &h2, hc));
-            GSR_RT(pool_alloc(ctx, st, &p2, pc));
-            GSR_RH(radix_sort_pairs(st->pair_tile, st->pair_id, st->pair_tile_alt, st->pair_id_alt, P,
-                                    bits_for(st->n_tiles), h2, p2, &which, s));
-        }
+        if (st->P > 1)
+            GSR_RH(radix_sort_pairs(st->pair_tile, st->pair_id, st->pair_tile_alt, st->pair_id_alt, st->P,
+                                    bits_for(st->n_tiles), st->tsort_hist, st->tsort_partials, &which, s));
         sorted_tile[v] = which ? st->pair_tile_alt : st->pair_tile;
         st->sorted_pair_id = which ? st->pair_id_alt : st->pair_id;
     }
@@ -419,37 +473,47 @@ gsr_status render_views(gsr_ctx *ctx, int nv, const gsr_scene *scenes, const gsr
     // a4: per-tile ranges
     for (int v = 0; v < nv; ++v) GSR_RH(launch_tile_ranges(sts[v]->P, sorted_tile[v], sts[v]->ranges, sts[v]->n_tiles, s));
     mark(ctx, tm, EV_R5);
-    // a5: one forward composite over every (view, tile) pair, longest list first; it records
-    // each tile's deepest n_contrib, which orders the backward's tiles the same way.
-    const bool ordered = !(config->flags & (GSR_FLAG_XCD_REMAP | GSR_FLAG_NO_TILE_ORDER));
-    ViewBatch vb{};
-    vb.n = nv;
-    for (int v = 0; v < nv; ++v) {
-        gsr_fwd *st = sts[v];
-        if (ordered) GSR_RT(pool_alloc(ctx, st, &st->tile_walk, st->n_tiles));
-        vb.v[v] = desc_of(st, images[v], nullptr);
-        vb.base[v + 1] = vb.base[v] + (uint32_t)st->n_tiles;
-    }
-    {
-        TempBuf tb;
-        uint2 *work = nullptr;
-        if (nv > 1 || ordered) {
-            GSR_RT(temp_alloc(ctx, tb, &work, vb.base[nv]));
-            GSR_RH(launch_order_tiles(vb, ordered ? ORDER_BY_LENGTH : ORDER_IDENTITY, work, s));
-        }
-        const int remap = (nv == 1 && (config->flags & GSR_FLAG_XCD_REMAP)) ? 1 : 0;
-        GSR_RH(launch_composite_fwd(vb, config->tile, config->lds_batch, remap, work, s));
-    }
-    if (ordered && nv == 1) {
-        gsr_fwd *st = sts[0];
-        GSR_RT(pool_alloc(ctx, st, &st->order_bwd, st->n_tiles));
-        GSR_RH(launch_order_tiles(vb, ORDER_BY_WALK, st->order_bwd, s));
-    }
-    mark(ctx, tm, EV_R6);
+    GSR_RT(enqueue_composite_fwd(ctx, nv, sts, images, config, nullptr, tm));
 #undef GSR_RT
 #undef GSR_RH
     for (int v = 0; v < nv; ++v) states_out[v] = sts[v];
     return GSR_OK;
+}
+
+// Capacity mode: re-renders existing states (their scenes' current contents, their cameras)
+// into their own buffers without any host synchronisation. Each view sorts its whole pair
+// capacity, the entries past its pair count carrying a sentinel tile that sorts last; a view
+// whose pairs exceed the capacity sets its overflow flag (gsr_fwd_sync reports it).
+gsr_status rerender_views(gsr_ctx *ctx, int nv, gsr_fwd *const *sts, float *const *images, const gsr_config *config,
+                          uint2 *work_buf, bool tm) {
+    hipStream_t s = ctx->stream;
+    uint32_t *sorted_tile[kMaxViews] = {};
+    for (int v = 0; v < nv; ++v) {
+        sts[v]->p_known = false;
+        sts[v]->capacity_mode = true;
+    }
+    GSR_TRY(enqueue_project_and_depth_sort(ctx, nv, sts, tm));
+    for (int v = 0; v < nv; ++v) {
+        gsr_fwd *st = sts[v];
+        GSR_HIP(ctx, launch_emit_pairs(st->n, st->sorted_ids_by_depth, st->offsets, st->rec, st->radius, st->dcam,
+                                       st->pair_tile, st->pair_id, st->pair_cap, s));
+        GSR_HIP(ctx, launch_pad_pairs(st->totals, st->pair_cap, (uint32_t)st->n_tiles, st->pair_tile, st->pair_id,
+                                      st->totals + 2, s));
+    }
+    mark(ctx, tm, EV_R3);
+    for (int v = 0; v < nv; ++v) {
+        gsr_fwd *st = sts[v];
+        int which = 0;
+        GSR_HIP(ctx, radix_sort_pairs(st->pair_tile, st->pair_id, st->pair_tile_alt, st->pair_id_alt, st->pair_cap,
+                                      bits_for(st->n_tiles + 1), st->tsort_hist, st->tsort_partials, &which, s));
+        sorted_tile[v] = which ? st->pair_tile_alt : st->pair_tile;
+        st->sorted_pair_id = which ? st->pair_id_alt : st->pair_id;
+    }
+    mark(ctx, tm, EV_R4);
+    for (int v = 0; v < nv; ++v)
+        GSR_HIP(ctx, launch_tile_ranges(sts[v]->pair_cap, sorted_tile[v], sts[v]->ranges, sts[v]->n_tiles, s));
+    mark(ctx, tm, EV_R5);
+    return enqueue_composite_fwd(ctx, nv, sts, images, config, work_buf, tm);
 }
 
 // Backward composite over nv checked states, in two parts so that the second
@@ -470,7 +534,11 @@ gsr_status bwd_prepare(gsr_ctx *ctx, int nv, gsr_fwd *const *sts, const float *c
     const bool count = (cfg->flags & GSR_FLAG_DEBUG_COUNTERS) != 0;
     for (int v = 0; v < nv; ++v) {
         gsr_fwd *st = sts[v];
-        if (!st->acc) GSR_TRY(pool_alloc(ctx, st, &st->acc, (size_t)(st->n > 0 ? st->n : 1) * GSR_ACC_STRIDE));
+        if (!st->acc) {
+            double *a = nullptr; // rows sized for doubles, so either precision fits
+            GSR_TRY(pool_alloc(ctx, st, &a, (size_t)(st->n > 0 ? st->n : 1) * GSR_ACC_STRIDE));
+            st->acc = a;
+        }
     }
     if (count && !sts[0]->counters) GSR_TRY(pool_alloc(ctx, sts[0], &sts[0]->counters, 80));
     ViewBatch &vb = plan.vb;
@@ -512,11 +580,13 @@ gsr_status bwd_enqueue(gsr_ctx *ctx, int nv, gsr_fwd *const *sts, const gsr_conf
                        bool tm) {
     hipStream_t s = ctx->stream;
     const bool count = (cfg->flags & GSR_FLAG_DEBUG_COUNTERS) != 0;
+    const bool f64 = (cfg->flags & GSR_FLAG_ACC_F64) != 0;
     for (int v = 0; v < nv; ++v) sts[v]->counters_valid = false;
     mark(ctx, tm, EV_B0);
     for (int v = 0; v < nv; ++v) {
         const int64_t nn = sts[v]->n > 0 ? sts[v]->n : 1;
-        GSR_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t *>(sts[v]->acc), 0u, nn * GSR_ACC_STRIDE, s));
+        GSR_HIP(ctx, launch_fill_u32(static_cast<uint32_t *>(sts[v]->acc), 0u, nn * GSR_ACC_STRIDE * (f64 ? 2 : 1), s));
+        sts[v]->acc_f64 = f64;
     }
     if (count) GSR_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t *>(sts[0]->counters), 0u, 160, s));
     mark(ctx, tm, EV_B1);
@@ -525,7 +595,7 @@ gsr_status bwd_enqueue(gsr_ctx *ctx, int nv, gsr_fwd *const *sts, const gsr_conf
     p.counters = count ? sts[0]->counters : nullptr;
     p.threshold = cfg->reduce_threshold < 1 ? 1 : cfg->reduce_threshold;
     GSR_HIP(ctx, launch_composite_bwd(plan.vb, cfg->tile, cfg->lds_batch, plan.remap, cfg->bwd_mode, count,
-                                      (cfg->flags & GSR_FLAG_LANE_SPLIT_ATOMICS) != 0, p, plan.work, s));
+                                      (cfg->flags & GSR_FLAG_LANE_SPLIT_ATOMICS) != 0, f64, p, plan.work, s));
     mark(ctx, tm, EV_B2);
     sts[0]->counters_valid = count;
     return GSR_OK;
@@ -603,7 +673,7 @@ gsr_status gsr_backward_params(gsr_ctx *ctx, gsr_fwd *st, const gsr_grads *out, 
     GSR_TRY(check_grads(ctx, st, out));
     if (!st->acc) return fail(ctx, GSR_ESTATE, "no backward composite has run on this state");
     GSR_HIP(ctx, hipSetDevice(ctx->device));
-    GSR_HIP(ctx, launch_preprocess_bwd(st->scene, st->dcam, st->radius, st->acc, *out, accumulate ? 1 : 0,
+    GSR_HIP(ctx, launch_preprocess_bwd(st->scene, st->dcam, st->radius, st->acc, st->acc_f64, *out, accumulate ? 1 : 0,
                                        ctx->stream));
     return GSR_OK;
 }
@@ -617,7 +687,7 @@ gsr_status gsr_backward(gsr_ctx *ctx, gsr_fwd *st, const float *dl_dimage_chw, c
     GSR_HIP(ctx, hipSetDevice(ctx->device));
     const bool tm = (config->flags & GSR_FLAG_STAGE_TIMING) != 0;
     GSR_TRY(bwd_views(ctx, 1, &st, &dl_dimage_chw, config, tm));
-    GSR_HIP(ctx, launch_preprocess_bwd(st->scene, st->dcam, st->radius, st->acc, *out, accumulate ? 1 : 0,
+    GSR_HIP(ctx, launch_preprocess_bwd(st->scene, st->dcam, st->radius, st->acc, st->acc_f64, *out, accumulate ? 1 : 0,
                                        ctx->stream));
     mark(ctx, tm, EV_B3);
     ctx->timing_bwd = tm;
@@ -654,7 +724,7 @@ gsr_status check_batch_bwd(gsr_ctx *ctx, int32_t n_views, gsr_fwd *const *states
 gsr_status enqueue_params(gsr_ctx *ctx, int nv, gsr_fwd *const *states, const gsr_grads *outs, const int *adds) {
     for (int v = 0; v < nv; ++v) {
         gsr_fwd *st = states[v];
-        GSR_HIP(ctx, launch_preprocess_bwd(st->scene, st->dcam, st->radius, st->acc, outs[v], adds[v], ctx->stream));
+        GSR_HIP(ctx, launch_preprocess_bwd(st->scene, st->dcam, st->radius, st->acc, st->acc_f64, outs[v], adds[v], ctx->stream));
     }
     return GSR_OK;
 }
@@ -663,8 +733,10 @@ gsr_status enqueue_params(gsr_ctx *ctx, int nv, gsr_fwd *const *states, const gs
 
 struct gsr_graph {
     int device = 0;
+    gsr_ctx *ctx = nullptr;          // the capturing context; its pool owns `owned`
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    std::vector<void *> owned;       // buffers only the replays use (work tables, loss scratch)
 };
 
 extern "C" {
@@ -685,23 +757,14 @@ gsr_status gsr_backward_batch(gsr_ctx *ctx, int32_t n_views, gsr_fwd *const *sta
     return GSR_OK;
 }
 
-gsr_status gsr_graph_capture_backward(gsr_ctx *ctx, int32_t n_views, gsr_fwd *const *states,
-                                      const float *const *dl_dimages_chw, const gsr_grads *outs, int accumulate,
-                                      const gsr_config *config, gsr_graph **graph_out) {
-    if (!ctx) return GSR_EINVAL;
-    ctx->err.clear();
-    if (!graph_out) return fail(ctx, GSR_EINVAL, "graph_out is null");
-    *graph_out = nullptr;
-    int adds[kMaxViews] = {};
-    GSR_TRY(check_batch_bwd(ctx, n_views, states, dl_dimages_chw, outs, accumulate, &config, adds));
-    gsr_config cfg = *config;
-    cfg.flags &= ~GSR_FLAG_STAGE_TIMING;
-    GSR_HIP(ctx, hipSetDevice(ctx->device));
-    // Every buffer is allocated (and a single view's tile order computed) before the capture,
-    // so the captured work is kernels only.
-    BwdPlan plan;
-    GSR_TRY(bwd_prepare(ctx, n_views, states, dl_dimages_chw, &cfg, plan));
-    // Capture needs a stream other than the null stream.
+} // extern "C"
+
+namespace {
+
+// Records `body` (which only enqueues kernels on ctx->stream) into a graph. When the context
+// is on the null stream the capture runs on a temporary stream of default priority.
+template <typename F>
+gsr_status capture_graph(gsr_ctx *ctx, gsr_graph *gr, F &&body) {
     hipStream_t saved = ctx->stream, cs = ctx->stream;
     const bool own = cs == nullptr;
     if (own) GSR_HIP(ctx, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
@@ -709,8 +772,7 @@ gsr_status gsr_graph_capture_backward(gsr_ctx *ctx, int32_t n_views, gsr_fwd *co
     gsr_status st = GSR_OK;
     if (e == hipSuccess) {
         ctx->stream = cs;
-        st = bwd_enqueue(ctx, n_views, states, &cfg, plan, false);
-        if (st == GSR_OK) st = enqueue_params(ctx, n_views, states, outs, adds);
+        st = body();
         ctx->stream = saved;
     }
     hipGraph_t g = nullptr;
@@ -727,15 +789,185 @@ gsr_status gsr_graph_capture_backward(gsr_ctx *ctx, int32_t n_views, gsr_fwd *co
         (void)hipGraphDestroy(g);
         return fail(ctx, GSR_EHIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
     }
-    gsr_graph *gr = new (std::nothrow) gsr_graph();
-    if (!gr) {
-        (void)hipGraphExecDestroy(ex);
-        (void)hipGraphDestroy(g);
-        return fail(ctx, GSR_ENOMEM, "host allocation failed");
-    }
     gr->device = ctx->device;
+    gr->ctx = ctx;
     gr->graph = g;
     gr->exec = ex;
+    return GSR_OK;
+}
+
+template <typename T>
+gsr_status graph_alloc(gsr_ctx *ctx, gsr_graph *gr, T **p, size_t count) {
+    GSR_TRY(pool_alloc(ctx, nullptr, p, count));
+    gr->owned.push_back(*p);
+    return GSR_OK;
+}
+
+void free_graph(gsr_ctx *ctx, gsr_graph *gr) {
+    for (void *p : gr->owned) ctx->pool->release(p);
+    delete gr;
+}
+
+} // namespace
+
+extern "C" {
+
+gsr_status gsr_graph_capture_backward(gsr_ctx *ctx, int32_t n_views, gsr_fwd *const *states,
+                                      const float *const *dl_dimages_chw, const gsr_grads *outs, int accumulate,
+                                      const gsr_config *config, gsr_graph **graph_out) {
+    if (!ctx) return GSR_EINVAL;
+    ctx->err.clear();
+    if (!graph_out) return fail(ctx, GSR_EINVAL, "graph_out is null");
+    *graph_out = nullptr;
+    int adds[kMaxViews] = {};
+    GSR_TRY(check_batch_bwd(ctx, n_views, states, dl_dimages_chw, outs, accumulate, &config, adds));
+    gsr_config cfg = *config;
+    cfg.flags &= ~GSR_FLAG_STAGE_TIMING;
+    GSR_HIP(ctx, hipSetDevice(ctx->device));
+    // Every buffer is allocated (and a single view's tile order computed) before the capture,
+    // so the captured work is kernels only.
+    BwdPlan plan;
+    GSR_TRY(bwd_prepare(ctx, n_views, states, dl_dimages_chw, &cfg, plan));
+    gsr_graph *gr = new (std::nothrow) gsr_graph();
+    if (!gr) return fail(ctx, GSR_ENOMEM, "host allocation failed");
+    const gsr_status st = capture_graph(ctx, gr, [&] {
+        GSR_TRY(bwd_enqueue(ctx, n_views, states, &cfg, plan, false));
+        return enqueue_params(ctx, n_views, states, outs, adds);
+    });
+    if (st != GSR_OK) {
+        free_graph(ctx, gr);
+        return st;
+    }
+    *graph_out = gr;
+    return GSR_OK;
+}
+
+gsr_status gsr_rerender_batch(gsr_ctx *ctx, int32_t n_views, gsr_fwd *const *states, float *const *images_chw,
+                              const gsr_config *config) {
+    if (!ctx) return GSR_EINVAL;
+    ctx->err.clear();
+    if (n_views < 1 || n_views > GSR_MAX_BATCH) return fail(ctx, GSR_EINVAL, "n_views %d outside 1..16", n_views);
+    if (!states || !images_chw) return fail(ctx, GSR_EINVAL, "null array argument");
+    if (!states[0]) return fail(ctx, GSR_EINVAL, "state 0 is null");
+    if (!config) config = &states[0]->config;
+    for (int v = 0; v < n_views; ++v) {
+        if (!states[v] || !images_chw[v]) return fail(ctx, GSR_EINVAL, "null state or image (view %d)", v);
+        if (states[v]->config.tile != config->tile) return fail(ctx, GSR_EINVAL, "tile differs from the render's");
+        if (gsr_validate_config(config, &states[v]->camera) != GSR_OK) return fail(ctx, GSR_EINVAL, "invalid config");
+        for (int u = 0; u < v; ++u)
+            if (states[u] == states[v]) return fail(ctx, GSR_EINVAL, "views %d and %d share a state", u, v);
+    }
+    GSR_HIP(ctx, hipSetDevice(ctx->device));
+    const bool tm = (config->flags & GSR_FLAG_STAGE_TIMING) != 0;
+    ctx->timing_render = tm;
+    return rerender_views(ctx, n_views, states, images_chw, config, nullptr, tm);
+}
+
+gsr_status gsr_fwd_sync(gsr_ctx *ctx, gsr_fwd *st, int64_t *n_pairs, int32_t *overflowed) {
+    if (!ctx) return GSR_EINVAL;
+    ctx->err.clear();
+    if (!st) return fail(ctx, GSR_EINVAL, "state is null");
+    GSR_HIP(ctx, hipSetDevice(ctx->device));
+    int32_t over = 0;
+    // After a capacity-mode render (or graph replays of one) the device holds the counts.
+    if (!st->p_known || st->capacity_mode) {
+        GSR_HIP(ctx, hipMemcpyAsync(ctx->host_pinned, st->totals, 3 * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                                    ctx->stream));
+        GSR_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        st->P = st->n > 0 ? (int64_t)ctx->host_pinned[0] : 0;
+        st->n_visible = st->n > 0 ? (int64_t)ctx->host_pinned[1] : 0;
+        over = ctx->host_pinned[2] != 0u;
+        if (over) st->P = st->pair_cap; // the lists hold the first pair_cap pairs only
+        st->p_known = true;
+        st->overflowed = over != 0;
+    } else {
+        over = st->overflowed ? 1 : 0;
+    }
+    if (n_pairs) *n_pairs = st->P;
+    if (overflowed) *overflowed = over;
+    return GSR_OK;
+}
+
+gsr_status gsr_graph_capture_step(gsr_ctx *ctx, int32_t n_views, gsr_fwd *const *states, float *const *images_chw,
+                                  const float *const *targets_chw, float loss_lambda, float *const *dl_dimages_chw,
+                                  const gsr_grads *outs, int accumulate, const gsr_config *config,
+                                  gsr_graph **graph_out) {
+    if (!ctx) return GSR_EINVAL;
+    ctx->err.clear();
+    if (!graph_out) return fail(ctx, GSR_EINVAL, "graph_out is null");
+    *graph_out = nullptr;
+    if (!images_chw || !targets_chw || !dl_dimages_chw) return fail(ctx, GSR_EINVAL, "null array argument");
+    if (!(loss_lambda >= 0.0f && loss_lambda <= 1.0f)) return fail(ctx, GSR_EINVAL, "lambda outside [0, 1]");
+    int adds[kMaxViews] = {};
+    GSR_TRY(check_batch_bwd(ctx, n_views, states, dl_dimages_chw, outs, accumulate, &config, adds));
+    for (int v = 0; v < n_views; ++v)
+        if (!images_chw[v] || !targets_chw[v]) return fail(ctx, GSR_EINVAL, "null image or target (view %d)", v);
+    gsr_config cfg = *config;
+    cfg.flags &= ~GSR_FLAG_STAGE_TIMING;
+    GSR_HIP(ctx, hipSetDevice(ctx->device));
+    gsr_graph *gr = new (std::nothrow) gsr_graph();
+    if (!gr) return fail(ctx, GSR_ENOMEM, "host allocation failed");
+    const auto bail = [&](gsr_status code) {
+        free_graph(ctx, gr);
+        return code;
+    };
+    // Eager preparation: every buffer the replays touch exists before the capture.
+    const bool ordered = !(cfg.flags & (GSR_FLAG_XCD_REMAP | GSR_FLAG_NO_TILE_ORDER));
+    int64_t tiles = 0;
+    for (int v = 0; v < n_views; ++v) {
+        gsr_fwd *st = states[v];
+        if (ordered && !st->tile_walk) {
+            const gsr_status e = pool_alloc(ctx, st, &st->tile_walk, st->n_tiles);
+            if (e != GSR_OK) return bail(e);
+        }
+        if (ordered && n_views == 1 && !st->order_bwd) {
+            const gsr_status e = pool_alloc(ctx, st, &st->order_bwd, st->n_tiles);
+            if (e != GSR_OK) return bail(e);
+        }
+        tiles += st->n_tiles;
+    }
+    uint2 *fwd_work = nullptr;
+    if (n_views > 1 || ordered) {
+        const gsr_status e = graph_alloc(ctx, gr, &fwd_work, tiles);
+        if (e != GSR_OK) return bail(e);
+    }
+    float *scratch[kMaxViews][4] = {};
+    if (loss_lambda > 0.0f)
+        for (int v = 0; v < n_views; ++v) {
+            const size_t n3 = 3 * (size_t)states[v]->camera.width * states[v]->camera.height;
+            for (int k = 0; k < 3; ++k) {
+                const gsr_status e = graph_alloc(ctx, gr, &scratch[v][k], n3);
+                if (e != GSR_OK) return bail(e);
+            }
+            const gsr_status e = graph_alloc(ctx, gr, &scratch[v][3], 2);
+            if (e != GSR_OK) return bail(e);
+        }
+    const float *dls_c[kMaxViews];
+    for (int v = 0; v < n_views; ++v) dls_c[v] = dl_dimages_chw[v];
+    BwdPlan plan;
+    {
+        const gsr_status e = bwd_prepare(ctx, n_views, states, dls_c, &cfg, plan);
+        if (e != GSR_OK) return bail(e);
+    }
+    const gsr_status st = capture_graph(ctx, gr, [&] {
+        GSR_TRY(rerender_views(ctx, n_views, states, images_chw, &cfg, fwd_work, false));
+        for (int v = 0; v < n_views; ++v) {
+            const gsr_camera &c = states[v]->camera;
+            if (loss_lambda > 0.0f) {
+                GSR_HIP(ctx, launch_l1_dssim_grad(images_chw[v], targets_chw[v], 3, c.width, c.height, loss_lambda,
+                                                  scratch[v][0], scratch[v][1], scratch[v][2], scratch[v][3],
+                                                  dl_dimages_chw[v], nullptr, ctx->stream));
+            } else {
+                GSR_HIP(ctx, launch_l1_grad(images_chw[v], targets_chw[v], 3 * (int64_t)c.width * c.height,
+                                            dl_dimages_chw[v], ctx->stream));
+            }
+        }
+        // The rerender refreshed the lists and walks the plan's view table points at.
+        for (int v = 0; v < n_views; ++v) plan.vb.v[v] = desc_of(states[v], nullptr, dls_c[v]);
+        GSR_TRY(bwd_enqueue(ctx, n_views, states, &cfg, plan, false));
+        return enqueue_params(ctx, n_views, states, outs, adds);
+    });
+    if (st != GSR_OK) return bail(st);
     *graph_out = gr;
     return GSR_OK;
 }
@@ -756,6 +988,8 @@ void gsr_graph_destroy(gsr_ctx *ctx, gsr_graph *graph) {
     if (ctx) (void)hipStreamSynchronize(ctx->stream);
     if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
     if (graph->graph) (void)hipGraphDestroy(graph->graph);
+    if (graph->ctx)
+        for (void *p : graph->owned) graph->ctx->pool->release(p);
     delete graph;
 }
 
@@ -769,8 +1003,8 @@ gsr_status gsr_fwd_release(gsr_ctx *ctx, gsr_fwd *st) {
 gsr_status gsr_fwd_stats(const gsr_fwd *st, gsr_fwd_stats_t *out) {
     if (!st || !out) return GSR_EINVAL;
     out->n = st->n;
-    out->n_visible = st->n_visible;
-    out->n_pairs = st->P;
+    out->n_visible = st->p_known ? st->n_visible : -1;
+    out->n_pairs = st->p_known ? st->P : -1;
     out->grid_x = st->dcam.grid_x;
     out->grid_y = st->dcam.grid_y;
     out->tile = st->config.tile;
@@ -809,9 +1043,14 @@ gsr_status gsr_fwd_export(gsr_ctx *ctx, const gsr_fwd *st, const gsr_fwd_export_
         if (d->clamp_mask) GSR_HIP(ctx, hipMemcpyAsync(d->clamp_mask, st->clamp_mask, n, hipMemcpyDeviceToDevice, s));
         if (d->acc) {
             if (!st->acc) return fail(ctx, GSR_ESTATE, "no backward has run on this state");
-            GSR_HIP(ctx, hipMemcpyAsync(d->acc, st->acc, n * GSR_ACC_STRIDE * 4, hipMemcpyDeviceToDevice, s));
+            if (st->acc_f64)
+                GSR_HIP(ctx, launch_f64_to_f32(static_cast<const double *>(st->acc), d->acc, n * GSR_ACC_STRIDE, s));
+            else
+                GSR_HIP(ctx, hipMemcpyAsync(d->acc, st->acc, n * GSR_ACC_STRIDE * 4, hipMemcpyDeviceToDevice, s));
         }
     }
+    if (d->sorted_ids && !st->p_known)
+        return fail(ctx, GSR_ESTATE, "pair count unknown after a capacity-mode render: call gsr_fwd_sync");
     if (d->sorted_ids && st->P > 0)
         GSR_HIP(ctx, hipMemcpyAsync(d->sorted_ids, st->sorted_pair_id, st->P * 4, hipMemcpyDeviceToDevice, s));
     if (d->ranges)

@@ -23,6 +23,7 @@ GSR_FLAG_XCD_REMAP = 2
 GSR_FLAG_STAGE_TIMING = 4
 GSR_FLAG_LANE_SPLIT_ATOMICS = 8
 GSR_FLAG_NO_TILE_ORDER = 16
+GSR_FLAG_ACC_F64 = 32
 GSR_MAX_BATCH = 16
 GSR_EBUDGET = -5
 GSR_ACC_STRIDE = 16
@@ -154,6 +155,13 @@ _PROTOS = {
     "gsr_server_results": (c_int32, [c_void_p, ctypes.POINTER(gsr_result), c_int32, ctypes.POINTER(c_int32)]),
     "gsr_l1_dssim_grad": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, ctypes.c_float, c_void_p,
                                     c_void_p]),
+    "gsr_rerender_batch": (c_int32, [c_void_p, c_int32, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p),
+                                     ctypes.POINTER(gsr_config)]),
+    "gsr_fwd_sync": (c_int32, [c_void_p, c_void_p, ctypes.POINTER(c_int64), ctypes.POINTER(c_int32)]),
+    "gsr_graph_capture_step": (c_int32, [c_void_p, c_int32, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p),
+                                         ctypes.POINTER(c_void_p), ctypes.c_float, ctypes.POINTER(c_void_p),
+                                         ctypes.POINTER(gsr_grads), c_int32, ctypes.POINTER(gsr_config),
+                                         ctypes.POINTER(c_void_p)]),
     "gsr_backward_composite": (c_int32, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(gsr_config)]),
     "gsr_backward_params": (c_int32, [c_void_p, c_void_p, ctypes.POINTER(gsr_grads), c_int32]),
     "gsr_fwd_release": (c_int32, [c_void_p, c_void_p]),
@@ -294,6 +302,32 @@ def gsr_graph_capture_backward(ctx, states, dl_dimages, grads, accumulate: int =
                                                   (gsr_grads * n)(*grads), int(accumulate),
                                                   ctypes.byref(cfg) if cfg is not None else None,
                                                   ctypes.byref(graph)))
+    return graph
+
+
+def gsr_rerender_batch(ctx, states, images, cfg: gsr_config | None = None):
+    n = len(states)
+    _check(ctx, load().gsr_rerender_batch(ctx, n, (c_void_p * n)(*[s.value for s in states]),
+                                          (c_void_p * n)(*[im.data_ptr() for im in images]),
+                                          ctypes.byref(cfg) if cfg is not None else None))
+
+
+def gsr_fwd_sync(ctx, state):
+    """Returns (pair count, overflowed)."""
+    p, o = c_int64(), c_int32()
+    _check(ctx, load().gsr_fwd_sync(ctx, state, ctypes.byref(p), ctypes.byref(o)))
+    return p.value, bool(o.value)
+
+
+def gsr_graph_capture_step(ctx, states, images, targets, dl_dimages, grads, lam: float = 0.0, accumulate: int = 0,
+                           cfg: gsr_config | None = None):
+    n = len(states)
+    graph = c_void_p()
+    ptrs = lambda ts: (c_void_p * n)(*[t.data_ptr() for t in ts])
+    _check(ctx, load().gsr_graph_capture_step(ctx, n, (c_void_p * n)(*[s.value for s in states]), ptrs(images),
+                                              ptrs(targets), float(lam), ptrs(dl_dimages), (gsr_grads * n)(*grads),
+                                              int(accumulate), ctypes.byref(cfg) if cfg is not None else None,
+                                              ctypes.byref(graph)))
     return graph
 
 

@@ -102,6 +102,8 @@ def _workload_tiny():
     (gsr.GSR_BWD_SERIAL_REDUCE, 24, 0),
     (gsr.GSR_BWD_BLOCK_REDUCE, 1, 0),
     (gsr.GSR_BWD_BLOCK_REDUCE, 32, 0),
+    (gsr.GSR_BWD_PLAIN_ATOMIC, 0, gsr.GSR_FLAG_ACC_F64),
+    (gsr.GSR_BWD_WAVE_REDUCE, 4, gsr.GSR_FLAG_ACC_F64),
 ])
 def test_tiny_parity(renderer, mode, thr, flags):
     say(f"[gpu] tiny_1k parity mode={mode} thr={thr} flags={flags}")

@@ -27,7 +27,10 @@ GiB = 1 << 30
 
 
 def cfg():
-    return gsr.make_config(16, 256, gsr.GSR_BWD_WAVE_REDUCE, 4, gsr.GSR_FLAG_LANE_SPLIT_ATOMICS)
+    # fp64 accumulators: the server's and the direct path's sums agree to rounding, not to the
+    # fp32 atomic-order noise (1e-5 relative and more at scale).
+    return gsr.make_config(16, 256, gsr.GSR_BWD_WAVE_REDUCE, 4,
+                           gsr.GSR_FLAG_LANE_SPLIT_ATOMICS | gsr.GSR_FLAG_ACC_F64)
 
 
 @pytest.fixture(scope="module")
@@ -90,7 +93,7 @@ def test_request_equals_direct_path_and_oracle_adam(gsr, scenes):
         r.close()
     direct = np.concatenate([g[k].cpu().numpy().ravel() for k in ("means3d", "log_scales", "quats",
                                                                    "opacity_logits", "sh")])
-    assert rel_l2(g_srv, direct) <= 1e-5
+    assert rel_l2(g_srv, direct) <= 1e-6
     assert abs(res[0].loss - loss) <= 1e-5 * loss
     # Adam: the oracle's fp64 step from the same gradient
     pr, mr, vr = oracle.adam_step(p0, g_srv, np.zeros_like(p0), np.zeros_like(p0), 1, lr=1e-3, eps=1e-15)
@@ -141,7 +144,7 @@ def test_same_result_alone_and_in_a_batched_mix(gsr, scenes):
     assert max(r.batch_size for r in res) > 1, "the burst was never batched"
     say(f"[gpu] mix batches: {sorted(set(r.batch_size for r in res))}, lanes {sorted(set(r.lane for r in res))}")
     assert abs(ra.loss - rm.loss) <= 1e-5 * ra.loss
-    assert rel_l2(mixed["grads"], alone["grads"]) <= 1e-5
+    assert rel_l2(mixed["grads"], alone["grads"]) <= 1e-6
     # Adam's first step is lr * g / (|g| + eps): equal except where g is at rounding level.
     g = alone["grads"]
     d = np.abs(mixed["params"] - alone["params"])
