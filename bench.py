@@ -432,6 +432,8 @@ def main():
     r6, r7 = b.backward_only(fr, cfg_r, iters)
     s6, _ = b.backward_only(fr, b.cfg(gsr.GSR_BWD_SERIAL_REDUCE, thr), iters)
     k6, _ = b.backward_only(fr, b.cfg(gsr.GSR_BWD_BLOCK_REDUCE, thr), iters)
+    f6, f7 = b.backward_only(fr, b.cfg(gsr.GSR_BWD_WAVE_REDUCE, thr, gsr.GSR_FLAG_ACC_F64), iters)
+    fp6, _ = b.backward_only(fr, b.cfg(gsr.GSR_BWD_PLAIN_ATOMIC, 0, gsr.GSR_FLAG_ACC_F64), max(3, iters // 4))
     cp = b.counters(fr, gsr.GSR_BWD_PLAIN_ATOMIC, 0)
     cr = b.counters(fr, gsr.GSR_BWD_WAVE_REDUCE, thr)
     ck = b.counters(fr, gsr.GSR_BWD_BLOCK_REDUCE, thr)
@@ -490,7 +492,10 @@ def main():
             "composite_bwd_by_mode_ms": {"wave_reduce": round(float(np.median(r6)), 4),
                                          "serial_leader": round(float(np.median(s6)), 4),
                                          "block_lds": round(float(np.median(k6)), 4),
-                                         "plain_atomic": round(float(np.median(p6)), 4)},
+                                         "plain_atomic": round(float(np.median(p6)), 4),
+                                         "wave_reduce_acc_f64": round(float(np.median(f6)), 4),
+                                         "plain_atomic_acc_f64": round(float(np.median(fp6)), 4)},
+            "wave_reduce_acc_f64_bwd_ms": round(float(np.median(f6) + np.median(f7)), 4),
             "lane_atomics_block_lds": int(ck.lane_atomics), "atomic_instrs_block_lds": int(ck.atomic_instrs),
         },
         "forward_ms": round(float(fwd.mean()), 4),

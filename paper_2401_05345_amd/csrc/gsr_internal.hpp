@@ -1,6 +1,6 @@
 // Internal declarations shared by the HIP translation units of libgsr.
 // Device layouts (all in HBM, one allocation each, from the context pool):
-//   rec        [n][3] float4  (u, v, A, B) (C, o, r, g) (b, depth, 0, 0): the
+//   rec        [n][3] float4  (u, v, A, B) (C, o, r, g) (b, depth, 2 ln(255 o), 0): the
 //              record each list entry gathers in the composite kernels
 //   radius     [n] int32, tiles_touched [n] uint32, clamp_mask [n] uint8
 //   depth_key  [n] uint32 (fp32 depth bits, 0xffffffff when culled), ids [n]
@@ -51,19 +51,6 @@ private:
     std::multimap<size_t, void *> free_;
     std::map<void *, size_t> live_;
     size_t reserved_ = 0;
-};
-
-template <typename T>
-struct Buf {
-    T *p = nullptr;
-    size_t count = 0;
-};
-
-// Scratch for the scan / radix sort helpers.
-struct SortScratch {
-    uint32_t *hist = nullptr;     // digit histograms per block, then their exclusive scan
-    uint32_t *partials = nullptr; // per-block sums for multi-level scans
-    size_t hist_count = 0, partial_count = 0;
 };
 
 // ----- kernel launchers (defined in the .hip files) -----

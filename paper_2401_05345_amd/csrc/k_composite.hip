@@ -111,22 +111,45 @@ __device__ __forceinline__ uint32_t emit9(bool active, float (&v)[9], AccT *dst,
 }
 
 // Entries of a staged LDS batch this wave has to visit, as wave-uniform bit
-// masks (bit j % 64 of mask[j / 64] for entry j < limit): the splat's
-// alpha >= 1/255 box (centre (u, v), half-extents in s2.zw) meets the wave's
-// 8x8 sample points (centre qc, 3.5 px half-width, plus 1 px margin). No lane
-// of the wave can pass an entry outside it. Lane l tests entries l, l+64, ...
-// so the walk loops need no per-entry test and skip culled entries with
-// scalar bit scans.
+// masks (bit j % 64 of mask[j / 64] for entry j < limit). A lane of the wave
+// can pass entry j only if the splat's quadratic form d^T K d (K the conic,
+// d the offset from its centre) is at most 2 ln(255 o) at that lane's sample
+// point. The test takes the minimum of the form over the square holding all
+// 8x8 sample points of the wave, widened by half a pixel: zero when the
+// centre lies inside, else the least of the four edge minima (each a clamped
+// one-dimensional quadratic). Being a minimum over a superset of the sample
+// points, with an absolute slack of 1e-3, it never drops an entry some lane
+// passes. Lane l tests entries l, l+64, ... so the walk loops need no
+// per-entry test and skip the rest with scalar bit scans.
+__device__ __forceinline__ float edge_min(float d, float lo, float hi, float kd, float kcross, float ko) {
+    // min over e in [lo, hi] of kd d^2 + 2 kcross d e + ko e^2 (ko > 0)
+    // (an approximate minimiser moves the value only to second order, far inside the slack)
+    const float e = fminf(fmaxf(-kcross * d * __builtin_amdgcn_rcpf(ko), lo), hi);
+    return fmaf(kd * d, d, fmaf(2.0f * kcross * d, e, ko * e * e));
+}
+
 template <int BATCH>
-__device__ __forceinline__ void wave_visit_masks(const float4 *s0, const float4 *s2, int limit, float qcx, float qcy,
-                                                 int lane, uint64_t (&mask)[BATCH / 64]) {
+__device__ __forceinline__ void wave_visit_masks(const float4 *s0, const float4 *s1, const float4 *s2, int limit,
+                                                 float qcx, float qcy, int lane, uint64_t (&mask)[BATCH / 64]) {
 #pragma unroll
     for (int q = 0; q < BATCH / 64; ++q) {
         const int j = q * 64 + lane;
         bool vis = false;
         if (j < limit) {
-            const float4 a = s0[j], c = s2[j];
-            vis = !(fabsf(a.x - qcx) > c.z + 4.5f || fabsf(a.y - qcy) > c.w + 4.5f);
+            const float4 a = s0[j];
+            const float Kc = s1[j].x, reach = s2[j].z;
+            // square [qc - 4, qc + 4]^2 relative to the splat centre
+            const float lx = qcx - 4.0f - a.x, hx = qcx + 4.0f - a.x;
+            const float ly = qcy - 4.0f - a.y, hy = qcy + 4.0f - a.y;
+            const bool inside = lx <= 0.0f && hx >= 0.0f && ly <= 0.0f && hy >= 0.0f;
+            float fmin = 0.0f;
+            if (!(a.z > 0.0f && Kc > 0.0f && a.z * Kc - a.w * a.w > 0.0f)) {
+                fmin = 0.0f; // not positive definite (numerically): keep the entry
+            } else if (!inside) {
+                fmin = fminf(fminf(edge_min(lx, ly, hy, a.z, a.w, Kc), edge_min(hx, ly, hy, a.z, a.w, Kc)),
+                             fminf(edge_min(ly, lx, hx, Kc, a.w, a.z), edge_min(hy, lx, hx, Kc, a.w, a.z)));
+            }
+            vis = reach > 0.0f && fmin <= reach + 1e-3f;
         }
         mask[q] = __ballot(vis);
     }
@@ -186,7 +209,7 @@ __global__ __launch_bounds__(TILE *TILE) void composite_fwd_kernel(ViewBatch vb,
         __syncthreads();
         const int cnt = min(BATCH, (int)(rg.y - start));
         uint64_t vis[BATCH / 64];
-        wave_visit_masks<BATCH>(s0, s2, cnt, qcx, qcy, lane, vis);
+        wave_visit_masks<BATCH>(s0, s1, s2, cnt, qcx, qcy, lane, vis);
 #pragma unroll
         for (int q = 0; q < BATCH / 64; ++q) {
             for (uint64_t mq = vis[q]; mq && !done;) {
@@ -304,7 +327,7 @@ __global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(ViewBatch vb,
         const int jtop = min(cnt, (int)wmax - start) - 1;
         // Entries this wave must visit (at or below its walk bound, not culled), one bit each.
         uint64_t vis[BATCH / 64];
-        wave_visit_masks<BATCH>(s0, s2, jtop + 1, qcx, qcy, lane, vis);
+        wave_visit_masks<BATCH>(s0, s1, s2, jtop + 1, qcx, qcy, lane, vis);
 #pragma unroll
         for (int q = BATCH / 64 - 1; q >= 0; --q) {
             for (uint64_t mq = vis[q]; mq;) {

@@ -173,17 +173,15 @@ __global__ __launch_bounds__(256) void preprocess_fwd_kernel(int n, const float 
         }
     }
     const float o = 1.0f / (1.0f + expf(-opacity_logits[i]));
-    // Bounding box of the pixels this splat can reach: alpha >= 1/255 needs
-    // power >= -ln(255 o), i.e. d^T K d <= 2 ln(255 o), an ellipse whose
-    // half-extents are sqrt(2 ln(255 o) a) and sqrt(2 ln(255 o) c) (K^-1 =
-    // [[a, b], [b, c]]). Composite kernels use it only to skip work for
-    // wavefronts none of whose pixels can pass, with a pixel of margin.
+    // Reach of the splat: alpha >= 1/255 needs power >= -ln(255 o), i.e. the
+    // ellipse d^T K d <= 2 ln(255 o) (K the conic). Composite kernels use it
+    // only to skip entries that no pixel of a wavefront can pass; a splat that
+    // can never reach 1/255 gets -1.
     const float tau = logf(255.0f * o);
-    const float ex = tau > 0.0f ? sqrtf(2.0f * tau * p.a) : -INFINITY;
-    const float ey = tau > 0.0f ? sqrtf(2.0f * tau * p.c) : -INFINITY;
+    const float two_tau = tau > 0.0f ? 2.0f * tau : -1.0f;
     rec[3 * (int64_t)i] = make_float4(u, v, A, B);
     rec[3 * (int64_t)i + 1] = make_float4(C, o, rgb[0], rgb[1]);
-    rec[3 * (int64_t)i + 2] = make_float4(rgb[2], tz, ex, ey);
+    rec[3 * (int64_t)i + 2] = make_float4(rgb[2], tz, two_tau, 0.0f);
     radius[i] = r;
     tiles_touched[i] = (uint32_t)ntiles;
     depth_key[i] = __float_as_uint(tz);

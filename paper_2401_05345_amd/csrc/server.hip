@@ -46,7 +46,6 @@ struct Batch {
     std::vector<Pending> reqs;
     std::vector<int32_t> steps;
     std::vector<gsr_status> status;
-    hipEvent_t done = nullptr;
     double t_start = 0.0;
 };
 

@@ -95,8 +95,11 @@ def test_request_equals_direct_path_and_oracle_adam(gsr, scenes):
                                                                    "opacity_logits", "sh")])
     assert rel_l2(g_srv, direct) <= 1e-6
     assert abs(res[0].loss - loss) <= 1e-5 * loss
-    # Adam: the oracle's fp64 step from the same gradient
-    pr, mr, vr = oracle.adam_step(p0, g_srv, np.zeros_like(p0), np.zeros_like(p0), 1, lr=1e-3, eps=1e-15)
+    # Adam: the oracle's fp64 step from the same gradient, with the hyper-parameters the server
+    # holds (fp32: beta2 = 0.999 is 0.99900001287 there, so 1 - beta2 differs from 0.001 by 1.3e-5)
+    f = lambda x: float(np.float32(x))
+    pr, mr, vr = oracle.adam_step(p0, g_srv, np.zeros_like(p0), np.zeros_like(p0), 1, lr=f(1e-3), beta1=f(0.9),
+                                  beta2=f(0.999), eps=f(1e-15))
     assert np.max(np.abs(p1 - pr)) <= 1e-3 * 1e-4 + 2.0 ** -23 * np.max(np.abs(p0))
     assert rel_l2(m1, mr) <= 1e-6 and rel_l2(v1, vr) <= 1e-6
 
