@@ -44,7 +44,7 @@ FLOPS_PER_EVAL = 14
 FLOPS_PER_CONTRIB = 40
 BYTES_PER_RECORD = 40             # id + mean2d + conic + opacity + rgb, read once per tile-list entry walked
 BYTES_PER_PIXEL = 20              # dL/dI (12) + T_final (4) + n_contrib (4)
-BYTES_PER_VISIBLE = 2 * 36        # accumulators written back once (zero-fill excluded) and read by a7
+BYTES_PER_VISIBLE = 2 * 72        # nine fp64 sums written back once (zero-fill excluded) and read by a7
 
 
 MODES = {"reduce": 1, "plain": 0, "serial": 2, "block": 3}   # gsr_bwd_mode values
@@ -220,7 +220,7 @@ def bench_multi_view(flags, reps=5):
     best, entries = gsr.gsr_autotune(ctx, scenes, cams, space)
     tune_s = time.perf_counter() - t0
     cfg = gsr.make_config(best.tile, best.lds_batch, gsr.GSR_BWD_WAVE_REDUCE, best.reduce_threshold, flags)
-    cfg_plain = gsr.make_config(best.tile, best.lds_batch, gsr.GSR_BWD_PLAIN_ATOMIC, 0, flags)
+    cfg_plain = gsr.make_config(best.tile, best.lds_batch, gsr.GSR_BWD_PLAIN_ATOMIC, 0, flags | gsr.GSR_FLAG_ACC_F32)
     log(f"[bench] autotune ({tune_s:.1f} s): tile {best.tile}, lds {best.lds_batch}, thr {best.reduce_threshold}")
 
     states = gsr.gsr_render_batch(ctx, scenes, cams, cfg, imgs)
@@ -276,7 +276,8 @@ def bench_multi_view(flags, reps=5):
     return res
 
 
-SERVE_RATES = (50, 100, 200, 400)
+SERVE_RATES = (50, 100, 200, 400)       # the served stream's rates (both servers)
+SERVE_RATES_HIGH = (800, 1600, 3200)    # beyond them, the batching server alone: where batches form
 
 
 def _latency_stats(res):
@@ -319,7 +320,7 @@ def bench_serving(flags, seconds):
     out = {"scenes": sizes, "resident_bytes": int(resident), "admitted_at_4GiB": admitted4,
            "budget_bytes": int(resident + (8 << 30)), "rates": {}}
     reduce_cfg = gsr.make_config(16, 256, gsr.GSR_BWD_WAVE_REDUCE, 4, flags)
-    plain_cfg = gsr.make_config(16, 256, gsr.GSR_BWD_PLAIN_ATOMIC, 0, flags)
+    plain_cfg = gsr.make_config(16, 256, gsr.GSR_BWD_PLAIN_ATOMIC, 0, flags | gsr.GSR_FLAG_ACC_F32)
     servers = {"batched_reduce": dict(max_batch=16, lanes=2, config=reduce_cfg),
                "sequential_plain": dict(max_batch=1, lanes=1, config=plain_cfg)}
     for name, kw in servers.items():
@@ -329,7 +330,7 @@ def bench_serving(flags, seconds):
             srv.replay([srv.request(ids[si], cam, seed) for _, si, cam, seed in warm], [0.0] * len(warm))
             srv.drain()
             srv.results()
-            for rate in SERVE_RATES:
+            for rate in SERVE_RATES + (SERVE_RATES_HIGH if name == "batched_reduce" else ()):
                 stream = sg.serving_requests(1000 + rate, len(ids), max(8, int(rate * seconds)), float(rate))
                 reqs = [srv.request(ids[si], cam, seed) for _, si, cam, seed in stream]
                 t0 = time.perf_counter()
@@ -341,6 +342,8 @@ def bench_serving(flags, seconds):
                 out["rates"].setdefault(str(rate), {})[name] = st
                 log(f"[bench] serve {name} {rate}/s: {st}")
     for rate, d in out["rates"].items():
+        if "sequential_plain" not in d:
+            continue
         d["p99_speedup"] = round(d["sequential_plain"]["p99_ms"] / d["batched_reduce"]["p99_ms"], 2)
         d["throughput_ratio"] = round(d["batched_reduce"]["steps_per_s"] / d["sequential_plain"]["steps_per_s"], 2)
     return out
@@ -428,12 +431,14 @@ def main():
     # A/B on one forward state: plain atomics vs wave reduce, same inputs.
     fr = b.forward_state(cfg_r)
     iters = max(10, args.steps)
-    p6, p7 = b.backward_only(fr, b.cfg(gsr.GSR_BWD_PLAIN_ATOMIC, 0), iters)
+    F32 = gsr.GSR_FLAG_ACC_F32
+    # plain atomics with fp32 accumulators: the paper's baseline
+    p6, p7 = b.backward_only(fr, b.cfg(gsr.GSR_BWD_PLAIN_ATOMIC, 0, F32), iters)
     r6, r7 = b.backward_only(fr, cfg_r, iters)
+    w6, w7 = b.backward_only(fr, b.cfg(gsr.GSR_BWD_WAVE_REDUCE, thr, F32), iters)
     s6, _ = b.backward_only(fr, b.cfg(gsr.GSR_BWD_SERIAL_REDUCE, thr), iters)
     k6, _ = b.backward_only(fr, b.cfg(gsr.GSR_BWD_BLOCK_REDUCE, thr), iters)
-    f6, f7 = b.backward_only(fr, b.cfg(gsr.GSR_BWD_WAVE_REDUCE, thr, gsr.GSR_FLAG_ACC_F64), iters)
-    fp6, _ = b.backward_only(fr, b.cfg(gsr.GSR_BWD_PLAIN_ATOMIC, 0, gsr.GSR_FLAG_ACC_F64), max(3, iters // 4))
+    q6, _ = b.backward_only(fr, b.cfg(gsr.GSR_BWD_PLAIN_ATOMIC, 0), max(3, iters // 4))
     cp = b.counters(fr, gsr.GSR_BWD_PLAIN_ATOMIC, 0)
     cr = b.counters(fr, gsr.GSR_BWD_WAVE_REDUCE, thr)
     ck = b.counters(fr, gsr.GSR_BWD_BLOCK_REDUCE, thr)
@@ -473,15 +478,19 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "n_gaussians": wl.scene.n, "width": wl.camera.width,
                    "height": wl.camera.height, "sh_degree": wl.scene.sh_degree, "tile": 16, "lds_batch": 256,
-                   "bwd_mode": "wave_reduce", "reduce_threshold": thr, "n_pairs": int(stats.n_pairs),
+                   "bwd_mode": "wave_reduce", "reduce_threshold": thr, "accumulators": "f64",
+                   "n_pairs": int(stats.n_pairs),
                    "n_visible": n_vis},
         "roofline": roofline,
         "backward": {
             "wave_reduce_ms": round(float(np.median(r6) + np.median(r7)), 4),
             "plain_atomic_ms": round(float(np.median(p6) + np.median(p7)), 4),
+            "wave_reduce_acc_f32_ms": round(float(np.median(w6) + np.median(w7)), 4),
             "composite_bwd_wave_reduce_ms": round(float(np.median(r6)), 4),
             "composite_bwd_plain_ms": round(float(np.median(p6)), 4),
             "speedup_composite_bwd": round(float(np.median(p6) / np.median(r6)), 3),
+            "speedup_composite_bwd_both_f32": round(float(np.median(p6) / np.median(w6)), 3),
+            "speedup_composite_bwd_both_f64": round(float(np.median(q6) / np.median(r6)), 3),
             "p50_backward_ms": round(float(np.percentile(bwd, 50)), 4),
             "p99_backward_ms": round(float(np.percentile(bwd, 99)), 4),
             "lane_atomics_plain": int(cp.lane_atomics), "lane_atomics_reduce": int(cr.lane_atomics),
@@ -489,13 +498,13 @@ def main():
             "evaluated_E": int(cr.evaluated), "active_A": int(cr.active), "wave_entries": int(cr.wave_entries),
             "reduced_W_R": int(cr.reduced), "plain_lanes_A_lt": int(cr.plain_lanes),
             "threshold_sweep_ms": sweep,
-            "composite_bwd_by_mode_ms": {"wave_reduce": round(float(np.median(r6)), 4),
-                                         "serial_leader": round(float(np.median(s6)), 4),
-                                         "block_lds": round(float(np.median(k6)), 4),
-                                         "plain_atomic": round(float(np.median(p6)), 4),
-                                         "wave_reduce_acc_f64": round(float(np.median(f6)), 4),
-                                         "plain_atomic_acc_f64": round(float(np.median(fp6)), 4)},
-            "wave_reduce_acc_f64_bwd_ms": round(float(np.median(f6) + np.median(f7)), 4),
+            "composite_bwd_by_mode_ms": {
+                "f64_accumulators": {"wave_reduce": round(float(np.median(r6)), 4),
+                                     "serial_leader": round(float(np.median(s6)), 4),
+                                     "block_lds": round(float(np.median(k6)), 4),
+                                     "plain_atomic": round(float(np.median(q6)), 4)},
+                "f32_accumulators": {"wave_reduce": round(float(np.median(w6)), 4),
+                                     "plain_atomic": round(float(np.median(p6)), 4)}},
             "lane_atomics_block_lds": int(ck.lane_atomics), "atomic_instrs_block_lds": int(ck.atomic_instrs),
         },
         "forward_ms": round(float(fwd.mean()), 4),
@@ -509,7 +518,8 @@ def main():
         fr3 = b3.forward_state(b3.cfg(gsr.GSR_BWD_WAVE_REDUCE, 32))
         s3 = b3.sweep(fr3, iters=2)
         thr3 = min(s3, key=s3.get)
-        p6, p7 = b3.backward_only(fr3, b3.cfg(gsr.GSR_BWD_PLAIN_ATOMIC, 0), 5)
+        p6, p7 = b3.backward_only(fr3, b3.cfg(gsr.GSR_BWD_PLAIN_ATOMIC, 0, gsr.GSR_FLAG_ACC_F32), 5)
+        w6, w7 = b3.backward_only(fr3, b3.cfg(gsr.GSR_BWD_WAVE_REDUCE, 2, gsr.GSR_FLAG_ACC_F32), 5)
         r6, r7 = b3.backward_only(fr3, b3.cfg(gsr.GSR_BWD_WAVE_REDUCE, thr3), 5)
         c3 = b3.counters(fr3, gsr.GSR_BWD_WAVE_REDUCE, thr3)
         c3p = b3.counters(fr3, gsr.GSR_BWD_PLAIN_ATOMIC, 0)
@@ -520,6 +530,7 @@ def main():
             "composite_bwd_wave_reduce_ms": round(float(np.median(r6)), 4),
             "composite_bwd_plain_ms": round(float(np.median(p6)), 4),
             "speedup_composite_bwd": round(float(np.median(p6) / np.median(r6)), 3),
+            "wave_reduce_acc_f32_bwd_ms": round(float(np.median(w6) + np.median(w7)), 4),
             "lane_atomics_plain": int(c3p.lane_atomics), "lane_atomics_reduce": int(c3.lane_atomics),
             "threshold_sweep_ms": s3,
         }

@@ -59,9 +59,10 @@ enum {
     GSR_FLAG_STAGE_TIMING = 4,   /* record HIP events around each stage (gsr_ctx_stage_times) */
     GSR_FLAG_LANE_SPLIT_ATOMICS = 8, /* reduce path: lanes 0..8 each issue one of the 9 sums in one instruction */
     GSR_FLAG_NO_TILE_ORDER = 16,     /* launch tiles in index order instead of longest-work first */
-    GSR_FLAG_ACC_F64 = 32            /* backward accumulators in fp64: per-wave sums stay fp32, each value is
-                                        one fp64 atomic add (plain and wave-reduce modes; the reduced
-                                        sums are issued by lanes 0..8). Removes fp32 atomic-order noise. */
+    GSR_FLAG_ACC_F32 = 32            /* fp32 backward accumulators (the paper's setting). Without it the
+                                        per-wave sums, kept in fp32 registers, are added into fp64
+                                        accumulator rows (one 128-byte row per Gaussian): the result no
+                                        longer depends on the order of the atomic adds. */
 };
 
 /* Number of floats reserved per Gaussian in the backward accumulators:

@@ -100,6 +100,11 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream
 // out[0] = number of r[i] > 0.
 hipError_t launch_count_positive(const int32_t *r, int64_t n, uint32_t *out, hipStream_t st);
 
+// flags[i] = (r[i] > 0); and the compaction of the flagged (key[i], i) to positions pos[i].
+hipError_t launch_positive_flags(const int32_t *r, int64_t n, uint32_t *flags, hipStream_t st);
+hipError_t launch_compact_keys(const uint32_t *flags, const uint32_t *pos, int64_t n, const uint32_t *key,
+                               uint32_t *key_out, uint32_t *id_out, hipStream_t st);
+
 // One view of a composite launch. A launch covers up to kMaxViews views (same
 // tile size and LDS batch): the views travel by value in the kernel
 // arguments and a work table gives each workgroup its (view, tile).
@@ -152,7 +157,8 @@ hipError_t launch_l1_sum(const float *a, const float *b, int64_t count, float *o
 
 // (1 - lambda) L1 + lambda (1 - SSIM) of C-channel W x H images (k_loss.hip): dL/dimage into
 // out, the loss into *loss when loss != nullptr. dmu/dexx/dexy: C*W*H scratch floats each,
-// sums: 2 scratch floats.
+// sums: dssim_partial_count(C, W, H) scratch floats (used only when loss != nullptr).
+size_t dssim_partial_count(int C, int W, int H);
 hipError_t launch_l1_dssim_grad(const float *img, const float *ref, int C, int W, int H, float lambda, float *dmu,
                                 float *dexx, float *dexy, float *sums, float *out, float *loss, hipStream_t st);
 hipError_t launch_wave_reduce_selftest(const float *vals, const uint8_t *active, int n_waves, int mode,
@@ -196,6 +202,7 @@ struct gsr_fwd {
     uint32_t *totals = nullptr;         // [0] P, [1] n_visible, [2] overflow flag
     uint32_t *dsort_hist = nullptr, *dsort_partials = nullptr, *scan_partials = nullptr;
     uint32_t *tsort_hist = nullptr, *tsort_partials = nullptr;
+    uint32_t *vis_flags = nullptr;      // radius > 0, for the compaction before the depth sort
     uint2 *ranges = nullptr;
     uint32_t *tile_walk = nullptr; // deepest n_contrib per tile (ordered renders)
     uint2 *order_bwd = nullptr;    // this view's tiles by decreasing walk (single-view backward)

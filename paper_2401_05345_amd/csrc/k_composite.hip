@@ -507,40 +507,39 @@ hipError_t fwd_t(const ViewBatch &vb, int remap, const uint2 *work, hipStream_t 
     return hipGetLastError();
 }
 
+template <int TILE, int BATCH, typename AccT>
+hipError_t bwd_acc(const dim3 grid, const ViewBatch &vb, int remap, int mode, bool count, bool split,
+                   const BwdParams &p, const uint2 *work, hipStream_t st) {
+    const dim3 block(TILE * TILE);
+#define GSR_BWD(M, C, S) composite_bwd_kernel<TILE, BATCH, M, C, S, AccT><<<grid, block, 0, st>>>(vb, remap, work, p)
+    if (mode == GSR_BWD_PLAIN_ATOMIC) {
+        if (count) GSR_BWD(GSR_BWD_PLAIN_ATOMIC, true, false);
+        else GSR_BWD(GSR_BWD_PLAIN_ATOMIC, false, false);
+    } else if (mode == GSR_BWD_SERIAL_REDUCE) {
+        if (count) GSR_BWD(GSR_BWD_SERIAL_REDUCE, true, true);
+        else GSR_BWD(GSR_BWD_SERIAL_REDUCE, false, true);
+    } else if (mode == GSR_BWD_BLOCK_REDUCE) {
+        if (count) GSR_BWD(GSR_BWD_BLOCK_REDUCE, true, true);
+        else GSR_BWD(GSR_BWD_BLOCK_REDUCE, false, true);
+    } else if (split) {
+        if (count) GSR_BWD(GSR_BWD_WAVE_REDUCE, true, true);
+        else GSR_BWD(GSR_BWD_WAVE_REDUCE, false, true);
+    } else {
+        if (count) GSR_BWD(GSR_BWD_WAVE_REDUCE, true, false);
+        else GSR_BWD(GSR_BWD_WAVE_REDUCE, false, false);
+    }
+#undef GSR_BWD
+    return hipGetLastError();
+}
+
 template <int TILE, int BATCH>
 hipError_t bwd_t(const ViewBatch &vb, int remap, int mode, bool count, bool split, bool f64, const BwdParams &p,
                  const uint2 *work, hipStream_t st) {
     const int n_tiles = vb.v[0].cam.grid_x * vb.v[0].cam.grid_y;
-    const dim3 grid(work ? vb.base[vb.n] : (unsigned)grid_for_tiles(n_tiles, remap)), block(TILE * TILE);
+    const dim3 grid(work ? vb.base[vb.n] : (unsigned)grid_for_tiles(n_tiles, remap));
     if (grid.x == 0) return hipSuccess;
-#define GSR_BWD(M, C, S, A) composite_bwd_kernel<TILE, BATCH, M, C, S, A><<<grid, block, 0, st>>>(vb, remap, work, p)
-    if (f64) {
-        // fp64 accumulators: plain atomics, or the butterfly with lanes 0..8 issuing.
-        if (mode == GSR_BWD_PLAIN_ATOMIC) {
-            if (count) GSR_BWD(GSR_BWD_PLAIN_ATOMIC, true, false, double);
-            else GSR_BWD(GSR_BWD_PLAIN_ATOMIC, false, false, double);
-        } else {
-            if (count) GSR_BWD(GSR_BWD_WAVE_REDUCE, true, true, double);
-            else GSR_BWD(GSR_BWD_WAVE_REDUCE, false, true, double);
-        }
-    } else if (mode == GSR_BWD_PLAIN_ATOMIC) {
-        if (count) GSR_BWD(GSR_BWD_PLAIN_ATOMIC, true, false, float);
-        else GSR_BWD(GSR_BWD_PLAIN_ATOMIC, false, false, float);
-    } else if (mode == GSR_BWD_SERIAL_REDUCE) {
-        if (count) GSR_BWD(GSR_BWD_SERIAL_REDUCE, true, true, float);
-        else GSR_BWD(GSR_BWD_SERIAL_REDUCE, false, true, float);
-    } else if (mode == GSR_BWD_BLOCK_REDUCE) {
-        if (count) GSR_BWD(GSR_BWD_BLOCK_REDUCE, true, true, float);
-        else GSR_BWD(GSR_BWD_BLOCK_REDUCE, false, true, float);
-    } else if (split) {
-        if (count) GSR_BWD(GSR_BWD_WAVE_REDUCE, true, true, float);
-        else GSR_BWD(GSR_BWD_WAVE_REDUCE, false, true, float);
-    } else {
-        if (count) GSR_BWD(GSR_BWD_WAVE_REDUCE, true, false, float);
-        else GSR_BWD(GSR_BWD_WAVE_REDUCE, false, false, float);
-    }
-#undef GSR_BWD
-    return hipGetLastError();
+    return f64 ? bwd_acc<TILE, BATCH, double>(grid, vb, remap, mode, count, split, p, work, st)
+               : bwd_acc<TILE, BATCH, float>(grid, vb, remap, mode, count, split, p, work, st);
 }
 
 } // namespace

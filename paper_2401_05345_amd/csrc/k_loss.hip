@@ -104,14 +104,17 @@ __global__ __launch_bounds__(TX *TY) void ssim_stage1_kernel(const float *__rest
         part[1][tid >> 6] = l1;
     }
     __syncthreads();
-    if (tid == 0) {
+    if (tid == 0 && sums) {
+        // One partial pair per block (a same-address atomic per block would serialise
+        // thousands of adds at one L2 line); ssim_finalize_kernel sums them.
         float a = 0.f, b = 0.f;
         for (int i = 0; i < TX * TY / 64; ++i) {
             a += part[0][i];
             b += part[1][i];
         }
-        atomicAdd(&sums[0], a);
-        atomicAdd(&sums[1], b);
+        const size_t blk = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+        sums[2 * blk] = a;
+        sums[2 * blk + 1] = b;
     }
 }
 
@@ -168,9 +171,27 @@ __global__ __launch_bounds__(TX *TY) void ssim_stage2_kernel(const float *__rest
     out[o] = l1_scale * sgn - ssim_scale * dS;
 }
 
-__global__ void ssim_finalize_kernel(const float *sums, float inv_n, float lambda, float *loss) {
-    if (threadIdx.x == 0 && blockIdx.x == 0)
-        loss[0] = (1.0f - lambda) * sums[1] * inv_n + lambda * (1.0f - sums[0] * inv_n);
+// One block: the loss from the per-block partial sums (SSIM, |x - y|), in fp64.
+__global__ __launch_bounds__(256) void ssim_finalize_kernel(const float *sums, int64_t n_blocks, double inv_n,
+                                                             float lambda, float *loss) {
+    __shared__ double red[2][256];
+    double a = 0.0, b = 0.0;
+    for (int64_t i = threadIdx.x; i < n_blocks; i += 256) {
+        a += (double)sums[2 * i];
+        b += (double)sums[2 * i + 1];
+    }
+    red[0][threadIdx.x] = a;
+    red[1][threadIdx.x] = b;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + w];
+            red[1][threadIdx.x] += red[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        loss[0] = (float)((1.0 - (double)lambda) * red[1][0] * inv_n + (double)lambda * (1.0 - red[0][0] * inv_n));
 }
 
 } // namespace
@@ -186,20 +207,24 @@ hipError_t launch_l1_dssim_grad(const float *img, const float *ref, int C, int W
         tot += w[k];
     }
     for (int k = 0; k <= 2 * R; ++k) g.w[k] = (float)(w[k] / tot);
-    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(sums), 0u, 2, st);
-    if (e != hipSuccess) return e;
     const dim3 grid((W + TX - 1) / TX, (H + TY - 1) / TY, C), block(TX * TY);
-    ssim_stage1_kernel<<<grid, block, 0, st>>>(img, ref, W, H, g, dmu, dexx, dexy, sums);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // Per-block partial sums only when the loss value is wanted.
+    ssim_stage1_kernel<<<grid, block, 0, st>>>(img, ref, W, H, g, dmu, dexx, dexy, loss ? sums : nullptr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     const double n = (double)C * W * H;
     ssim_stage2_kernel<<<grid, block, 0, st>>>(img, ref, W, H, g, dmu, dexx, dexy, (float)((1.0 - lambda) / n),
                                                (float)(lambda / n), out);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (loss) {
-        ssim_finalize_kernel<<<1, 64, 0, st>>>(sums, (float)(1.0 / n), lambda, loss);
+        ssim_finalize_kernel<<<1, 256, 0, st>>>(sums, (int64_t)grid.x * grid.y * grid.z, 1.0 / n, lambda, loss);
         e = hipGetLastError();
     }
     return e;
+}
+
+size_t dssim_partial_count(int C, int W, int H) {
+    return 2 * (size_t)((W + TX - 1) / TX) * ((H + TY - 1) / TY) * (C > 0 ? C : 1);
 }
 
 } // namespace gsr

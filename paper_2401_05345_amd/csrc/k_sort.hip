@@ -262,27 +262,58 @@ hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *
 // ---------------------------------------------------------------------------
 namespace {
 
+// One thread per depth-ordered Gaussian writes its rectangle's pairs (row by
+// row). Rectangles of more than 32 tiles - the few Gaussians that cover much
+// of the screen - would hold their wave for thousands of serial stores, so
+// they are written by the whole wave instead, one rectangle at a time, lanes
+// striding over its tiles; the pair order is the same either way.
 __global__ __launch_bounds__(256) void emit_pairs_kernel(int64_t n, const uint32_t *sorted_ids,
                                                           const uint32_t *offsets, const float4 *rec,
                                                           const int32_t *radius, DevCamera cam, uint32_t *pair_tile,
                                                           uint32_t *pair_id, uint32_t cap) {
+    constexpr int kSerialMax = 32;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t g = sorted_ids[i];
-    const int r = radius[g];
-    if (r <= 0) return;
-    const float4 r0 = rec[3 * (int64_t)g];
-    int x0, x1, y0, y1;
-    rect_of(r0.x, r0.y, r, cam, x0, x1, y0, y1);
-    uint32_t o = offsets[i];
-    for (int ty = y0; ty < y1; ++ty)
-        for (int tx = x0; tx < x1; ++tx) {
-            if (o < cap) { // pairs past the buffer's capacity are dropped (and flagged by pad_pairs)
-                pair_tile[o] = (uint32_t)(ty * cam.grid_x + tx);
-                pair_id[o] = g;
+    const int lane = threadIdx.x & 63;
+    int x0 = 0, x1 = 0, y0 = 0, y1 = 0;
+    uint32_t o = 0, g = 0;
+    bool big = false;
+    if (i < n) {
+        g = sorted_ids[i];
+        const int r = radius[g];
+        if (r > 0) {
+            const float4 r0 = rec[3 * (int64_t)g];
+            rect_of(r0.x, r0.y, r, cam, x0, x1, y0, y1);
+            o = offsets[i];
+            if ((x1 - x0) * (y1 - y0) > kSerialMax) {
+                big = true;
+            } else {
+                uint32_t oo = o;
+                for (int ty = y0; ty < y1; ++ty)
+                    for (int tx = x0; tx < x1; ++tx) {
+                        if (oo < cap) { // pairs past the buffer's capacity are dropped (pad_pairs flags it)
+                            pair_tile[oo] = (uint32_t)(ty * cam.grid_x + tx);
+                            pair_id[oo] = g;
+                        }
+                        ++oo;
+                    }
             }
-            ++o;
         }
+    }
+    for (uint64_t bigm = __ballot(big); bigm; bigm &= bigm - 1) {
+        const int l = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(bigm));
+        const int bx0 = __builtin_amdgcn_readlane(x0, l), bx1 = __builtin_amdgcn_readlane(x1, l);
+        const int by0 = __builtin_amdgcn_readlane(y0, l), by1 = __builtin_amdgcn_readlane(y1, l);
+        const uint32_t bo = (uint32_t)__builtin_amdgcn_readlane((int)o, l);
+        const uint32_t bg = (uint32_t)__builtin_amdgcn_readlane((int)g, l);
+        const int w = bx1 - bx0, cnt = w * (by1 - by0);
+        for (int k = lane; k < cnt; k += 64) {
+            const uint32_t oo = bo + (uint32_t)k;
+            if (oo < cap) {
+                pair_tile[oo] = (uint32_t)((by0 + k / w) * cam.grid_x + bx0 + k % w);
+                pair_id[oo] = bg;
+            }
+        }
+    }
 }
 
 // Capacity mode: entries [total, cap) get the sentinel tile (sorted last, ignored by the
@@ -364,11 +395,41 @@ __global__ __launch_bounds__(256) void count_positive_kernel(const int32_t *r, i
 
 } // namespace
 
+// flags[i] = (r[i] > 0)
+__global__ __launch_bounds__(256) void positive_flags_kernel(const int32_t *r, int64_t n, uint32_t *flags) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) flags[i] = r[i] > 0 ? 1u : 0u;
+}
+
+// Entry i with flags[i] set goes to position pos[i]: (key[i], i).
+__global__ __launch_bounds__(256) void compact_keys_kernel(const uint32_t *flags, const uint32_t *pos, int64_t n,
+                                                            const uint32_t *key, uint32_t *key_out, uint32_t *id_out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && flags[i]) {
+        key_out[pos[i]] = key[i];
+        id_out[pos[i]] = (uint32_t)i;
+    }
+}
+
+hipError_t launch_positive_flags(const int32_t *r, int64_t n, uint32_t *flags, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    positive_flags_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(r, n, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact_keys(const uint32_t *flags, const uint32_t *pos, int64_t n, const uint32_t *key,
+                               uint32_t *key_out, uint32_t *id_out, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    compact_keys_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(flags, pos, n, key, key_out, id_out);
+    return hipGetLastError();
+}
+
 hipError_t launch_count_positive(const int32_t *r, int64_t n, uint32_t *out, hipStream_t st) {
     hipError_t e = launch_fill_u32(out, 0u, 1, st);
     if (e != hipSuccess || n <= 0) return e;
+    // Few blocks: each adds its count to one address, and same-address atomics serialise.
     int64_t blocks = (n + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
+    if (blocks > 256) blocks = 256;
     count_positive_kernel<<<(unsigned)blocks, 256, 0, st>>>(r, n, out);
     return hipGetLastError();
 }

@@ -90,8 +90,9 @@ hipError_t launch_uniform(float *out, int64_t count, uint64_t seed, hipStream_t 
 
 hipError_t launch_l1_sum(const float *a, const float *b, int64_t count, float *out, hipStream_t st) {
     if (count <= 0) return hipSuccess;
+    // Few blocks: each adds its partial sum to one address (same-address atomics serialise).
     int64_t blocks = (count + 255) / 256;
-    if (blocks > 1024) blocks = 1024;
+    if (blocks > 256) blocks = 256;
     l1_sum_kernel<<<(unsigned)blocks, 256, 0, st>>>(a, b, count, out);
     return hipGetLastError();
 }

@@ -184,10 +184,7 @@ gsr_status gsr_validate_config(const gsr_config *cf, const gsr_camera *c) {
     if (cf->bwd_mode < GSR_BWD_PLAIN_ATOMIC || cf->bwd_mode > GSR_BWD_BLOCK_REDUCE) return GSR_EINVAL;
     if (cf->reduce_threshold < 0 || cf->reduce_threshold > 65) return GSR_EINVAL;
     if (cf->flags & ~(GSR_FLAG_DEBUG_COUNTERS | GSR_FLAG_XCD_REMAP | GSR_FLAG_STAGE_TIMING |
-                      GSR_FLAG_LANE_SPLIT_ATOMICS | GSR_FLAG_NO_TILE_ORDER | GSR_FLAG_ACC_F64))
-        return GSR_EINVAL;
-    // fp64 accumulators exist for the plain and the butterfly modes.
-    if ((cf->flags & GSR_FLAG_ACC_F64) && cf->bwd_mode != GSR_BWD_PLAIN_ATOMIC && cf->bwd_mode != GSR_BWD_WAVE_REDUCE)
+                      GSR_FLAG_LANE_SPLIT_ATOMICS | GSR_FLAG_NO_TILE_ORDER | GSR_FLAG_ACC_F32))
         return GSR_EINVAL;
     if (c) {
         const int64_t tiles = (int64_t)((c->width + cf->tile - 1) / cf->tile) * ((c->height + cf->tile - 1) / cf->tile);
@@ -324,6 +321,7 @@ gsr_status alloc_view(gsr_ctx *ctx, gsr_fwd *st) {
         GSR_TRY(pool_alloc(ctx, st, &st->dsort_partials, scan_partial_count((int64_t)hc)));
     }
     GSR_TRY(pool_alloc(ctx, st, &st->scan_partials, scan_partial_count(nn) + 8));
+    GSR_TRY(pool_alloc(ctx, st, &st->vis_flags, nn));
     return GSR_OK;
 }
 
@@ -443,19 +441,47 @@ gsr_status render_views(gsr_ctx *ctx, int nv, const gsr_scene *scenes, const gsr
         st->n_tiles = (int64_t)st->dcam.grid_x * st->dcam.grid_y;
         GSR_RT(alloc_view(ctx, st));
     }
-    GSR_RT(enqueue_project_and_depth_sort(ctx, nv, sts, tm));
-    // The totals P of all views are read back at once to size the pair buffers.
-    for (int v = 0; v < nv; ++v)
-        GSR_RH(hipMemcpyAsync(ctx->host_pinned + 2 * v, sts[v]->totals, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost,
-                              s));
+    mark(ctx, tm, EV_R0);
+    // a1: projection
+    for (int v = 0; v < nv; ++v) {
+        gsr_fwd *st = sts[v];
+        GSR_RH(launch_preprocess_fwd(st->scene, st->dcam, st->rec, st->radius, st->tiles_touched, st->depth_key,
+                                     st->ids, st->clamp_mask, s));
+    }
+    mark(ctx, tm, EV_R1);
+    // Visible Gaussians are compacted (index order) before the depth sort, and the pair count
+    // P = sum of tile counts taken; the counts of all views are read back at once.
+    for (int v = 0; v < nv; ++v) {
+        gsr_fwd *st = sts[v];
+        GSR_RH(launch_positive_flags(st->radius, st->n, st->vis_flags, s));
+        GSR_RH(device_exclusive_scan(st->vis_flags, nullptr, st->offsets, st->n, st->totals + 1, st->scan_partials, s));
+        GSR_RH(launch_compact_keys(st->vis_flags, st->offsets, st->n, st->depth_key, st->key_alt, st->ids_alt, s));
+        GSR_RH(device_exclusive_scan(st->tiles_touched, nullptr, st->offsets, st->n, st->totals, st->scan_partials,
+                                     s));
+        GSR_RH(hipMemcpyAsync(ctx->host_pinned + 2 * v, st->totals, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    }
     GSR_RH(hipStreamSynchronize(s));
     for (int v = 0; v < nv; ++v) {
         gsr_fwd *st = sts[v];
         st->P = st->n > 0 ? (int64_t)ctx->host_pinned[2 * v] : 0;
         st->n_visible = st->n > 0 ? (int64_t)ctx->host_pinned[2 * v + 1] : 0;
         st->p_known = true;
+        // a2/a3 (depth digits): stable sort of the visible Gaussians by fp32 depth (ties keep
+        // index order).
+        int which = 0;
+        if (st->n_visible > 1)
+            GSR_RH(radix_sort_pairs(st->key_alt, st->ids_alt, st->depth_key, st->ids, st->n_visible, 32,
+                                    st->dsort_hist, st->dsort_partials, &which, s));
+        st->sorted_ids_by_depth = which ? st->ids : st->ids_alt;
+    }
+    mark(ctx, tm, EV_R2);
+    // a2: pair offsets in depth order and the pairs.
+    for (int v = 0; v < nv; ++v) {
+        gsr_fwd *st = sts[v];
+        GSR_RH(device_exclusive_scan(st->tiles_touched, st->sorted_ids_by_depth, st->offsets, st->n_visible,
+                                     st->totals, st->scan_partials, s));
         GSR_RT(alloc_pairs(ctx, st, pair_capacity(st->P)));
-        GSR_RH(launch_emit_pairs(st->n, st->sorted_ids_by_depth, st->offsets, st->rec, st->radius, st->dcam,
+        GSR_RH(launch_emit_pairs(st->n_visible, st->sorted_ids_by_depth, st->offsets, st->rec, st->radius, st->dcam,
                                  st->pair_tile, st->pair_id, st->pair_cap, s));
     }
     mark(ctx, tm, EV_R3);
@@ -580,7 +606,7 @@ gsr_status bwd_enqueue(gsr_ctx *ctx, int nv, gsr_fwd *const *sts, const gsr_conf
                        bool tm) {
     hipStream_t s = ctx->stream;
     const bool count = (cfg->flags & GSR_FLAG_DEBUG_COUNTERS) != 0;
-    const bool f64 = (cfg->flags & GSR_FLAG_ACC_F64) != 0;
+    const bool f64 = (cfg->flags & GSR_FLAG_ACC_F32) == 0;
     for (int v = 0; v < nv; ++v) sts[v]->counters_valid = false;
     mark(ctx, tm, EV_B0);
     for (int v = 0; v < nv; ++v) {
@@ -939,7 +965,7 @@ gsr_status gsr_graph_capture_step(gsr_ctx *ctx, int32_t n_views, gsr_fwd *const 
                 const gsr_status e = graph_alloc(ctx, gr, &scratch[v][k], n3);
                 if (e != GSR_OK) return bail(e);
             }
-            const gsr_status e = graph_alloc(ctx, gr, &scratch[v][3], 2);
+            const gsr_status e = graph_alloc(ctx, gr, &scratch[v][3], 2);  // loss value not produced
             if (e != GSR_OK) return bail(e);
         }
     const float *dls_c[kMaxViews];
@@ -1130,7 +1156,7 @@ gsr_status gsr_l1_dssim_grad(gsr_ctx *ctx, const float *image, const float *targ
     GSR_TRY(temp_alloc(ctx, t0, &dmu, n));
     GSR_TRY(temp_alloc(ctx, t1, &dexx, n));
     GSR_TRY(temp_alloc(ctx, t2, &dexy, n));
-    GSR_TRY(temp_alloc(ctx, t3, &sums, 2));
+    GSR_TRY(temp_alloc(ctx, t3, &sums, dssim_partial_count(3, width, height)));
     GSR_HIP(ctx, launch_l1_dssim_grad(image, target, 3, width, height, lambda, dmu, dexx, dexy, sums, dl_dimage, loss,
                                       ctx->stream));
     return GSR_OK;

@@ -23,7 +23,7 @@ GSR_FLAG_XCD_REMAP = 2
 GSR_FLAG_STAGE_TIMING = 4
 GSR_FLAG_LANE_SPLIT_ATOMICS = 8
 GSR_FLAG_NO_TILE_ORDER = 16
-GSR_FLAG_ACC_F64 = 32
+GSR_FLAG_ACC_F32 = 32
 GSR_MAX_BATCH = 16
 GSR_EBUDGET = -5
 GSR_ACC_STRIDE = 16

@@ -107,22 +107,20 @@ def test_autograd_full_large_view_equals_direct_backward(renderer):
         assert np.array_equal(out["image"], img.detach().cpu().numpy())   # same forward, bit for bit
         grads, _, _ = run_backward(renderer, gs, st, dl, cfg)
         again, _, _ = run_backward(renderer, gs, st, dl, cfg)
-        # fp64 accumulators: the atomic order no longer shows
-        cfg64 = gsr.make_config(16, 256, gsr.GSR_BWD_WAVE_REDUCE, 4,
-                                gsr.GSR_FLAG_LANE_SPLIT_ATOMICS | gsr.GSR_FLAG_ACC_F64)
-        d64a, _, _ = run_backward(renderer, gs, st, dl, cfg64)
-        d64b, _, _ = run_backward(renderer, gs, st, dl, cfg64)
+        # fp32 accumulators (the paper's setting): the order of the atomic adds shows
+        cfg32 = gsr.make_config(16, 256, gsr.GSR_BWD_WAVE_REDUCE, 4,
+                                gsr.GSR_FLAG_LANE_SPLIT_ATOMICS | gsr.GSR_FLAG_ACC_F32)
+        d32a, _, _ = run_backward(renderer, gs, st, dl, cfg32)
+        d32b, _, _ = run_backward(renderer, gs, st, dl, cfg32)
     finally:
         gsr.gsr_fwd_release(renderer.ctx, st)
-    for name, a, b, g in zip(NAMES, d64a, d64b, grads):
-        f64_floor, f32_vs_64 = rel_l2(b, a), rel_l2(g, a)
-        say(f"[gpu] full 3M {name}: fp64-accumulator runs differ by {f64_floor:.2e}; fp32 vs fp64 {f32_vs_64:.2e}")
-        assert f64_floor <= 1e-5, (name, f64_floor)
-    # Same sums in another atomic order: the difference is of the size of two direct runs'
-    # difference (fp32 reordering of 3M Gaussians' sums with cancellation), within the gradient
-    # tolerance of the path.
-    for name, p, g, h in zip(NAMES, params, grads, again):
-        e = rel_l2(p.grad.cpu().numpy(), g)
-        floor = rel_l2(h, g)
-        say(f"[gpu] full 3M {name}: autograd vs direct {e:.2e}, direct vs direct {floor:.2e}")
-        assert e <= max(1e-3, 1.5 * floor), (name, e, floor)
+    # fp64 accumulators (the default): autograd and two direct runs give the same sums; the
+    # fp32 runs differ from each other and from them by the atomic-order noise, which stays
+    # within the gradient tolerance of the path (or near its own run-to-run size).
+    for name, p, g, h, a32, b32 in zip(NAMES, params, grads, again, d32a, d32b):
+        e, floor64 = rel_l2(p.grad.cpu().numpy(), g), rel_l2(h, g)
+        floor32, e32 = rel_l2(b32, a32), rel_l2(a32, g)
+        say(f"[gpu] full 3M {name}: autograd vs direct {e:.2e}, direct runs {floor64:.2e} (fp64 acc); "
+            f"fp32 acc runs {floor32:.2e}, fp32 vs fp64 {e32:.2e}")
+        assert e <= 1e-5 and floor64 <= 1e-5, (name, e, floor64)
+        assert e32 <= max(1e-3, 2.0 * floor32), (name, e32, floor32)

@@ -108,16 +108,16 @@ def test_large_3m_1080p_sampled_parity(renderer):
         for n, e in errs.items():
             assert e <= 1e-3, (n, e)
 
-        # The plain-atomic kernel gives the same sums (up to summation order) on the whole frame.
-        g_plain, acc_plain, _ = run_backward(renderer, gs, st, dl, gsr.make_config(16, 256, gsr.GSR_BWD_PLAIN_ATOMIC, 0))
-        assert rel_l2(acc_plain, acc) <= 1e-5
-        # With fp64 accumulators the two modes differ only by the fp32 rounding of each wave's sum.
-        f64 = gsr.GSR_FLAG_ACC_F64
-        _, acc64, _ = run_backward(renderer, gs, st, dl, gsr.make_config(16, 256, gsr.GSR_BWD_WAVE_REDUCE, 4,
-                                                                           f64 | gsr.GSR_FLAG_LANE_SPLIT_ATOMICS))
-        _, acc64p, _ = run_backward(renderer, gs, st, dl, gsr.make_config(16, 256, gsr.GSR_BWD_PLAIN_ATOMIC, 0, f64))
-        e64 = rel_l2(acc64p, acc64)
-        say(f"[gpu] large_3m acc plain vs reduce: fp32 {rel_l2(acc_plain, acc):.2e}, fp64 accumulators {e64:.2e}")
-        assert e64 <= 1e-5
+        # The plain-atomic kernel gives the same sums on the whole frame: with the default fp64
+        # accumulators up to the fp32 rounding of each wave's sum, with fp32 accumulators (the
+        # paper's setting) up to the order of the atomic adds as well.
+        F32 = gsr.GSR_FLAG_ACC_F32
+        _, acc_plain, _ = run_backward(renderer, gs, st, dl, gsr.make_config(16, 256, gsr.GSR_BWD_PLAIN_ATOMIC, 0))
+        _, acc32, _ = run_backward(renderer, gs, st, dl, gsr.make_config(16, 256, gsr.GSR_BWD_WAVE_REDUCE, 4,
+                                                                           F32 | gsr.GSR_FLAG_LANE_SPLIT_ATOMICS))
+        _, acc32p, _ = run_backward(renderer, gs, st, dl, gsr.make_config(16, 256, gsr.GSR_BWD_PLAIN_ATOMIC, 0, F32))
+        e64, e32 = rel_l2(acc_plain, acc), rel_l2(acc32p, acc32)
+        say(f"[gpu] large_3m acc plain vs reduce: fp64 accumulators {e64:.2e}, fp32 accumulators {e32:.2e}")
+        assert e64 <= 1e-5 and e32 <= 1e-5
     finally:
         gsr.gsr_fwd_release(renderer.ctx, st)

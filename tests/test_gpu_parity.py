@@ -102,8 +102,9 @@ def _workload_tiny():
     (gsr.GSR_BWD_SERIAL_REDUCE, 24, 0),
     (gsr.GSR_BWD_BLOCK_REDUCE, 1, 0),
     (gsr.GSR_BWD_BLOCK_REDUCE, 32, 0),
-    (gsr.GSR_BWD_PLAIN_ATOMIC, 0, gsr.GSR_FLAG_ACC_F64),
-    (gsr.GSR_BWD_WAVE_REDUCE, 4, gsr.GSR_FLAG_ACC_F64),
+    (gsr.GSR_BWD_PLAIN_ATOMIC, 0, gsr.GSR_FLAG_ACC_F32),
+    (gsr.GSR_BWD_WAVE_REDUCE, 4, gsr.GSR_FLAG_ACC_F32 | gsr.GSR_FLAG_LANE_SPLIT_ATOMICS),
+    (gsr.GSR_BWD_BLOCK_REDUCE, 1, gsr.GSR_FLAG_ACC_F32),
 ])
 def test_tiny_parity(renderer, mode, thr, flags):
     say(f"[gpu] tiny_1k parity mode={mode} thr={thr} flags={flags}")
@@ -183,7 +184,9 @@ def test_object_100k_parity_and_modes(renderer):
         say(f"[gpu] object_100k image rel-L2 {img_err:.3e}, tie pixels {ties.sum()}")
         for mode, thr, flags in [(gsr.GSR_BWD_WAVE_REDUCE, 32, 0), (gsr.GSR_BWD_PLAIN_ATOMIC, 0, 0),
                                  (gsr.GSR_BWD_WAVE_REDUCE, 1, gsr.GSR_FLAG_LANE_SPLIT_ATOMICS),
-                                 (gsr.GSR_BWD_SERIAL_REDUCE, 1, 0), (gsr.GSR_BWD_BLOCK_REDUCE, 1, 0)]:
+                                 (gsr.GSR_BWD_SERIAL_REDUCE, 1, 0), (gsr.GSR_BWD_BLOCK_REDUCE, 1, 0),
+                                 (gsr.GSR_BWD_WAVE_REDUCE, 1, gsr.GSR_FLAG_LANE_SPLIT_ATOMICS | gsr.GSR_FLAG_ACC_F32),
+                                 (gsr.GSR_BWD_PLAIN_ATOMIC, 0, gsr.GSR_FLAG_ACC_F32)]:
             grads, acc, _ = run_backward(renderer, gs, st, dl, gsr.make_config(16, 256, mode, thr, flags))
             errs = _check_grads(grads, acc, acc_ref, grads_ref)
             say(f"[gpu] object_100k mode={mode} thr={thr} grad rel-L2 {errs}")

@@ -27,10 +27,9 @@ GiB = 1 << 30
 
 
 def cfg():
-    # fp64 accumulators: the server's and the direct path's sums agree to rounding, not to the
-    # fp32 atomic-order noise (1e-5 relative and more at scale).
-    return gsr.make_config(16, 256, gsr.GSR_BWD_WAVE_REDUCE, 4,
-                           gsr.GSR_FLAG_LANE_SPLIT_ATOMICS | gsr.GSR_FLAG_ACC_F64)
+    # fp64 accumulators (the default): the server's and the direct path's sums agree to
+    # rounding, not to the fp32 atomic-order noise (1e-5 relative and more at scale).
+    return gsr.make_config(16, 256, gsr.GSR_BWD_WAVE_REDUCE, 4, gsr.GSR_FLAG_LANE_SPLIT_ATOMICS)
 
 
 @pytest.fixture(scope="module")
