@@ -140,7 +140,8 @@ typedef struct {
  *  ranges [G,2] uint32 half-open [start,end) into sorted_ids,
  *  T_final [HW], n_contrib [HW] uint32 (1-based list position of the last
  *  composited entry, 0 = none), acc [n,GSR_ACC_STRIDE] (accumulators of the
- *  last backward). */
+ *  last backward as fp32, whatever their precision; rows of culled Gaussians
+ *  read 0). */
 typedef struct {
     float *mean2d;
     float *conic_opacity;

@@ -64,8 +64,11 @@ hipError_t launch_preprocess_fwd(const gsr_scene &s, const DevCamera &cam, float
 hipError_t launch_preprocess_bwd(const gsr_scene &s, const DevCamera &cam, const int32_t *radius, const void *acc,
                                  bool acc_f64, const gsr_grads &out, int accumulate, hipStream_t st);
 
-// dst[i] = (float)src[i] for count values.
-hipError_t launch_f64_to_f32(const double *src, float *dst, int64_t count, hipStream_t st);
+// Zero the accumulator rows of Gaussians with radius > 0 (the only rows the composite writes).
+hipError_t launch_zero_visible_rows(const int32_t *radius, int64_t n, void *acc, bool acc_f64, hipStream_t st);
+// Accumulators as fp32 [n][GSR_ACC_STRIDE], rows of culled Gaussians as zeros.
+hipError_t launch_export_acc(const int32_t *radius, int64_t n, const void *acc, bool acc_f64, float *dst,
+                             hipStream_t st);
 
 // Exclusive scan of n uint32 values (in[gather[i]] when gather != nullptr).
 // total (device, may be nullptr) receives the sum. Scratch sized by scan_scratch_count.

@@ -212,24 +212,42 @@ __global__ __launch_bounds__(TILE *TILE) void composite_fwd_kernel(ViewBatch vb,
         wave_visit_masks<BATCH>(s0, s1, s2, cnt, qcx, qcy, lane, vis);
 #pragma unroll
         for (int q = 0; q < BATCH / 64; ++q) {
-            for (uint64_t mq = vis[q]; mq && !done;) {
-                const int j = q * 64 + __builtin_ctzll(mq);
-                mq &= mq - 1;
-                const float4 a = s0[j], c = s2[j];
-                const float4 b = s1[j];
-                const SplatEval e = eval_splat(fpx, fpy, a.x, a.y, a.z, a.w, b.x, b.y);
-                if (!e.pass) continue;
-                const float Tn = T * (1.0f - e.alpha);
-                if (Tn < kTStop) {
-                    done = true;
-                    break;
+            uint64_t mq = vis[q];
+            if (!mq || done) continue;
+            int bit = __builtin_ctzll(mq);
+            mq &= mq - 1;
+            float4 a = s0[q * 64 + bit], b = s1[q * 64 + bit], c = s2[q * 64 + bit];
+            for (;;) {
+                const int j = q * 64 + bit;
+                // The next visited entry's record is read before this one is processed.
+                int bn = -1;
+                float4 na = a, nb = b, nc = c;
+                if (mq) {
+                    bn = __builtin_ctzll(mq);
+                    mq &= mq - 1;
+                    na = s0[q * 64 + bn];
+                    nb = s1[q * 64 + bn];
+                    nc = s2[q * 64 + bn];
                 }
-                const float w = e.alpha * T;
-                c0 = fmaf(w, b.z, c0);
-                c1 = fmaf(w, b.w, c1);
-                c2 = fmaf(w, c.x, c2);
-                T = Tn;
-                last = start - rg.x + (uint32_t)j + 1;
+                const SplatEval e = eval_splat(fpx, fpy, a.x, a.y, a.z, a.w, b.x, b.y);
+                if (e.pass) {
+                    const float Tn = T * (1.0f - e.alpha);
+                    if (Tn < kTStop) {
+                        done = true;
+                    } else {
+                        const float w = e.alpha * T;
+                        c0 = fmaf(w, b.z, c0);
+                        c1 = fmaf(w, b.w, c1);
+                        c2 = fmaf(w, c.x, c2);
+                        T = Tn;
+                        last = start - rg.x + (uint32_t)j + 1;
+                    }
+                }
+                if (bn < 0 || done) break;
+                bit = bn;
+                a = na;
+                b = nb;
+                c = nc;
             }
         }
     }

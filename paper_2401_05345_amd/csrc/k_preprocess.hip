@@ -447,15 +447,43 @@ hipError_t launch_preprocess_bwd(const gsr_scene &s, const DevCamera &cam, const
 }
 
 namespace {
-__global__ __launch_bounds__(256) void f64_to_f32_kernel(const double *src, float *dst, int64_t count) {
+// Rows of the Gaussians that can appear in a tile list (radius > 0) are the only ones the
+// backward composite adds into and a7 reads: only they are cleared.
+__global__ __launch_bounds__(256) void zero_visible_rows_kernel(const int32_t *radius, int64_t n, uint4 *acc,
+                                                                 int chunks_per_row) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < count) dst[i] = (float)src[i];
+    if (i >= n || radius[i] <= 0) return;
+    uint4 *row = acc + i * chunks_per_row;
+    for (int c = 0; c < chunks_per_row; ++c) row[c] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// dst[i][k] = acc[i][k] as fp32, 0 for rows never written (radius <= 0).
+template <typename AccT>
+__global__ __launch_bounds__(256) void export_acc_kernel(const int32_t *radius, int64_t n, const AccT *acc,
+                                                          float *dst) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * GSR_ACC_STRIDE) return;
+    const int64_t i = t / GSR_ACC_STRIDE;
+    dst[t] = radius[i] > 0 ? (float)acc[t] : 0.0f;
 }
 } // namespace
 
-hipError_t launch_f64_to_f32(const double *src, float *dst, int64_t count, hipStream_t st) {
-    if (count <= 0) return hipSuccess;
-    f64_to_f32_kernel<<<(unsigned)((count + 255) / 256), 256, 0, st>>>(src, dst, count);
+hipError_t launch_zero_visible_rows(const int32_t *radius, int64_t n, void *acc, bool acc_f64, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int chunks = GSR_ACC_STRIDE * (acc_f64 ? 8 : 4) / 16;
+    zero_visible_rows_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(radius, n, static_cast<uint4 *>(acc), chunks);
+    return hipGetLastError();
+}
+
+hipError_t launch_export_acc(const int32_t *radius, int64_t n, const void *acc, bool acc_f64, float *dst,
+                             hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int64_t count = n * GSR_ACC_STRIDE;
+    const unsigned blocks = (unsigned)((count + 255) / 256);
+    if (acc_f64)
+        export_acc_kernel<double><<<blocks, 256, 0, st>>>(radius, n, static_cast<const double *>(acc), dst);
+    else
+        export_acc_kernel<float><<<blocks, 256, 0, st>>>(radius, n, static_cast<const float *>(acc), dst);
     return hipGetLastError();
 }
 

@@ -610,8 +610,7 @@ gsr_status bwd_enqueue(gsr_ctx *ctx, int nv, gsr_fwd *const *sts, const gsr_conf
     for (int v = 0; v < nv; ++v) sts[v]->counters_valid = false;
     mark(ctx, tm, EV_B0);
     for (int v = 0; v < nv; ++v) {
-        const int64_t nn = sts[v]->n > 0 ? sts[v]->n : 1;
-        GSR_HIP(ctx, launch_fill_u32(static_cast<uint32_t *>(sts[v]->acc), 0u, nn * GSR_ACC_STRIDE * (f64 ? 2 : 1), s));
+        GSR_HIP(ctx, launch_zero_visible_rows(sts[v]->radius, sts[v]->n, sts[v]->acc, f64, s));
         sts[v]->acc_f64 = f64;
     }
     if (count) GSR_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t *>(sts[0]->counters), 0u, 160, s));
@@ -1069,10 +1068,7 @@ gsr_status gsr_fwd_export(gsr_ctx *ctx, const gsr_fwd *st, const gsr_fwd_export_
         if (d->clamp_mask) GSR_HIP(ctx, hipMemcpyAsync(d->clamp_mask, st->clamp_mask, n, hipMemcpyDeviceToDevice, s));
         if (d->acc) {
             if (!st->acc) return fail(ctx, GSR_ESTATE, "no backward has run on this state");
-            if (st->acc_f64)
-                GSR_HIP(ctx, launch_f64_to_f32(static_cast<const double *>(st->acc), d->acc, n * GSR_ACC_STRIDE, s));
-            else
-                GSR_HIP(ctx, hipMemcpyAsync(d->acc, st->acc, n * GSR_ACC_STRIDE * 4, hipMemcpyDeviceToDevice, s));
+            GSR_HIP(ctx, launch_export_acc(st->radius, n, st->acc, st->acc_f64, d->acc, s));
         }
     }
     if (d->sorted_ids && !st->p_known)
