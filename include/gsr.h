@@ -57,7 +57,7 @@ enum {
     GSR_FLAG_DEBUG_COUNTERS = 1, /* backward counts wave-entries, active lanes and issued atomics */
     GSR_FLAG_XCD_REMAP = 2,      /* composite kernels map consecutive blocks of one XCD to neighbouring tiles */
     GSR_FLAG_STAGE_TIMING = 4,   /* record HIP events around each stage (gsr_ctx_stage_times) */
-    GSR_FLAG_LANE_SPLIT_ATOMICS = 8, /* reduce path: lanes 0..8 each issue one of the 9 sums in one instruction */
+    GSR_FLAG_LANE_SPLIT_ATOMICS = 8, /* reduce path: nine lanes each issue one of the 9 sums in one instruction */
     GSR_FLAG_NO_TILE_ORDER = 16,     /* launch tiles in index order instead of longest-work first */
     GSR_FLAG_ACC_F32 = 32            /* fp32 backward accumulators (the paper's setting). Without it the
                                         per-wave sums, kept in fp32 registers, are added into fp64
@@ -139,9 +139,11 @@ typedef struct {
  *  sorted_ids [P] uint32 (Gaussian per list entry, tile-major then depth),
  *  ranges [G,2] uint32 half-open [start,end) into sorted_ids,
  *  T_final [HW], n_contrib [HW] uint32 (1-based list position of the last
- *  composited entry, 0 = none), acc [n,GSR_ACC_STRIDE] (accumulators of the
- *  last backward as fp32, whatever their precision; rows of culled Gaussians
- *  read 0). */
+ *  composited entry, 0 = none), acc [n,GSR_ACC_STRIDE] (the last backward's
+ *  accumulators as fp32 gradients in the column order of GSR_ACC_STRIDE,
+ *  whatever their precision; rows of culled Gaussians read 0. The composite
+ *  accumulates moments of dL/dpower, which the export turns into mean and
+ *  conic gradients with the state's current conics). */
 typedef struct {
     float *mean2d;
     float *conic_opacity;

@@ -23,28 +23,45 @@ __device__ __forceinline__ void rect_of(float u, float v, int r, const DevCamera
     y1 = min(max((int)floorf((v + rf + ts - 1.0f) / ts), 0), cam.grid_y);
 }
 
-// One (pixel, splat) evaluation. The forward composite and the backward
-// recompute it with this same function (no FMA contraction inside), so the
-// backward takes exactly the forward's skip decisions.
+// Records as the composite kernels stage them in LDS: the conic (A, B, C) of
+// power = -0.5 (A dx^2 + C dy^2) - B dx dy is prescaled to
+// (a, b, c) = -log2(e) (A/2, B, C/2), so that power log2(e) = a dx^2 + b dx dy
+// + c dy^2 costs five operations and the Gaussian is one hardware exp2; the
+// reach 2 ln(255 o) of the splat is rescaled to the same units
+// (log2(255 o)). Everything else is the record as stored.
+constexpr float kLog2e = 1.4426950408889634f;
+__device__ __forceinline__ void stage_record(const float4 *__restrict__ rec, uint32_t g, float4 &r0, float4 &r1,
+                                             float4 &r2) {
+    r0 = rec[3 * (size_t)g];
+    r1 = rec[3 * (size_t)g + 1];
+    r2 = rec[3 * (size_t)g + 2];
+    r0.z *= -0.5f * kLog2e;
+    r0.w *= -kLog2e;
+    r1.x *= -0.5f * kLog2e;
+    r2.z *= 0.5f * kLog2e;
+}
+
+// One (pixel, splat) evaluation on a staged record. The forward composite and
+// the backward recompute it with this same function (no FMA contraction
+// inside), so the backward takes exactly the forward's skip decisions.
 struct SplatEval {
-    float dx, dy, power, G, raw, alpha;
+    float dx, dy, G, raw, alpha;
     bool pass; // power <= 0 and alpha >= 1/255
 };
 
-__device__ __forceinline__ SplatEval eval_splat(float px, float py, float u, float v, float A, float B, float C,
+__device__ __forceinline__ SplatEval eval_splat(float px, float py, float u, float v, float a, float b, float c,
                                                 float o) {
 #pragma clang fp contract(off)
     SplatEval e;
     e.dx = px - u;
     e.dy = py - v;
-    const float q = fmaf(A * e.dx, e.dx, (C * e.dy) * e.dy);
-    e.power = fmaf(-B * e.dx, e.dy, -0.5f * q);
-    // Hardware exp2 of power*log2(e): relative error ~|power|*2^-24 (3e-7 where alpha meets
-    // 1/255), against ~12 instructions for the correctly rounded expf.
-    e.G = __expf(e.power);
+    const float t = fmaf(a, e.dx, b * e.dy);
+    const float lp = fmaf(t, e.dx, (c * e.dy) * e.dy); // power log2(e)
+    // Hardware exp2: relative error about 1 ulp.
+    e.G = __builtin_amdgcn_exp2f(lp);
     e.raw = o * e.G;
     e.alpha = fminf(kAlphaMax, e.raw);
-    e.pass = !(e.power > 0.0f) && e.alpha >= kAlphaMin;
+    e.pass = !(lp > 0.0f) && e.alpha >= kAlphaMin;
     return e;
 }
 
@@ -63,30 +80,54 @@ __device__ __forceinline__ float wave_sum_to_lane63(float v) {
     return v;
 }
 
-// Nine values summed over the 64 lanes, the total of value k delivered to the
-// lanes whose index within their 16-lane row is k (k < 9), every lane active.
-//  1. in-row butterfly, the four DPP steps interleaved across the nine values
-//     (independent chains, so no hazard padding between dependent DPP ops);
-//  2. transpose: lane k of each row keeps its row's partial of value k;
-//  3. the four rows added by two lane permutes (xor 16, xor 32). (The gfx950
-//     row-swap builtins were not used: this toolchain returned the first
-//     operand for both results of the swap.)
-__device__ __forceinline__ float wave_sum9_to_row_lanes(float (&v)[9], int lane) {
-#define GSR_DPP_STEP(ctrl)                                                                                           \
-    _Pragma("unroll") for (int k = 0; k < 9; ++k) v[k] += __builtin_bit_cast(                                       \
-        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v[k]), ctrl, 0xF, 0xF, false));
-    GSR_DPP_STEP(0xB1)  // quad_perm [1,0,3,2]
-    GSR_DPP_STEP(0x4E)  // quad_perm [2,3,0,1]
-    GSR_DPP_STEP(0x141) // row_half_mirror
-    GSR_DPP_STEP(0x140) // row_mirror
-#undef GSR_DPP_STEP
-    const int r = lane & 15;
-    float w = v[0];
-#pragma unroll
-    for (int k = 1; k < 9; ++k) w = (r == k) ? v[k] : w;
-    w += __shfl_xor(w, 16, 64);
-    w += __shfl_xor(w, 32, 64);
-    return w;
+// Nine values summed over the 64 lanes as a reduce-scatter: each step pairs two
+// registers and halves the lanes that carry each of them, so the work shrinks
+// with every step instead of repeating a nine-value butterfly at every level.
+//  1. lanes l and l^32: the gfx950 lane swap v_permlane32_swap on a register
+//     pair (a, b) returns the lower halves of both in one result and the upper
+//     halves in the other; their sum holds a's partial in lanes 0..31 and b's
+//     in lanes 32..63 (one swap and one add for two values);
+//  2. lanes l and l^16 likewise with v_permlane16_swap (rows 0 and 2 keep the
+//     first register, rows 1 and 3 the second);
+//  3. within each 16-lane row, DPP partners l^8 (row rotate by 8), l^7 (row
+//     half mirror), l^2 and l^1; where two registers are paired, each lane
+//     keeps the sum of the register its half of the pair carries.
+// Value k's total ends in the lanes whose sum9_slot is k; sum9_issues marks one
+// lane per value (lanes 0, 8, ..., 56 and lane 4). Every lane must be active.
+__device__ __forceinline__ int sum9_slot(int lane) {
+    return (lane & 4) ? 8 : ((lane >> 1) & 4) + ((lane >> 3) & 2) + ((lane >> 5) & 1);
+}
+__device__ __forceinline__ bool sum9_issues(int lane) { return (lane & 3) == 0 && ((lane & 4) == 0 || lane == 4); }
+
+__device__ __forceinline__ float swap32_sum(float a, float b) {
+    const auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(p[0]) + __uint_as_float(p[1]);
+}
+__device__ __forceinline__ float swap16_sum(float a, float b) {
+    const auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(p[0]) + __uint_as_float(p[1]);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_sum(float v) {
+    return v + __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF,
+                                                                     false));
+}
+
+__device__ __forceinline__ float wave_sum9_scatter(const float (&v)[9], int lane) {
+    const float a0 = swap32_sum(v[0], v[1]), a1 = swap32_sum(v[2], v[3]);
+    const float a2 = swap32_sum(v[4], v[5]), a3 = swap32_sum(v[6], v[7]);
+    const float a4 = swap32_sum(v[8], v[8]);
+    const float b0 = swap16_sum(a0, a1), b1 = swap16_sum(a2, a3), b2 = swap16_sum(a4, a4);
+    // row rotate by 8 (ctrl 0x128): partner l^8
+    const float c0x = dpp_sum<0x128>(b0), c0y = dpp_sum<0x128>(b1);
+    const float c0 = (lane & 8) ? c0y : c0x;
+    const float c1 = dpp_sum<0x128>(b2);
+    // row half mirror (0x141): partner l^7
+    const float dx = dpp_sum<0x141>(c0), dy = dpp_sum<0x141>(c1);
+    float d = (lane & 4) ? dy : dx;
+    d = dpp_sum<0x4E>(d); // quad_perm [2,3,0,1]: l^2
+    d = dpp_sum<0xB1>(d); // quad_perm [1,0,3,2]: l^1
+    return d;
 }
 
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {

@@ -1,13 +1,14 @@
 // Internal declarations shared by the HIP translation units of libgsr.
 // Device layouts (all in HBM, one allocation each, from the context pool):
-//   rec        [n][3] float4  (u, v, A, B) (C, o, r, g) (b, depth, 2 ln(255 o), 0): the
+//   rec        [n][3] float4  (u, v, A, B) (C, o, r, g) (b, id bits, 2 ln(255 o), depth): the
 //              record each list entry gathers in the composite kernels
 //   radius     [n] int32, tiles_touched [n] uint32, clamp_mask [n] uint8
 //   depth_key  [n] uint32 (fp32 depth bits, 0xffffffff when culled), ids [n]
 //   offsets    [n] uint32 exclusive scan of tiles_touched in depth order
 //   pair_tile / pair_id [P] uint32 (+ alternates for the radix sort)
 //   ranges     [tiles] uint2, T_final [HW] f32, n_contrib [HW] uint32
-//   acc        [n][GSR_ACC_STRIDE] f32 backward accumulators
+//   acc        [n][GSR_ACC_STRIDE] f32 or f64 backward accumulators: five moments of dL/dpower
+//              over the pixel offsets, dL/do, dL/drgb
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -66,9 +67,10 @@ hipError_t launch_preprocess_bwd(const gsr_scene &s, const DevCamera &cam, const
 
 // Zero the accumulator rows of Gaussians with radius > 0 (the only rows the composite writes).
 hipError_t launch_zero_visible_rows(const int32_t *radius, int64_t n, void *acc, bool acc_f64, hipStream_t st);
-// Accumulators as fp32 [n][GSR_ACC_STRIDE], rows of culled Gaussians as zeros.
-hipError_t launch_export_acc(const int32_t *radius, int64_t n, const void *acc, bool acc_f64, float *dst,
-                             hipStream_t st);
+// Accumulator rows as fp32 gradients [n][GSR_ACC_STRIDE] (dL/du, dL/dv, dL/dA, dL/dB, dL/dC,
+// dL/do, dL/drgb: the moments converted with the record's conic), culled rows as zeros.
+hipError_t launch_export_acc(const int32_t *radius, const float4 *rec, int64_t n, const void *acc, bool acc_f64,
+                             float *dst, hipStream_t st);
 
 // Exclusive scan of n uint32 values (in[gather[i]] when gather != nullptr).
 // total (device, may be nullptr) receives the sum. Scratch sized by scan_scratch_count.

@@ -42,8 +42,9 @@ __device__ __forceinline__ void atomic_acc(double *p, float v) { unsafeAtomicAdd
 // must call it (uniform control flow). Returns the atomic lane-operations
 // this lane issued.
 template <int MODE, bool SPLIT, typename AccT>
-__device__ __forceinline__ uint32_t emit9(bool active, float (&v)[9], AccT *dst, int threshold, int lane,
+__device__ __forceinline__ uint32_t emit9(bool active, uint64_t m, float (&v)[9], AccT *dst, int threshold, int lane,
                                           uint64_t &reduced_mask_out) {
+    // m: the wave's ballot of active
     uint32_t issued = 0;
     reduced_mask_out = 0;
     if (MODE == GSR_BWD_PLAIN_ATOMIC) {
@@ -54,7 +55,6 @@ __device__ __forceinline__ uint32_t emit9(bool active, float (&v)[9], AccT *dst,
         }
         return issued;
     }
-    const uint64_t m = __ballot(active);
     const int cnt = __popcll(m);
     if (MODE == GSR_BWD_SERIAL_REDUCE) {
         if (cnt >= threshold) {
@@ -85,24 +85,28 @@ __device__ __forceinline__ uint32_t emit9(bool active, float (&v)[9], AccT *dst,
         }
         return issued;
     }
-    if (cnt >= threshold) { // threshold >= 1, so cnt > 0 here
-        reduced_mask_out = m;
-        if (SPLIT) {
-            const float mine = wave_sum9_to_row_lanes(v, lane);
-            if (lane < 9) {
-                atomic_acc(dst + lane, mine);
-                issued = 1;
-            }
-            return issued;
-        }
+    // The sparse case is issued first, as straight-line code under the lane mask: the reduction
+    // is then the last use of v, and its lane swaps (which overwrite their operands) need no
+    // copies of the nine values.
+    const bool sparse = cnt < threshold;
+    if (sparse && active) {
 #pragma unroll
-        for (int k = 0; k < 9; ++k) v[k] = wave_sum_to_lane63(v[k]);
-        if (lane == 63) {
-#pragma unroll
-            for (int k = 0; k < 9; ++k) atomic_acc(dst + k, v[k]);
-            issued = 9;
+        for (int k = 0; k < 9; ++k) atomic_acc(dst + k, v[k]);
+        issued = 9;
+    }
+    if (sparse) return issued;
+    reduced_mask_out = m; // threshold >= 1, so cnt > 0 here
+    if (SPLIT) {
+        const float mine = wave_sum9_scatter(v, lane);
+        if (sum9_issues(lane)) {
+            atomic_acc(dst + sum9_slot(lane), mine);
+            issued = 1;
         }
-    } else if (active) {
+        return issued;
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) v[k] = wave_sum_to_lane63(v[k]);
+    if (lane == 63) {
 #pragma unroll
         for (int k = 0; k < 9; ++k) atomic_acc(dst + k, v[k]);
         issued = 9;
@@ -112,9 +116,10 @@ __device__ __forceinline__ uint32_t emit9(bool active, float (&v)[9], AccT *dst,
 
 // Entries of a staged LDS batch this wave has to visit, as wave-uniform bit
 // masks (bit j % 64 of mask[j / 64] for entry j < limit). A lane of the wave
-// can pass entry j only if the splat's quadratic form d^T K d (K the conic,
-// d the offset from its centre) is at most 2 ln(255 o) at that lane's sample
-// point. The test takes the minimum of the form over the square holding all
+// can pass entry j only if the splat's quadratic form (log2(e)/2) d^T K d (K
+// the conic, d the offset from its centre; the staged units) is at most
+// log2(255 o) at that lane's sample point. The test takes the minimum of the
+// form over the square holding all
 // 8x8 sample points of the wave, widened by half a pixel: zero when the
 // centre lies inside, else the least of the four edge minima (each a clamped
 // one-dimensional quadratic). Being a minimum over a superset of the sample
@@ -136,18 +141,19 @@ __device__ __forceinline__ void wave_visit_masks(const float4 *s0, const float4 
         const int j = q * 64 + lane;
         bool vis = false;
         if (j < limit) {
-            const float4 a = s0[j];
-            const float Kc = s1[j].x, reach = s2[j].z;
+            const float4 r = s0[j];
+            // the staged form is -log2(e)/2 (d^T K d): (ka, kb, kc) = its negation as (A, B, C)
+            const float ka = -r.z, kb = -0.5f * r.w, kc = -s1[j].x, reach = s2[j].z;
             // square [qc - 4, qc + 4]^2 relative to the splat centre
-            const float lx = qcx - 4.0f - a.x, hx = qcx + 4.0f - a.x;
-            const float ly = qcy - 4.0f - a.y, hy = qcy + 4.0f - a.y;
+            const float lx = qcx - 4.0f - r.x, hx = qcx + 4.0f - r.x;
+            const float ly = qcy - 4.0f - r.y, hy = qcy + 4.0f - r.y;
             const bool inside = lx <= 0.0f && hx >= 0.0f && ly <= 0.0f && hy >= 0.0f;
             float fmin = 0.0f;
-            if (!(a.z > 0.0f && Kc > 0.0f && a.z * Kc - a.w * a.w > 0.0f)) {
+            if (!(ka > 0.0f && kc > 0.0f && ka * kc - kb * kb > 0.0f)) {
                 fmin = 0.0f; // not positive definite (numerically): keep the entry
             } else if (!inside) {
-                fmin = fminf(fminf(edge_min(lx, ly, hy, a.z, a.w, Kc), edge_min(hx, ly, hy, a.z, a.w, Kc)),
-                             fminf(edge_min(ly, lx, hx, Kc, a.w, a.z), edge_min(hy, lx, hx, Kc, a.w, a.z)));
+                fmin = fminf(fminf(edge_min(lx, ly, hy, ka, kb, kc), edge_min(hx, ly, hy, ka, kb, kc)),
+                             fminf(edge_min(ly, lx, hx, kc, kb, ka), edge_min(hy, lx, hx, kc, kb, ka)));
             }
             vis = reach > 0.0f && fmin <= reach + 1e-3f;
         }
@@ -200,12 +206,7 @@ __global__ __launch_bounds__(TILE *TILE) void composite_fwd_kernel(ViewBatch vb,
     for (uint32_t start = rg.x; start < rg.y; start += BATCH) {
         if (__syncthreads_count(done) == NT) break;
         const uint32_t k = start + tid;
-        if (tid < BATCH && k < rg.y) {
-            const uint32_t g = ids[k];
-            s0[tid] = rec[3 * (size_t)g];
-            s1[tid] = rec[3 * (size_t)g + 1];
-            s2[tid] = rec[3 * (size_t)g + 2];
-        }
+        if (tid < BATCH && k < rg.y) stage_record(rec, ids[k], s0[tid], s1[tid], s2[tid]);
         __syncthreads();
         const int cnt = min(BATCH, (int)(rg.y - start));
         uint64_t vis[BATCH / 64];
@@ -276,7 +277,6 @@ __global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(ViewBatch vb,
                                                                    const uint2 *__restrict__ work, BwdParams p) {
     constexpr int QX = TILE / 8;
     __shared__ float4 s0[BATCH], s1[BATCH], s2[BATCH];
-    __shared__ uint32_t sid[BATCH];
     __shared__ uint32_t s_walk;
     __shared__ unsigned long long s_cnt[COUNT ? CNT_HIST + 65 : 1];
     // Block pre-reduction: the reduced sums of every wave land in LDS per batch entry, and the
@@ -330,13 +330,7 @@ __global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(ViewBatch vb,
         const int start = end > BATCH ? end - BATCH : 0;
         const int cnt = end - start;
         __syncthreads();
-        if (tid < cnt) {
-            const uint32_t g = a.ids[rg.x + start + tid];
-            sid[tid] = g;
-            s0[tid] = a.rec[3 * (size_t)g];
-            s1[tid] = a.rec[3 * (size_t)g + 1];
-            s2[tid] = a.rec[3 * (size_t)g + 2];
-        }
+        if (tid < cnt) stage_record(a.rec, a.ids[rg.x + start + tid], s0[tid], s1[tid], s2[tid]);
         if (BLOCK) {
             for (int i = tid; i < cnt * 9; i += TILE * TILE) s_acc[i] = 0.0f;
             if (tid < cnt) s_touch[tid] = 0u;
@@ -357,40 +351,47 @@ __global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(ViewBatch vb,
                 const float4 r1 = s1[j];
                 const float rb = r2.x;
                 const SplatEval e = eval_splat(fpx, fpy, r0.x, r0.y, r0.z, r0.w, r1.x, r1.y);
-                const bool walked = pos <= nc;
-                const bool active = walked && e.pass;
+                const bool active = pos <= nc && e.pass;
+                const uint64_t am = __ballot(active);
+                // Lanes that skip this entry run the same arithmetic with alpha, G and o G set to
+                // zero: their nine values come out as zeros and T, Q stay as they are.
+                const float al = active ? e.alpha : 0.0f;
+                const float gz = active ? e.G : 0.0f;
+                const float rz = active ? e.raw : 0.0f;
+                // Transmittance in front of this entry; hardware reciprocal (1 ulp) instead of the
+                // IEEE division sequence.
+                const float Tin = T * __builtin_amdgcn_rcpf(1.0f - al);
+                T = active ? Tin : T;
                 float v[9];
-    #pragma unroll
-                for (int k = 0; k < 9; ++k) v[k] = 0.0f;
-                if (active) {
-                    // Transmittance in front of this entry; hardware reciprocal (1 ulp) instead of the
-                    // IEEE division sequence.
-                    T = T * __builtin_amdgcn_rcpf(1.0f - e.alpha);
-                    const float w = e.alpha * T;
-                    v[6] = w * G0;
-                    v[7] = w * G1;
-                    v[8] = w * G2;
-                    const float dL_dalpha = T * ((r1.z - Q0) * G0 + (r1.w - Q1) * G1 + (rb - Q2) * G2);
-                    Q0 = fmaf(e.alpha, r1.z - Q0, Q0);
-                    Q1 = fmaf(e.alpha, r1.w - Q1, Q1);
-                    Q2 = fmaf(e.alpha, rb - Q2, Q2);
-                    const float dL_doG = e.raw > kAlphaMax ? 0.0f : dL_dalpha; // alpha = min(0.99, o G)
-                    v[5] = e.G * dL_doG;
-                    const float dL_dp = e.raw * dL_doG;
-                    v[0] = dL_dp * (r0.z * e.dx + r0.w * e.dy);
-                    v[1] = dL_dp * (r0.w * e.dx + r1.x * e.dy);
-                    v[2] = -0.5f * dL_dp * e.dx * e.dx;
-                    v[3] = -dL_dp * e.dx * e.dy;
-                    v[4] = -0.5f * dL_dp * e.dy * e.dy;
-                }
-                AccT *dst = static_cast<AccT *>(a.acc) + (size_t)sid[j] * GSR_ACC_STRIDE;
+                const float w = al * T;
+                v[6] = w * G0;
+                v[7] = w * G1;
+                v[8] = w * G2;
+                const float dL_dalpha = T * ((r1.z - Q0) * G0 + (r1.w - Q1) * G1 + (rb - Q2) * G2);
+                Q0 = fmaf(al, r1.z - Q0, Q0);
+                Q1 = fmaf(al, r1.w - Q1, Q1);
+                Q2 = fmaf(al, rb - Q2, Q2);
+                const float dL_doG = rz > kAlphaMax ? 0.0f : dL_dalpha; // alpha = min(0.99, o G)
+                v[5] = gz * dL_doG;
+                // Moments of dL/dpower over the pixel offsets; the conic, the same for every pixel,
+                // turns them into the mean and conic gradients once per Gaussian.
+                const float dL_dp = rz * dL_doG;
+                const float mx = dL_dp * e.dx, my = dL_dp * e.dy;
+                v[0] = mx;
+                v[1] = my;
+                v[2] = mx * e.dx;
+                v[3] = mx * e.dy;
+                v[4] = my * e.dy;
+                // The record carries its Gaussian's id (the same in every lane): the row address is
+                // formed in scalar registers.
+                const uint32_t gid = (uint32_t)__builtin_amdgcn_readfirstlane((int)__float_as_uint(r2.y));
+                AccT *dst = static_cast<AccT *>(a.acc) + (size_t)gid * GSR_ACC_STRIDE;
                 uint64_t red_mask = 0;
                 if (BLOCK) {
-                    const uint64_t m = __ballot(active);
-                    if (__popcll(m) >= p.threshold) {
-                        red_mask = m;
-                        const float mine = wave_sum9_to_row_lanes(v, lane);
-                        if (lane < 9) atomicAdd(&s_acc[j * 9 + lane], mine);
+                    if (__popcll(am) >= p.threshold) {
+                        red_mask = am;
+                        const float mine = wave_sum9_scatter(v, lane);
+                        if (sum9_issues(lane)) atomicAdd(&s_acc[j * 9 + sum9_slot(lane)], mine);
                         if (lane == 0) s_touch[j] = 1u;
                     } else if (active) {
     #pragma unroll
@@ -398,11 +399,10 @@ __global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(ViewBatch vb,
                         issued += 9;
                     }
                 } else {
-                    issued += emit9<MODE, SPLIT>(active, v, dst, p.threshold, lane, red_mask);
+                    issued += emit9<MODE, SPLIT>(active, am, v, dst, p.threshold, lane, red_mask);
                 }
                 if (COUNT) {
-                    const uint64_t ma = __ballot(active);
-                    const int ca = __popcll(ma);
+                    const int ca = __popcll(am);
                     c_active += ca;
                     if (ca) {
                         c_we += 1;
@@ -426,7 +426,8 @@ __global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(ViewBatch vb,
                 const int e = i / 9;
                 const bool f = s_touch[e] != 0u;
                 if (f) {
-                    atomic_acc(static_cast<AccT *>(a.acc) + (size_t)sid[e] * GSR_ACC_STRIDE + (i - 9 * e), s_acc[i]);
+                    atomic_acc(static_cast<AccT *>(a.acc) + (size_t)__float_as_uint(s2[e].y) * GSR_ACC_STRIDE +
+                                   (i - 9 * e), s_acc[i]);
                     ++issued;
                 }
                 if (COUNT && __ballot(f)) c_instr += 1;
@@ -460,7 +461,7 @@ __global__ __launch_bounds__(64) void wave_reduce_selftest_kernel(const float *v
 #pragma unroll
     for (int k = 0; k < 9; ++k) v[k] = act ? vals[i * 9 + k] : 0.0f;
     uint64_t red;
-    const uint32_t issued = emit9<MODE, SPLIT, float>(act, v, sums, threshold, lane, red);
+    const uint32_t issued = emit9<MODE, SPLIT, float>(act, __ballot(act), v, sums, threshold, lane, red);
     if (issued) atomicAdd(lane_atomics, (unsigned long long)issued);
 }
 

@@ -181,7 +181,9 @@ __global__ __launch_bounds__(256) void preprocess_fwd_kernel(int n, const float 
     const float two_tau = tau > 0.0f ? 2.0f * tau : -1.0f;
     rec[3 * (int64_t)i] = make_float4(u, v, A, B);
     rec[3 * (int64_t)i + 1] = make_float4(C, o, rgb[0], rgb[1]);
-    rec[3 * (int64_t)i + 2] = make_float4(rgb[2], tz, two_tau, 0.0f);
+    // second slot: the Gaussian's own index (bits), so a list entry's record names its accumulator
+    // row (next to the blue channel: the backward composite reads both with one 8-byte load)
+    rec[3 * (int64_t)i + 2] = make_float4(rgb[2], __uint_as_float((uint32_t)i), two_tau, tz);
     radius[i] = r;
     tiles_touched[i] = (uint32_t)ntiles;
     depth_key[i] = __float_as_uint(tz);
@@ -239,6 +241,23 @@ __global__ __launch_bounds__(256) void preprocess_bwd_kernel(int n, const float 
     }
 }
 
+// The backward composite adds, per Gaussian, the five moments of g = dL/dpower
+// over the pixel offsets (dx, dy) = (px - u, py - v):
+//   m = (sum g dx, sum g dy, sum g dx^2, sum g dx dy, sum g dy^2).
+// With power = -0.5 (A dx^2 + C dy^2) - B dx dy and (A, B, C) the same for
+// every pixel, the mean and conic gradients follow as
+//   dL/du = A m0 + B m1, dL/dv = B m0 + C m1,
+//   dL/dA = -0.5 m2, dL/dB = -m3, dL/dC = -0.5 m4,
+// in the accumulators' precision.
+template <typename AccT>
+__device__ __forceinline__ void moments_to_grads(const AccT *m, float A, float B, float C, float (&g)[5]) {
+    g[0] = (float)((AccT)A * m[0] + (AccT)B * m[1]);
+    g[1] = (float)((AccT)B * m[0] + (AccT)C * m[1]);
+    g[2] = (float)((AccT)-0.5 * m[2]);
+    g[3] = (float)(-m[3]);
+    g[4] = (float)((AccT)-0.5 * m[4]);
+}
+
 // Everything of one Gaussian except the SH gradient, which the caller writes
 // (Y receives the basis values, g the dL/drgb passed through the clamp; both
 // stay zero for a culled Gaussian).
@@ -265,14 +284,17 @@ __device__ __forceinline__ void preprocess_bwd_one(int i, const float *__restric
         return;
     }
     const AccT *g = acc + (int64_t)i * GSR_ACC_STRIDE;
-    const float gu = (float)g[0], gv = (float)g[1], gA = (float)g[2], gB = (float)g[3], gC = (float)g[4],
-                go = (float)g[5];
-    const float grgb[3] = {(float)g[6], (float)g[7], (float)g[8]};
-
     const float mx = means[3 * i], my = means[3 * i + 1], mz = means[3 * i + 2];
     const float tz = depth_of(cam, mx, my, mz);
     Proj p;
     project_splat(cam, mx, my, mz, tz, log_scales + 3 * i, quats + 4 * i, p);
+    float g5[5];
+    {
+        const float idet = 1.0f / p.det; // the conic as the forward computed it
+        moments_to_grads(g, p.c * idet, -p.b * idet, p.a * idet, g5);
+    }
+    const float gu = g5[0], gv = g5[1], gA = g5[2], gB = g5[3], gC = g5[4], go = (float)g[5];
+    const float grgb[3] = {(float)g[6], (float)g[7], (float)g[8]};
 
     // ---- colour: rgb = max(sum_k Y_k f_k + 0.5, 0) along d = (m - centre)/|m - centre| ----
     float ex = mx - cam.centre[0], ey = my - cam.centre[1], ez = mz - cam.centre[2];
@@ -457,14 +479,30 @@ __global__ __launch_bounds__(256) void zero_visible_rows_kernel(const int32_t *r
     for (int c = 0; c < chunks_per_row; ++c) row[c] = make_uint4(0u, 0u, 0u, 0u);
 }
 
-// dst[i][k] = acc[i][k] as fp32, 0 for rows never written (radius <= 0).
+// Row i of dst: (dL/du, dL/dv, dL/dA, dL/dB, dL/dC, dL/do, dL/drgb) from the
+// accumulated moments and the conic in the record, as fp32; zeros for rows
+// never written (radius <= 0).
 template <typename AccT>
-__global__ __launch_bounds__(256) void export_acc_kernel(const int32_t *radius, int64_t n, const AccT *acc,
-                                                          float *dst) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n * GSR_ACC_STRIDE) return;
-    const int64_t i = t / GSR_ACC_STRIDE;
-    dst[t] = radius[i] > 0 ? (float)acc[t] : 0.0f;
+__global__ __launch_bounds__(256) void export_acc_kernel(const int32_t *radius, const float4 *rec, int64_t n,
+                                                          const AccT *acc, float *dst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float *o = dst + i * GSR_ACC_STRIDE;
+    float row[GSR_ACC_STRIDE];
+#pragma unroll
+    for (int k = 0; k < GSR_ACC_STRIDE; ++k) row[k] = 0.0f;
+    if (radius[i] > 0) {
+        const AccT *m = acc + i * GSR_ACC_STRIDE;
+        const float4 r0 = rec[3 * i];
+        float g5[5];
+        moments_to_grads(m, r0.z, r0.w, rec[3 * i + 1].x, g5);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) row[k] = g5[k];
+#pragma unroll
+        for (int k = 5; k < 9; ++k) row[k] = (float)m[k];
+    }
+#pragma unroll
+    for (int k = 0; k < GSR_ACC_STRIDE; ++k) o[k] = row[k];
 }
 } // namespace
 
@@ -475,15 +513,14 @@ hipError_t launch_zero_visible_rows(const int32_t *radius, int64_t n, void *acc,
     return hipGetLastError();
 }
 
-hipError_t launch_export_acc(const int32_t *radius, int64_t n, const void *acc, bool acc_f64, float *dst,
-                             hipStream_t st) {
+hipError_t launch_export_acc(const int32_t *radius, const float4 *rec, int64_t n, const void *acc, bool acc_f64,
+                             float *dst, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    const int64_t count = n * GSR_ACC_STRIDE;
-    const unsigned blocks = (unsigned)((count + 255) / 256);
+    const unsigned blocks = (unsigned)((n + 255) / 256);
     if (acc_f64)
-        export_acc_kernel<double><<<blocks, 256, 0, st>>>(radius, n, static_cast<const double *>(acc), dst);
+        export_acc_kernel<double><<<blocks, 256, 0, st>>>(radius, rec, n, static_cast<const double *>(acc), dst);
     else
-        export_acc_kernel<float><<<blocks, 256, 0, st>>>(radius, n, static_cast<const float *>(acc), dst);
+        export_acc_kernel<float><<<blocks, 256, 0, st>>>(radius, rec, n, static_cast<const float *>(acc), dst);
     return hipGetLastError();
 }
 

@@ -1050,7 +1050,7 @@ gsr_status gsr_fwd_export(gsr_ctx *ctx, const gsr_fwd *st, const gsr_fwd_export_
         return hipMemcpy2DAsync(dst, dpitch, src, spitch, width, rows, hipMemcpyDeviceToDevice, s);
     };
     if (n > 0) {
-        // rec rows are 48 bytes: (u, v, A, B) (C, o, r, g) (b, depth, ., .)
+        // rec rows are 48 bytes: (u, v, A, B) (C, o, r, g) (b, id, reach, depth)
         const float *rec = reinterpret_cast<const float *>(st->rec);
         GSR_HIP(ctx, cp(d->mean2d, rec, 0, 48, 8, 8, n));
         if (d->conic_opacity) {
@@ -1061,14 +1061,14 @@ gsr_status gsr_fwd_export(gsr_ctx *ctx, const gsr_fwd *st, const gsr_fwd_export_
             GSR_HIP(ctx, hipMemcpy2DAsync(d->rgb, 12, rec + 6, 48, 8, n, hipMemcpyDeviceToDevice, s));
             GSR_HIP(ctx, hipMemcpy2DAsync(d->rgb + 2, 12, rec + 8, 48, 4, n, hipMemcpyDeviceToDevice, s));
         }
-        GSR_HIP(ctx, cp(d->depth, rec + 9, 0, 48, 4, 4, n));
+        GSR_HIP(ctx, cp(d->depth, rec + 11, 0, 48, 4, 4, n));
         if (d->radius) GSR_HIP(ctx, hipMemcpyAsync(d->radius, st->radius, n * 4, hipMemcpyDeviceToDevice, s));
         if (d->tiles_touched)
             GSR_HIP(ctx, hipMemcpyAsync(d->tiles_touched, st->tiles_touched, n * 4, hipMemcpyDeviceToDevice, s));
         if (d->clamp_mask) GSR_HIP(ctx, hipMemcpyAsync(d->clamp_mask, st->clamp_mask, n, hipMemcpyDeviceToDevice, s));
         if (d->acc) {
             if (!st->acc) return fail(ctx, GSR_ESTATE, "no backward has run on this state");
-            GSR_HIP(ctx, launch_export_acc(st->radius, n, st->acc, st->acc_f64, d->acc, s));
+            GSR_HIP(ctx, launch_export_acc(st->radius, st->rec, n, st->acc, st->acc_f64, d->acc, s));
         }
     }
     if (d->sorted_ids && !st->p_known)
