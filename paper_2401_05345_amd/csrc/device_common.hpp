@@ -45,8 +45,8 @@ __device__ __forceinline__ void stage_record(const float4 *__restrict__ rec, uin
 // the backward recompute it with this same function (no FMA contraction
 // inside), so the backward takes exactly the forward's skip decisions.
 struct SplatEval {
-    float dx, dy, G, raw, alpha;
-    bool pass; // power <= 0 and alpha >= 1/255
+    float dx, dy, lp, G, raw, alpha; // lp = power log2(e)
+    bool pass;                       // power <= 0 and alpha >= 1/255
 };
 
 __device__ __forceinline__ SplatEval eval_splat(float px, float py, float u, float v, float a, float b, float c,
@@ -56,12 +56,12 @@ __device__ __forceinline__ SplatEval eval_splat(float px, float py, float u, flo
     e.dx = px - u;
     e.dy = py - v;
     const float t = fmaf(a, e.dx, b * e.dy);
-    const float lp = fmaf(t, e.dx, (c * e.dy) * e.dy); // power log2(e)
+    e.lp = fmaf(t, e.dx, (c * e.dy) * e.dy);
     // Hardware exp2: relative error about 1 ulp.
-    e.G = __builtin_amdgcn_exp2f(lp);
+    e.G = __builtin_amdgcn_exp2f(e.lp);
     e.raw = o * e.G;
     e.alpha = fminf(kAlphaMax, e.raw);
-    e.pass = !(lp > 0.0f) && e.alpha >= kAlphaMin;
+    e.pass = !(e.lp > 0.0f) && e.alpha >= kAlphaMin;
     return e;
 }
 

@@ -211,44 +211,37 @@ __global__ __launch_bounds__(TILE *TILE) void composite_fwd_kernel(ViewBatch vb,
         const int cnt = min(BATCH, (int)(rg.y - start));
         uint64_t vis[BATCH / 64];
         wave_visit_masks<BATCH>(s0, s1, s2, cnt, qcx, qcy, lane, vis);
+        // One entry for the whole wave: lanes that have stopped (or skip it) run the same
+        // arithmetic with their updates masked off, so the walk is a uniform loop.
+        const auto blend = [&](int j, const float4 &a, const float4 &b, const float4 &c, bool valid) {
+            const SplatEval e = eval_splat(fpx, fpy, a.x, a.y, a.z, a.w, b.x, b.y);
+            const bool take = valid && e.pass && !done;
+            const float Tn = T * (1.0f - e.alpha);
+            const bool stop = take && Tn < kTStop;
+            const bool use = take && !stop;
+            done = done || stop;
+            const float w = use ? e.alpha * T : 0.0f;
+            c0 = fmaf(w, b.z, c0);
+            c1 = fmaf(w, b.w, c1);
+            c2 = fmaf(w, c.x, c2);
+            T = use ? Tn : T;
+            last = use ? start - rg.x + (uint32_t)j + 1 : last;
+        };
 #pragma unroll
         for (int q = 0; q < BATCH / 64; ++q) {
             uint64_t mq = vis[q];
-            if (!mq || done) continue;
-            int bit = __builtin_ctzll(mq);
-            mq &= mq - 1;
-            float4 a = s0[q * 64 + bit], b = s1[q * 64 + bit], c = s2[q * 64 + bit];
-            for (;;) {
-                const int j = q * 64 + bit;
-                // The next visited entry's record is read before this one is processed.
-                int bn = -1;
-                float4 na = a, nb = b, nc = c;
-                if (mq) {
-                    bn = __builtin_ctzll(mq);
-                    mq &= mq - 1;
-                    na = s0[q * 64 + bn];
-                    nb = s1[q * 64 + bn];
-                    nc = s2[q * 64 + bn];
-                }
-                const SplatEval e = eval_splat(fpx, fpy, a.x, a.y, a.z, a.w, b.x, b.y);
-                if (e.pass) {
-                    const float Tn = T * (1.0f - e.alpha);
-                    if (Tn < kTStop) {
-                        done = true;
-                    } else {
-                        const float w = e.alpha * T;
-                        c0 = fmaf(w, b.z, c0);
-                        c1 = fmaf(w, b.w, c1);
-                        c2 = fmaf(w, c.x, c2);
-                        T = Tn;
-                        last = start - rg.x + (uint32_t)j + 1;
-                    }
-                }
-                if (bn < 0 || done) break;
-                bit = bn;
-                a = na;
-                b = nb;
-                c = nc;
+            // Visited entries two at a time: both records are read before the first is blended
+            // (an odd last entry is paired with itself, the copy masked off).
+            while (mq && __ballot(!done)) {
+                const int j1 = q * 64 + __builtin_ctzll(mq);
+                mq &= mq - 1;
+                const bool two = mq != 0;
+                const int j2 = two ? q * 64 + __builtin_ctzll(mq) : j1;
+                mq = two ? mq & (mq - 1) : mq;
+                const float4 a1 = s0[j1], b1 = s1[j1], e1 = s2[j1];
+                const float4 a2 = s0[j2], b2 = s1[j2], e2 = s2[j2];
+                blend(j1, a1, b1, e1, true);
+                blend(j2, a2, b2, e2, two);
             }
         }
     }
@@ -302,7 +295,9 @@ __global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(ViewBatch vb,
     const float G0 = inside ? a.dl_dimage[pix] : 0.0f;
     const float G1 = inside ? a.dl_dimage[hw + pix] : 0.0f;
     const float G2 = inside ? a.dl_dimage[2 * hw + pix] : 0.0f;
-    float Q0 = cam.bg[0], Q1 = cam.bg[1], Q2 = cam.bg[2];
+    // Colour behind the current entry, projected on this pixel's dL/dpixel: the recursion
+    // Q <- Q + alpha (c - Q) of the three channels carried as one number S = Q . dL/dpixel.
+    float S = cam.bg[0] * G0 + cam.bg[1] * G1 + cam.bg[2] * G2;
     const uint2 rg = a.ranges[tile];
 
     if (tid == 0) s_walk = 0;
@@ -351,8 +346,10 @@ __global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(ViewBatch vb,
                 const float4 r1 = s1[j];
                 const float rb = r2.x;
                 const SplatEval e = eval_splat(fpx, fpy, r0.x, r0.y, r0.z, r0.w, r1.x, r1.y);
-                const bool active = pos <= nc && e.pass;
-                const uint64_t am = __ballot(active);
+                const bool walked = pos <= nc;
+                const bool active = walked && e.pass;
+                // the ballot as the AND of the three compares' own lane masks
+                const uint64_t am = __ballot(walked) & __ballot(!(e.lp > 0.0f)) & __ballot(e.alpha >= kAlphaMin);
                 // Lanes that skip this entry run the same arithmetic with alpha, G and o G set to
                 // zero: their nine values come out as zeros and T, Q stay as they are.
                 const float al = active ? e.alpha : 0.0f;
@@ -367,10 +364,9 @@ __global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(ViewBatch vb,
                 v[6] = w * G0;
                 v[7] = w * G1;
                 v[8] = w * G2;
-                const float dL_dalpha = T * ((r1.z - Q0) * G0 + (r1.w - Q1) * G1 + (rb - Q2) * G2);
-                Q0 = fmaf(al, r1.z - Q0, Q0);
-                Q1 = fmaf(al, r1.w - Q1, Q1);
-                Q2 = fmaf(al, rb - Q2, Q2);
+                const float dc = (r1.z * G0 + r1.w * G1 + rb * G2) - S;
+                const float dL_dalpha = T * dc;
+                S = fmaf(al, dc, S);
                 const float dL_doG = rz > kAlphaMax ? 0.0f : dL_dalpha; // alpha = min(0.99, o G)
                 v[5] = gz * dL_doG;
                 // Moments of dL/dpower over the pixel offsets; the conic, the same for every pixel,
