@@ -77,6 +77,27 @@ def parse():
     return p.parse_args()
 
 
+def measure_roofs(ctx):
+    """Copy bandwidth and atomic rates of the backward's access patterns (library micro-benchmarks)."""
+    from paper_2401_05345_amd import gsr
+    mib = 1 << 20
+
+    def rate(kind, nbytes):
+        ms, ops = gsr.gsr_microbench(ctx, kind, nbytes, reps=5)
+        return ops / (ms * 1e-3)
+
+    out = {"hbm_copy_GBs": round(rate(gsr.GSR_MB_COPY, 1024 * mib) / 1e9, 1), "atomic_Gops": {}}
+    for name, kind, nbytes in [("f32_distinct_2MiB", gsr.GSR_MB_ATOMIC_F32_DISTINCT, 2 * mib),
+                               ("f32_distinct_128MiB", gsr.GSR_MB_ATOMIC_F32_DISTINCT, 128 * mib),
+                               ("f64_distinct_128MiB", gsr.GSR_MB_ATOMIC_F64_DISTINCT, 128 * mib),
+                               ("f32_same_address_16MiB", gsr.GSR_MB_ATOMIC_F32_SAME_ADDRESS, 16 * mib),
+                               ("f32_one_lane_16MiB", gsr.GSR_MB_ATOMIC_F32_ONE_LANE, 16 * mib),
+                               ("f64_nine_lanes_16MiB", gsr.GSR_MB_ATOMIC_F64_NINE_LANES, 16 * mib)]:
+        out["atomic_Gops"][name] = round(rate(kind, nbytes) / 1e9, 3)
+    log(f"[bench] roofs: {out}")
+    return out
+
+
 class Bench:
     def __init__(self, wl):
         import torch
@@ -510,6 +531,27 @@ def main():
         "forward_ms": round(float(fwd.mean()), 4),
         "p99_step_ms": None,
     }
+
+    # Measured roofs (micro-benchmarks of the kernel's memory patterns) and a6 against them.
+    if not args.profile_only:
+        try:
+            roofs = measure_roofs(b.r.ctx)
+            out["roofs"] = roofs
+            plain_rate = cp.lane_atomics / (float(np.median(p6)) * 1e-3)
+            red_rate = cr.lane_atomics / (float(np.median(r6)) * 1e-3)
+            out["backward"]["atomic_roofline"] = {
+                "plain": {"pattern": "f32_same_address_16MiB", "achieved_lane_ops_s": round(plain_rate / 1e9, 3),
+                          "peak_lane_ops_s": roofs["atomic_Gops"]["f32_same_address_16MiB"],
+                          "frac": round(plain_rate / 1e9 / roofs["atomic_Gops"]["f32_same_address_16MiB"], 4),
+                          "unit": "G lane-ops/s"},
+                "wave_reduce": {"pattern": "f64_nine_lanes_16MiB", "achieved_lane_ops_s": round(red_rate / 1e9, 3),
+                                "peak_lane_ops_s": roofs["atomic_Gops"]["f64_nine_lanes_16MiB"],
+                                "frac": round(red_rate / 1e9 / roofs["atomic_Gops"]["f64_nine_lanes_16MiB"], 4),
+                                "unit": "G lane-ops/s"}}
+            roofline["hbm_frac_measured_peak"] = round(roofline["hbm_GBs_algorithmic"] / roofs["hbm_copy_GBs"], 4)
+        except Exception as e:  # noqa: BLE001
+            log(f"[bench] roof micro-benchmarks failed: {e!r}")
+            out["roofs"] = {"error": repr(e)}
 
     if not args.no_large and args.workload != "large_3m":
         wl3 = sg.large_3m()

@@ -489,6 +489,40 @@ gsr_status gsr_wave_reduce_selftest(gsr_ctx *ctx, const float *vals, const uint8
                                     int32_t mode, int32_t threshold, int32_t lane_split,
                                     float *sums, uint64_t *lane_atomics);
 
+/* Measurement utility (not part of rendering): one memory-operation
+ * pattern of the backward composite, timed alone, to measure the roofs the
+ * kernels are held against (the survey of the method asks for a measured
+ * atomic rate, there being no published one for this GPU).
+ *   GSR_MB_COPY                   float4 copy of bytes/2 into the other half
+ *                                 (ops = bytes read + written: HBM bandwidth)
+ *   GSR_MB_ATOMIC_F32_DISTINCT    no-return fp32 adds, every lane its own
+ *                                 address, lanes of a wave on consecutive
+ *                                 elements (ops = lane-operations)
+ *   GSR_MB_ATOMIC_F64_DISTINCT    the same with fp64
+ *   GSR_MB_ATOMIC_F32_SAME_ADDRESS all 64 lanes of a wave add to one float
+ *                                 (the plain kernel's pattern; ops = lane-ops)
+ *   GSR_MB_ATOMIC_F32_ONE_LANE    lane 0 of each wave adds (one reduced sum
+ *                                 per instruction; ops = lane-ops)
+ *   GSR_MB_ATOMIC_F64_NINE_LANES  lanes 0..8 add to nine consecutive doubles
+ *                                 (the reduced kernel's nine-lane issue)
+ * The atomic patterns sweep a working set of `bytes` (128-byte slots for the
+ * last three) with 8192 workgroups of 256 threads, 64 operations each.
+ * bytes: a power of two in [1 MiB, 4 GiB], allocated and cleared by the call
+ * from the context's pool. Runs one untimed launch, then `reps` (1..100)
+ * timed ones on the context's stream and synchronises; ms_per_launch and
+ * ops_per_launch (host) receive the median launch time and the operation
+ * count of one launch. */
+enum {
+    GSR_MB_COPY = 0,
+    GSR_MB_ATOMIC_F32_DISTINCT = 1,
+    GSR_MB_ATOMIC_F64_DISTINCT = 2,
+    GSR_MB_ATOMIC_F32_SAME_ADDRESS = 3,
+    GSR_MB_ATOMIC_F32_ONE_LANE = 4,
+    GSR_MB_ATOMIC_F64_NINE_LANES = 5
+};
+gsr_status gsr_microbench(gsr_ctx *ctx, int32_t kind, int64_t bytes, int32_t reps, double *ms_per_launch,
+                          double *ops_per_launch);
+
 /* Host-only argument checks (no device needed); GSR_OK or GSR_EINVAL. */
 gsr_status gsr_validate_scene(const gsr_scene *scene);
 gsr_status gsr_validate_camera(const gsr_camera *camera);

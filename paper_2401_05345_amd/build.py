@@ -26,7 +26,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libgsr.so")
-SOURCES = ["runtime.hip", "k_preprocess.hip", "k_sort.hip", "k_composite.hip", "k_train.hip", "k_loss.hip", "server.hip"]
+SOURCES = ["runtime.hip", "k_preprocess.hip", "k_sort.hip", "k_composite.hip", "k_train.hip", "k_loss.hip", "k_micro.hip", "server.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

@@ -166,6 +166,9 @@ hipError_t launch_l1_sum(const float *a, const float *b, int64_t count, float *o
 size_t dssim_partial_count(int C, int W, int H);
 hipError_t launch_l1_dssim_grad(const float *img, const float *ref, int C, int W, int H, float lambda, float *dmu,
                                 float *dexx, float *dexy, float *sums, float *out, float *loss, hipStream_t st);
+// Micro-benchmark kernels (k_micro.hip): one launch of pattern `kind` (GSR_MB_*) over a
+// working set of `bytes` (a power of two >= 1 MiB); *ops = its operation count.
+hipError_t launch_microbench(int kind, void *buf, int64_t bytes, int64_t *ops, hipStream_t st);
 hipError_t launch_wave_reduce_selftest(const float *vals, const uint8_t *active, int n_waves, int mode,
                                        int threshold, int lane_split, float *sums, unsigned long long *lane_atomics,
                                        hipStream_t st);

@@ -1,0 +1,93 @@
+// Micro-benchmarks of the memory operations the backward composite is made
+// of, to measure the roofs it is held against on this GPU: a streaming copy
+// (HBM bandwidth) and no-return atomic adds in the access patterns of the
+// plain and the reduced kernels (the atomic rate of the L2/fabric). Every
+// kernel runs a fixed number of iterations per thread over a power-of-two
+// working set; nothing here is on the rendering path.
+#include "gsr_internal.hpp"
+
+namespace gsr {
+namespace {
+
+constexpr int kBlock = 256;
+
+__global__ __launch_bounds__(kBlock) void copy_kernel(const float4 *__restrict__ src, float4 *__restrict__ dst,
+                                                      int64_t n4) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n4; i += (int64_t)gridDim.x * kBlock)
+        dst[i] = src[i];
+}
+
+// Every lane its own address: lanes of a wave on consecutive elements, the
+// grid sweeping the working set (mask + 1 elements) iters times.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void atomic_distinct_kernel(T *buf, uint64_t mask, int iters) {
+    const uint64_t threads = (uint64_t)gridDim.x * kBlock;
+    const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    for (int it = 0; it < iters; ++it) unsafeAtomicAdd(&buf[(t + (uint64_t)it * threads) & mask], (T)1);
+}
+
+// One 128-byte slot per wave and iteration (slots = (mask + 1) / 32 floats):
+// all 64 lanes add to the slot's first float (the plain kernel's pattern),
+// lane 0 alone (one reduced sum per instruction), or lanes 0..8 to the
+// slot's first nine doubles (the reduced kernel's nine-lane issue).
+enum { SLOT_ALL_LANES = 0, SLOT_ONE_LANE = 1, SLOT_NINE_F64 = 2 };
+template <int PATTERN>
+__global__ __launch_bounds__(kBlock) void atomic_slot_kernel(float *buf, uint64_t slot_mask, int iters) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t waves = (uint64_t)gridDim.x * (kBlock / 64);
+    const uint64_t w = (uint64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    for (int it = 0; it < iters; ++it) {
+        float *slot = buf + 32 * ((w + (uint64_t)it * waves) & slot_mask);
+        if (PATTERN == SLOT_ALL_LANES) unsafeAtomicAdd(slot, 1.0f);
+        if (PATTERN == SLOT_ONE_LANE && lane == 0) unsafeAtomicAdd(slot, 1.0f);
+        if (PATTERN == SLOT_NINE_F64 && lane < 9) unsafeAtomicAdd(reinterpret_cast<double *>(slot) + lane, 1.0);
+    }
+}
+
+} // namespace
+
+hipError_t launch_microbench(int kind, void *buf, int64_t bytes, int64_t *ops, hipStream_t st) {
+    // bytes: power of two >= 1 MiB (checked by the caller)
+    const int grid = 256 * 32; // 8192 workgroups, 32 per CU
+    const int iters = 64;
+    const uint64_t threads = (uint64_t)grid * kBlock, waves = threads / 64;
+    switch (kind) {
+    case GSR_MB_COPY: {
+        const int64_t n4 = bytes / 2 / 16;
+        copy_kernel<<<grid, kBlock, 0, st>>>(static_cast<const float4 *>(buf),
+                                             static_cast<float4 *>(buf) + n4, n4);
+        *ops = 2 * n4 * 16; // bytes read + written
+        break;
+    }
+    case GSR_MB_ATOMIC_F32_DISTINCT:
+        atomic_distinct_kernel<float><<<grid, kBlock, 0, st>>>(static_cast<float *>(buf), (uint64_t)bytes / 4 - 1,
+                                                               iters);
+        *ops = (int64_t)(threads * iters);
+        break;
+    case GSR_MB_ATOMIC_F64_DISTINCT:
+        atomic_distinct_kernel<double><<<grid, kBlock, 0, st>>>(static_cast<double *>(buf), (uint64_t)bytes / 8 - 1,
+                                                                iters);
+        *ops = (int64_t)(threads * iters);
+        break;
+    case GSR_MB_ATOMIC_F32_SAME_ADDRESS:
+        atomic_slot_kernel<SLOT_ALL_LANES><<<grid, kBlock, 0, st>>>(static_cast<float *>(buf),
+                                                                    (uint64_t)bytes / 128 - 1, iters);
+        *ops = (int64_t)(threads * iters);
+        break;
+    case GSR_MB_ATOMIC_F32_ONE_LANE:
+        atomic_slot_kernel<SLOT_ONE_LANE><<<grid, kBlock, 0, st>>>(static_cast<float *>(buf),
+                                                                   (uint64_t)bytes / 128 - 1, iters);
+        *ops = (int64_t)(waves * iters);
+        break;
+    case GSR_MB_ATOMIC_F64_NINE_LANES:
+        atomic_slot_kernel<SLOT_NINE_F64><<<grid, kBlock, 0, st>>>(static_cast<float *>(buf),
+                                                                   (uint64_t)bytes / 128 - 1, iters);
+        *ops = (int64_t)(waves * iters * 9);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+} // namespace gsr

@@ -471,12 +471,13 @@ hipError_t launch_preprocess_bwd(const gsr_scene &s, const DevCamera &cam, const
 namespace {
 // Rows of the Gaussians that can appear in a tile list (radius > 0) are the only ones the
 // backward composite adds into and a7 reads: only they are cleared.
+// One thread per 16-byte chunk, so a wave's stores cover consecutive rows' chunks.
 __global__ __launch_bounds__(256) void zero_visible_rows_kernel(const int32_t *radius, int64_t n, uint4 *acc,
                                                                  int chunks_per_row) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = t / chunks_per_row;
     if (i >= n || radius[i] <= 0) return;
-    uint4 *row = acc + i * chunks_per_row;
-    for (int c = 0; c < chunks_per_row; ++c) row[c] = make_uint4(0u, 0u, 0u, 0u);
+    acc[t] = make_uint4(0u, 0u, 0u, 0u);
 }
 
 // Row i of dst: (dL/du, dL/dv, dL/dA, dL/dB, dL/dC, dL/do, dL/drgb) from the
@@ -509,7 +510,9 @@ __global__ __launch_bounds__(256) void export_acc_kernel(const int32_t *radius, 
 hipError_t launch_zero_visible_rows(const int32_t *radius, int64_t n, void *acc, bool acc_f64, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     const int chunks = GSR_ACC_STRIDE * (acc_f64 ? 8 : 4) / 16;
-    zero_visible_rows_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(radius, n, static_cast<uint4 *>(acc), chunks);
+    const int64_t threads = n * chunks;
+    zero_visible_rows_kernel<<<(unsigned)((threads + 255) / 256), 256, 0, st>>>(radius, n, static_cast<uint4 *>(acc),
+                                                                                chunks);
     return hipGetLastError();
 }
 

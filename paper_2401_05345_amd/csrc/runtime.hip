@@ -1158,6 +1158,47 @@ gsr_status gsr_l1_dssim_grad(gsr_ctx *ctx, const float *image, const float *targ
     return GSR_OK;
 }
 
+gsr_status gsr_microbench(gsr_ctx *ctx, int32_t kind, int64_t bytes, int32_t reps, double *ms_per_launch,
+                          double *ops_per_launch) {
+    if (!ctx) return GSR_EINVAL;
+    ctx->err.clear();
+    if (kind < GSR_MB_COPY || kind > GSR_MB_ATOMIC_F64_NINE_LANES) return fail(ctx, GSR_EINVAL, "bad kind");
+    if (bytes < (1 << 20) || bytes > (int64_t(1) << 32) || (bytes & (bytes - 1)))
+        return fail(ctx, GSR_EINVAL, "bytes must be a power of two in [1 MiB, 4 GiB]");
+    if (reps < 1 || reps > 100 || !ms_per_launch || !ops_per_launch) return fail(ctx, GSR_EINVAL, "bad arguments");
+    GSR_HIP(ctx, hipSetDevice(ctx->device));
+    TempBuf t;
+    uint8_t *buf = nullptr;
+    GSR_TRY(temp_alloc(ctx, t, &buf, (size_t)bytes));
+    GSR_HIP(ctx, hipMemsetAsync(buf, 0, (size_t)bytes, ctx->stream));
+    int64_t ops = 0;
+    GSR_HIP(ctx, launch_microbench(kind, buf, bytes, &ops, ctx->stream)); // untimed
+    std::vector<hipEvent_t> ev(reps + 1, nullptr);
+    gsr_status rc = GSR_OK;
+    for (auto &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) rc = fail(ctx, GSR_EHIP, "hipEventCreate failed");
+    std::vector<double> ms;
+    if (rc == GSR_OK && hipEventRecord(ev[0], ctx->stream) != hipSuccess) rc = fail(ctx, GSR_EHIP, "event record");
+    for (int r = 0; r < reps && rc == GSR_OK; ++r) {
+        if (launch_microbench(kind, buf, bytes, &ops, ctx->stream) != hipSuccess ||
+            hipEventRecord(ev[r + 1], ctx->stream) != hipSuccess)
+            rc = fail(ctx, GSR_EHIP, "launch failed");
+    }
+    if (rc == GSR_OK && hipEventSynchronize(ev[reps]) != hipSuccess) rc = fail(ctx, GSR_EHIP, "synchronize failed");
+    for (int r = 0; r < reps && rc == GSR_OK; ++r) {
+        float m = 0.0f;
+        if (hipEventElapsedTime(&m, ev[r], ev[r + 1]) != hipSuccess) rc = fail(ctx, GSR_EHIP, "elapsed time");
+        ms.push_back(m);
+    }
+    for (auto &e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (rc != GSR_OK) return rc;
+    std::sort(ms.begin(), ms.end());
+    *ms_per_launch = ms[ms.size() / 2];
+    *ops_per_launch = (double)ops;
+    return GSR_OK;
+}
+
 gsr_status gsr_wave_reduce_selftest(gsr_ctx *ctx, const float *vals, const uint8_t *active, int32_t n_waves,
                                     int32_t mode, int32_t threshold, int32_t lane_split, float *sums,
                                     uint64_t *lane_atomics) {

@@ -27,6 +27,8 @@ GSR_FLAG_ACC_F32 = 32
 GSR_MAX_BATCH = 16
 GSR_EBUDGET = -5
 GSR_ACC_STRIDE = 16
+(GSR_MB_COPY, GSR_MB_ATOMIC_F32_DISTINCT, GSR_MB_ATOMIC_F64_DISTINCT, GSR_MB_ATOMIC_F32_SAME_ADDRESS,
+ GSR_MB_ATOMIC_F32_ONE_LANE, GSR_MB_ATOMIC_F64_NINE_LANES) = range(6)
 
 c_void_p = ctypes.c_void_p
 c_int32 = ctypes.c_int32
@@ -172,6 +174,8 @@ _PROTOS = {
     "gsr_l1_grad": (c_int32, [c_void_p, c_void_p, c_void_p, c_int64, c_void_p]),
     "gsr_wave_reduce_selftest": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32, c_int32,
                                            c_void_p, c_void_p]),
+    "gsr_microbench": (c_int32, [c_void_p, c_int32, c_int64, c_int32, ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_double)]),
 }
 
 
@@ -538,6 +542,13 @@ def gsr_wave_reduce_selftest(ctx, vals, active, mode, threshold, lane_split, sum
     n_waves = int(active.numel() // 64)
     _check(ctx, load().gsr_wave_reduce_selftest(ctx, _ptr(vals), _ptr(active), n_waves, int(mode), int(threshold),
                                                 int(lane_split), _ptr(sums), _ptr(lane_atomics)))
+
+
+def gsr_microbench(ctx, kind: int, nbytes: int, reps: int = 5):
+    """(median ms per launch, operations per launch) of one GSR_MB_* pattern."""
+    ms, ops = ctypes.c_double(), ctypes.c_double()
+    _check(ctx, load().gsr_microbench(ctx, int(kind), int(nbytes), int(reps), ctypes.byref(ms), ctypes.byref(ops)))
+    return ms.value, ops.value
 
 
 # ---------------------------------------------------------------- convenience for torch callers
