@@ -11,10 +11,19 @@ namespace {
 
 constexpr int kBlock = 256;
 
+// Four independent 16-byte loads in flight per thread before their stores.
 __global__ __launch_bounds__(kBlock) void copy_kernel(const float4 *__restrict__ src, float4 *__restrict__ dst,
                                                       int64_t n4) {
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n4; i += (int64_t)gridDim.x * kBlock)
-        dst[i] = src[i];
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    for (; i + 3 * stride < n4; i += 4 * stride) {
+        const float4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+        dst[i] = a;
+        dst[i + stride] = b;
+        dst[i + 2 * stride] = c;
+        dst[i + 3 * stride] = d;
+    }
+    for (; i < n4; i += stride) dst[i] = src[i];
 }
 
 // Every lane its own address: lanes of a wave on consecutive elements, the

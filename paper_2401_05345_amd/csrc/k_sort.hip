@@ -95,6 +95,51 @@ __global__ __launch_bounds__(kThreads) void scan_apply_kernel(const uint32_t *in
     }
 }
 
+// Exclusive scan of up to kOneBlockMax items by one 1024-thread block, in
+// tiles of 16384 (thread t owns items [t*16, t*16+16) of a tile), carrying
+// the running total from tile to tile: one launch where the two-level scan
+// needs three.
+constexpr int kOneThreads = 1024;
+constexpr int64_t kOneBlockMax = 4 * kOneThreads * kItems; // 65536
+
+__global__ __launch_bounds__(kOneThreads) void scan_one_block_kernel(const uint32_t *in, const uint32_t *gather,
+                                                                     int64_t n, uint32_t *out, uint32_t *total_out) {
+    __shared__ uint32_t s_wave[kOneThreads / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t carry = 0;
+    for (int64_t tile = 0; tile < n; tile += (int64_t)kOneThreads * kItems) {
+        const int64_t base = tile + (int64_t)threadIdx.x * kItems;
+        uint32_t v[kItems];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            const int64_t i = base + k;
+            v[k] = (i < n) ? load_item(in, gather, i) : 0u;
+            sum += v[k];
+        }
+        const uint32_t inc = wave_inclusive_scan(sum, lane);
+        if (lane == 63) s_wave[wave] = inc;
+        __syncthreads();
+        uint32_t off = 0, tot = 0;
+#pragma unroll
+        for (int w = 0; w < kOneThreads / 64; ++w) {
+            const uint32_t x = s_wave[w];
+            off += (w < wave) ? x : 0u;
+            tot += x;
+        }
+        __syncthreads();
+        uint32_t run = carry + off + inc - sum;
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            const int64_t i = base + k;
+            if (i < n) out[i] = run;
+            run += v[k];
+        }
+        carry += tot;
+    }
+    if (total_out && threadIdx.x == 0) *total_out = carry;
+}
+
 } // namespace
 
 size_t scan_partial_count(int64_t n) {
@@ -119,6 +164,10 @@ hipError_t device_exclusive_scan(const uint32_t *in, const uint32_t *gather, uin
         scan_apply_kernel<<<1, kThreads, 0, st>>>(in, gather, n, nullptr, out, total);
         return hipGetLastError();
     }
+    if (n <= kOneBlockMax) {
+        scan_one_block_kernel<<<1, kOneThreads, 0, st>>>(in, gather, n, out, total);
+        return hipGetLastError();
+    }
     scan_reduce_kernel<<<(unsigned)blocks, kThreads, 0, st>>>(in, gather, n, partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -135,16 +184,27 @@ namespace {
 
 constexpr int kBins = 256;
 
-// Digit histogram of each 4096-item block, written digit-major so one
-// exclusive scan of the whole table yields every block's output offsets.
+// Sorts of fewer than kSmallSort items use 1024-item blocks (4 per thread)
+// instead of 4096: the visible Gaussians and pairs of a single view would
+// otherwise fill only a few dozen to a few hundred workgroups.
+constexpr int64_t kSmallSort = int64_t(1) << 21;
+__host__ __device__ __forceinline__ int sort_items(int64_t n) { return n < kSmallSort ? 4 : kItems; }
+__host__ __device__ __forceinline__ int64_t sort_blocks(int64_t n) {
+    const int64_t t = (int64_t)kThreads * sort_items(n);
+    return (n + t - 1) / t;
+}
+
+// Digit histogram of each block of ITEMS * 256 items, written digit-major so
+// one exclusive scan of the whole table yields every block's output offsets.
+template <int ITEMS>
 __global__ __launch_bounds__(kThreads) void radix_hist_kernel(const uint32_t *keys, int64_t n, int shift,
                                                               uint32_t mask, uint32_t *hist, int64_t blocks) {
     __shared__ uint32_t s_count[kBins];
     s_count[threadIdx.x] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kTileItems;
+    const int64_t base = (int64_t)blockIdx.x * (kThreads * ITEMS);
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
+    for (int k = 0; k < ITEMS; ++k) {
         int64_t i = base + (int64_t)k * kThreads + threadIdx.x;
         if (i < n) atomicAdd(&s_count[(keys[i] >> shift) & mask], 1u);
     }
@@ -152,31 +212,33 @@ __global__ __launch_bounds__(kThreads) void radix_hist_kernel(const uint32_t *ke
     hist[(int64_t)threadIdx.x * blocks + blockIdx.x] = s_count[threadIdx.x];
 }
 
-// Stable scatter of one 4096-item block. Wave w ranks items
-// [w*1024, (w+1)*1024) of the block in 16 rounds of 64; lanes with equal
-// digits find each other with one ballot per digit bit. Items are staged in
-// LDS in digit order and written out with consecutive threads on
+// Stable scatter of one block of ITEMS * 256 items. Wave w ranks items
+// [w*64*ITEMS, (w+1)*64*ITEMS) of the block in ITEMS rounds of 64; lanes
+// with equal digits find each other with one ballot per digit bit. Items are
+// staged in LDS in digit order and written out with consecutive threads on
 // consecutive addresses.
+template <int ITEMS>
 __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(const uint32_t *keys_in, const uint32_t *vals_in,
                                                                  uint32_t *keys_out, uint32_t *vals_out, int64_t n,
                                                                  int shift, int nbits, const uint32_t *offsets,
                                                                  int64_t blocks) {
+    constexpr int TILE_ITEMS = kThreads * ITEMS;
     __shared__ uint32_t s_wcount[kWaves][kBins];
     __shared__ uint32_t s_dstart[kBins];
     __shared__ uint32_t s_wave[kWaves];
-    __shared__ uint32_t s_key[kTileItems];
-    __shared__ uint32_t s_val[kTileItems];
+    __shared__ uint32_t s_key[TILE_ITEMS];
+    __shared__ uint32_t s_val[TILE_ITEMS];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t mask = (1u << nbits) - 1u;
     for (int i = threadIdx.x; i < kWaves * kBins; i += kThreads) (&s_wcount[0][0])[i] = 0;
     __syncthreads();
 
-    const int64_t base = (int64_t)blockIdx.x * kTileItems;
+    const int64_t base = (int64_t)blockIdx.x * TILE_ITEMS;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    uint32_t key[kItems], val[kItems], pos[kItems];
+    uint32_t key[ITEMS], val[ITEMS], pos[ITEMS];
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-        const int64_t i = base + (int64_t)wave * (kItems * 64) + r * 64 + lane;
+    for (int r = 0; r < ITEMS; ++r) {
+        const int64_t i = base + (int64_t)wave * (ITEMS * 64) + r * 64 + lane;
         const bool valid = i < n;
         key[r] = valid ? keys_in[i] : 0u;
         val[r] = valid ? vals_in[i] : 0u;
@@ -210,7 +272,7 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(const uint32_t 
     s_dstart[threadIdx.x] = dstart;
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
+    for (int r = 0; r < ITEMS; ++r) {
         if (pos[r] == 0xffffffffu) continue;
         const uint32_t d = (key[r] >> shift) & mask;
         const uint32_t slot = s_dstart[d] + s_wcount[wave][d] + pos[r];
@@ -227,31 +289,43 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(const uint32_t 
     }
 }
 
+template <int ITEMS>
+hipError_t radix_pass(const uint32_t *k_in, const uint32_t *v_in, uint32_t *k_out, uint32_t *v_out, int64_t n,
+                      int shift, int nb, int64_t blocks, uint32_t *hist, uint32_t *partials, hipStream_t st) {
+    radix_hist_kernel<ITEMS><<<(unsigned)blocks, kThreads, 0, st>>>(k_in, n, shift, (1u << nb) - 1u, hist, blocks);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = device_exclusive_scan(hist, nullptr, hist, blocks * kBins, nullptr, partials, st);
+    if (e != hipSuccess) return e;
+    radix_scatter_kernel<ITEMS><<<(unsigned)blocks, kThreads, 0, st>>>(k_in, v_in, k_out, v_out, n, shift, nb, hist,
+                                                                        blocks);
+    return hipGetLastError();
+}
+
 } // namespace
 
 size_t radix_hist_count(int64_t n) {
-    const int64_t blocks = (n + kTileItems - 1) / kTileItems;
-    return (size_t)blocks * kBins + 8;
+    // Room for every sort of at most n items: below kSmallSort the blocks are smaller, so a
+    // shorter sort can need more blocks than a longer one.
+    int64_t b = sort_blocks(n);
+    if (n >= kSmallSort) b = b > sort_blocks(kSmallSort - 1) ? b : sort_blocks(kSmallSort - 1);
+    return (size_t)b * kBins + 8;
 }
 
 hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n, int bits,
                             uint32_t *hist, uint32_t *partials, int *which, hipStream_t st) {
     *which = 0;
     if (n <= 1 || bits <= 0) return hipSuccess;
-    const int64_t blocks = (n + kTileItems - 1) / kTileItems;
+    const int64_t blocks = sort_blocks(n);
+    const bool small = sort_items(n) == 4;
     uint32_t *ks[2] = {k0, k1}, *vs[2] = {v0, v1};
     int cur = 0;
     for (int shift = 0; shift < bits; shift += 8) {
         const int nb = (bits - shift) < 8 ? (bits - shift) : 8;
-        const uint32_t mask = (1u << nb) - 1u;
-        radix_hist_kernel<<<(unsigned)blocks, kThreads, 0, st>>>(ks[cur], n, shift, mask, hist, blocks);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        e = device_exclusive_scan(hist, nullptr, hist, blocks * kBins, nullptr, partials, st);
-        if (e != hipSuccess) return e;
-        radix_scatter_kernel<<<(unsigned)blocks, kThreads, 0, st>>>(ks[cur], vs[cur], ks[cur ^ 1], vs[cur ^ 1], n,
-                                                                     shift, nb, hist, blocks);
-        e = hipGetLastError();
+        const hipError_t e =
+            small ? radix_pass<4>(ks[cur], vs[cur], ks[cur ^ 1], vs[cur ^ 1], n, shift, nb, blocks, hist, partials, st)
+                  : radix_pass<kItems>(ks[cur], vs[cur], ks[cur ^ 1], vs[cur ^ 1], n, shift, nb, blocks, hist,
+                                       partials, st);
         if (e != hipSuccess) return e;
         cur ^= 1;
     }
