@@ -517,6 +517,7 @@ def main():
             "lane_atomics_plain": int(cp.lane_atomics), "lane_atomics_reduce": int(cr.lane_atomics),
             "atomic_instrs_plain": int(cp.atomic_instrs), "atomic_instrs_reduce": int(cr.atomic_instrs),
             "evaluated_E": int(cr.evaluated), "active_A": int(cr.active), "wave_entries": int(cr.wave_entries),
+            "visited_wave_entries": int(cr.visited), "longest_wave_walk": int(cr.max_wave_visits),
             "reduced_W_R": int(cr.reduced), "plain_lanes_A_lt": int(cr.plain_lanes),
             "threshold_sweep_ms": sweep,
             "composite_bwd_by_mode_ms": {
@@ -574,6 +575,8 @@ def main():
             "speedup_composite_bwd": round(float(np.median(p6) / np.median(r6)), 3),
             "wave_reduce_acc_f32_bwd_ms": round(float(np.median(w6) + np.median(w7)), 4),
             "lane_atomics_plain": int(c3p.lane_atomics), "lane_atomics_reduce": int(c3.lane_atomics),
+            "wave_entries": int(c3.wave_entries), "visited_wave_entries": int(c3.visited),
+            "longest_wave_walk": int(c3.max_wave_visits),
             "threshold_sweep_ms": s3,
         }
         b3.r.release(fr3)

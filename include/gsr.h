@@ -167,10 +167,14 @@ typedef struct {
  *  plain_lanes   A_<: active lanes of wave-entries that issued per-lane atomics
  *  lane_atomics  atomic lane-operations issued (each lane of each atomic instruction)
  *  atomic_instrs atomic instructions issued
- *  hist[c]       wave-entries with c active lanes, c = 0..64 (c = 0 not counted) */
+ *  hist[c]       wave-entries with c active lanes, c = 0..64 (c = 0 not counted)
+ *  visited       (wave, entry) steps the walk took: entries a wave's visit
+ *                masks kept, active lanes or not (>= wave_entries)
+ *  max_wave_visits  the most entries one wave visited (the longest walk) */
 typedef struct {
     uint64_t evaluated, active, wave_entries, reduced, plain_lanes, lane_atomics, atomic_instrs;
     uint64_t hist[65];
+    uint64_t visited, max_wave_visits;
 } gsr_bwd_counters_t;
 
 /* Milliseconds of the stages of the last gsr_render / gsr_backward with

@@ -144,7 +144,7 @@ hipError_t launch_order_tiles(const ViewBatch &vb, int mode, uint2 *work, hipStr
 
 // a6: backward composite.
 struct BwdParams {
-    unsigned long long *counters; // [7 + 65] when counting (one set for the launch)
+    unsigned long long *counters; // [7 + 65 + 2] when counting (one set for the launch)
     int threshold;                // effective: reduce iff active >= threshold (>= 1)
 };
 hipError_t launch_composite_bwd(const ViewBatch &vb, int tile, int lds_batch, int remap, int mode, bool count,

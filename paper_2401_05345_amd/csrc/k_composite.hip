@@ -264,6 +264,9 @@ __global__ __launch_bounds__(TILE *TILE) void composite_fwd_kernel(ViewBatch vb,
 }
 
 enum { CNT_EVAL = 0, CNT_ACTIVE, CNT_WAVE_ENTRIES, CNT_REDUCED, CNT_PLAIN_LANES, CNT_LANE_ATOMICS, CNT_INSTRS, CNT_HIST };
+// after the 65 histogram slots: visited wave-entries (every entry a wave's visit masks keep)
+// and the most entries any one wave visited
+constexpr int CNT_VISITED = CNT_HIST + 65, CNT_MAX_WAVE_VISITS = CNT_HIST + 66, CNT_SLOTS = CNT_HIST + 67;
 
 template <int TILE, int BATCH, int MODE, bool COUNT, bool SPLIT, typename AccT>
 __global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(ViewBatch vb, int remap,
@@ -271,7 +274,7 @@ __global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(ViewBatch vb,
     constexpr int QX = TILE / 8;
     __shared__ float4 s0[BATCH], s1[BATCH], s2[BATCH];
     __shared__ uint32_t s_walk;
-    __shared__ unsigned long long s_cnt[COUNT ? CNT_HIST + 65 : 1];
+    __shared__ unsigned long long s_cnt[COUNT ? CNT_SLOTS : 1];
     // Block pre-reduction: the reduced sums of every wave land in LDS per batch entry, and the
     // block issues one atomic per (tile, Gaussian, value) when the batch is done.
     constexpr bool BLOCK = MODE == GSR_BWD_BLOCK_REDUCE;
@@ -302,7 +305,7 @@ __global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(ViewBatch vb,
 
     if (tid == 0) s_walk = 0;
     if (COUNT)
-        for (int i = tid; i < CNT_HIST + 65; i += TILE * TILE) s_cnt[i] = 0;
+        for (int i = tid; i < CNT_SLOTS; i += TILE * TILE) s_cnt[i] = 0;
     __syncthreads();
     // Entries past every pixel's n_contrib contribute nothing: the block walks to its deepest
     // pixel, each wave only to its own.
@@ -311,7 +314,7 @@ __global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(ViewBatch vb,
     __syncthreads();
     const int walk = (int)s_walk;
 
-    uint64_t c_eval = 0, c_active = 0, c_we = 0, c_red = 0, c_plain = 0, c_instr = 0;
+    uint64_t c_eval = 0, c_active = 0, c_we = 0, c_red = 0, c_plain = 0, c_instr = 0, c_visit = 0;
     uint32_t issued = 0;
     if (COUNT) {
         // E = sum of n_contrib: every pixel walks its entries 1..n_contrib.
@@ -399,6 +402,7 @@ __global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(ViewBatch vb,
                 }
                 if (COUNT) {
                     const int ca = __popcll(am);
+                    c_visit += 1;
                     c_active += ca;
                     if (ca) {
                         c_we += 1;
@@ -439,10 +443,15 @@ __global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(ViewBatch vb,
             atomicAdd(&s_cnt[CNT_REDUCED], (unsigned long long)c_red);
             atomicAdd(&s_cnt[CNT_PLAIN_LANES], (unsigned long long)c_plain);
             atomicAdd(&s_cnt[CNT_INSTRS], (unsigned long long)c_instr);
+            atomicAdd(&s_cnt[CNT_VISITED], (unsigned long long)c_visit);
+            atomicMax(&s_cnt[CNT_MAX_WAVE_VISITS], (unsigned long long)c_visit);
         }
         __syncthreads();
-        for (int i = tid; i < CNT_HIST + 65; i += TILE * TILE)
-            if (s_cnt[i]) atomicAdd(&p.counters[i], s_cnt[i]);
+        for (int i = tid; i < CNT_SLOTS; i += TILE * TILE)
+            if (s_cnt[i]) {
+                if (i == CNT_MAX_WAVE_VISITS) atomicMax(&p.counters[i], s_cnt[i]);
+                else atomicAdd(&p.counters[i], s_cnt[i]);
+            }
     }
 }
 

@@ -193,17 +193,21 @@ def test_batch_counters_are_sums(renderer, small):
         tot = gsr.gsr_bwd_counters(renderer.ctx, states[0])
         with pytest.raises(gsr.GsrError):
             gsr.gsr_bwd_counters(renderer.ctx, states[1])
-        keys = ("evaluated", "active", "wave_entries", "reduced", "plain_lanes", "lane_atomics", "atomic_instrs")
+        keys = ("evaluated", "active", "wave_entries", "reduced", "plain_lanes", "lane_atomics", "atomic_instrs",
+                "visited")
         acc = dict.fromkeys(keys, 0)
         hist = np.zeros(65, np.int64)
+        longest = 0
         for i, g in enumerate(gss):
             _backward_batch(renderer, [g], [states[i]], [dls[i]], cfg)
             c = gsr.gsr_bwd_counters(renderer.ctx, states[i])
             for k in keys:
                 acc[k] += getattr(c, k)
             hist += np.array(c.hist[:], np.int64)
+            longest = max(longest, c.max_wave_visits)
         for k in keys:
             assert getattr(tot, k) == acc[k], k
+        assert tot.max_wave_visits == longest
         assert np.array_equal(np.array(tot.hist[:], np.int64), hist)
         assert tot.evaluated > 0
     finally:

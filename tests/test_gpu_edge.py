@@ -178,6 +178,8 @@ def test_backward_counters_match_the_atomic_count_model(renderer):
                 assert abs(int(c.evaluated) - int(rr.n_contrib.sum())) <= 64 * (~keep).sum()
             assert int(c.evaluated) == int(out["n_contrib"].astype(np.int64).sum())
             assert hist[0] == 0 and hist.sum() == c.wave_entries and (hist * lanes).sum() == c.active
+            # every visited entry is a step of one wave's walk; the longest walk is one of them
+            assert c.visited >= c.wave_entries and 0 < c.max_wave_visits <= c.visited
             t = max(thr, 1)
             if mode == gsr.GSR_BWD_PLAIN_ATOMIC:
                 assert c.reduced == 0 and c.plain_lanes == c.active
