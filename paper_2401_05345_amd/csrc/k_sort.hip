@@ -45,21 +45,37 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *s
     return off + inc - v;
 }
 
-__device__ __forceinline__ uint32_t load_item(const uint32_t *in, const uint32_t *gather, int64_t i) {
-    return gather ? in[gather[i]] : in[i];
+// A thread's K items at positions pos(k) < n, zero past the end. The loads are
+// unconditional (positions clamped to n - 1, n >= 1) and issued together, the
+// gathered ones after all their indices: bounds tests around each load would
+// make the compiler wait for every load before issuing the next.
+template <int K, bool GATHER, typename Pos>
+__device__ __forceinline__ void load_items(const uint32_t *in, const uint32_t *gather, int64_t n, Pos pos,
+                                           uint32_t (&v)[K]) {
+    int64_t idx[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) idx[k] = pos(k) < n ? pos(k) : n - 1;
+    if (GATHER) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) idx[k] = gather[idx[k]];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = in[idx[k]];
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = pos(k) < n ? v[k] : 0u;
 }
 
 // Per-block sums of 4096 consecutive items.
+template <bool GATHER>
 __global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const uint32_t *in, const uint32_t *gather,
                                                                int64_t n, uint32_t *partials) {
     __shared__ uint32_t s_wave[kWaves];
-    const int64_t base = (int64_t)blockIdx.x * kTileItems;
+    const int64_t base = (int64_t)blockIdx.x * kTileItems + threadIdx.x;
+    uint32_t v[kItems];
+    load_items<kItems, GATHER>(in, gather, n, [&](int k) { return base + (int64_t)k * kThreads; }, v);
     uint32_t s = 0;
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-        int64_t i = base + (int64_t)k * kThreads + threadIdx.x;
-        if (i < n) s += load_item(in, gather, i);
-    }
+    for (int k = 0; k < kItems; ++k) s += v[k];
     uint32_t total;
     block_exclusive_scan(s, s_wave, total);
     if (threadIdx.x == 0) partials[blockIdx.x] = total;
@@ -68,19 +84,17 @@ __global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const uint32_t *i
 // Exclusive scan of each block's 4096 items plus the block's offset
 // (offsets == nullptr: single block, offset 0). Thread t owns items
 // [t*16, t*16+16) of the block so the order is the natural one.
+template <bool GATHER>
 __global__ __launch_bounds__(kThreads) void scan_apply_kernel(const uint32_t *in, const uint32_t *gather, int64_t n,
                                                               const uint32_t *offsets, uint32_t *out,
                                                               uint32_t *total_out) {
     __shared__ uint32_t s_wave[kWaves];
     const int64_t base = (int64_t)blockIdx.x * kTileItems + (int64_t)threadIdx.x * kItems;
     uint32_t v[kItems];
+    load_items<kItems, GATHER>(in, gather, n, [&](int k) { return base + k; }, v);
     uint32_t s = 0;
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-        int64_t i = base + k;
-        v[k] = (i < n) ? load_item(in, gather, i) : 0u;
-        s += v[k];
-    }
+    for (int k = 0; k < kItems; ++k) s += v[k];
     uint32_t total;
     uint32_t run = block_exclusive_scan(s, s_wave, total) + (offsets ? offsets[blockIdx.x] : 0u);
 #pragma unroll
@@ -102,6 +116,7 @@ __global__ __launch_bounds__(kThreads) void scan_apply_kernel(const uint32_t *in
 constexpr int kOneThreads = 1024;
 constexpr int64_t kOneBlockMax = 4 * kOneThreads * kItems; // 65536
 
+template <bool GATHER>
 __global__ __launch_bounds__(kOneThreads) void scan_one_block_kernel(const uint32_t *in, const uint32_t *gather,
                                                                      int64_t n, uint32_t *out, uint32_t *total_out) {
     __shared__ uint32_t s_wave[kOneThreads / 64];
@@ -110,13 +125,10 @@ __global__ __launch_bounds__(kOneThreads) void scan_one_block_kernel(const uint3
     for (int64_t tile = 0; tile < n; tile += (int64_t)kOneThreads * kItems) {
         const int64_t base = tile + (int64_t)threadIdx.x * kItems;
         uint32_t v[kItems];
+        load_items<kItems, GATHER>(in, gather, n, [&](int k) { return base + k; }, v);
         uint32_t sum = 0;
 #pragma unroll
-        for (int k = 0; k < kItems; ++k) {
-            const int64_t i = base + k;
-            v[k] = (i < n) ? load_item(in, gather, i) : 0u;
-            sum += v[k];
-        }
+        for (int k = 0; k < kItems; ++k) sum += v[k];
         const uint32_t inc = wave_inclusive_scan(sum, lane);
         if (lane == 63) s_wave[wave] = inc;
         __syncthreads();
@@ -161,20 +173,24 @@ hipError_t device_exclusive_scan(const uint32_t *in, const uint32_t *gather, uin
     }
     const int64_t blocks = (n + kTileItems - 1) / kTileItems;
     if (blocks == 1) {
-        scan_apply_kernel<<<1, kThreads, 0, st>>>(in, gather, n, nullptr, out, total);
+        if (gather) scan_apply_kernel<true><<<1, kThreads, 0, st>>>(in, gather, n, nullptr, out, total);
+        else scan_apply_kernel<false><<<1, kThreads, 0, st>>>(in, gather, n, nullptr, out, total);
         return hipGetLastError();
     }
     if (n <= kOneBlockMax) {
-        scan_one_block_kernel<<<1, kOneThreads, 0, st>>>(in, gather, n, out, total);
+        if (gather) scan_one_block_kernel<true><<<1, kOneThreads, 0, st>>>(in, gather, n, out, total);
+        else scan_one_block_kernel<false><<<1, kOneThreads, 0, st>>>(in, gather, n, out, total);
         return hipGetLastError();
     }
-    scan_reduce_kernel<<<(unsigned)blocks, kThreads, 0, st>>>(in, gather, n, partials);
+    if (gather) scan_reduce_kernel<true><<<(unsigned)blocks, kThreads, 0, st>>>(in, gather, n, partials);
+    else scan_reduce_kernel<false><<<(unsigned)blocks, kThreads, 0, st>>>(in, gather, n, partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // Scan the partials in place (recursively), then apply.
     e = device_exclusive_scan(partials, nullptr, partials, blocks, nullptr, partials + blocks + 1, st);
     if (e != hipSuccess) return e;
-    scan_apply_kernel<<<(unsigned)blocks, kThreads, 0, st>>>(in, gather, n, partials, out, total);
+    if (gather) scan_apply_kernel<true><<<(unsigned)blocks, kThreads, 0, st>>>(in, gather, n, partials, out, total);
+    else scan_apply_kernel<false><<<(unsigned)blocks, kThreads, 0, st>>>(in, gather, n, partials, out, total);
     return hipGetLastError();
 }
 
@@ -202,12 +218,13 @@ __global__ __launch_bounds__(kThreads) void radix_hist_kernel(const uint32_t *ke
     __shared__ uint32_t s_count[kBins];
     s_count[threadIdx.x] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * (kThreads * ITEMS);
+    const int64_t base = (int64_t)blockIdx.x * (kThreads * ITEMS) + threadIdx.x;
+    uint32_t k[ITEMS];
+    const auto pos = [&](int r) { return base + (int64_t)r * kThreads; };
+    load_items<ITEMS, false>(keys, nullptr, n, pos, k);
 #pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-        int64_t i = base + (int64_t)k * kThreads + threadIdx.x;
-        if (i < n) atomicAdd(&s_count[(keys[i] >> shift) & mask], 1u);
-    }
+    for (int r = 0; r < ITEMS; ++r)
+        if (pos(r) < n) atomicAdd(&s_count[(k[r] >> shift) & mask], 1u);
     __syncthreads();
     hist[(int64_t)threadIdx.x * blocks + blockIdx.x] = s_count[threadIdx.x];
 }
@@ -236,12 +253,13 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(const uint32_t 
     const int64_t base = (int64_t)blockIdx.x * TILE_ITEMS;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     uint32_t key[ITEMS], val[ITEMS], pos[ITEMS];
+    const int64_t first = base + (int64_t)wave * (ITEMS * 64) + lane;
+    const auto at = [&](int r) { return first + r * 64; };
+    load_items<ITEMS, false>(keys_in, nullptr, n, at, key);
+    load_items<ITEMS, false>(vals_in, nullptr, n, at, val);
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
-        const int64_t i = base + (int64_t)wave * (ITEMS * 64) + r * 64 + lane;
-        const bool valid = i < n;
-        key[r] = valid ? keys_in[i] : 0u;
-        val[r] = valid ? vals_in[i] : 0u;
+        const bool valid = at(r) < n;
         const uint32_t d = (key[r] >> shift) & mask;
         uint64_t peers = __ballot(valid);
         for (int b = 0; b < nbits; ++b) {
