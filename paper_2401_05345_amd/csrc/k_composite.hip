@@ -338,84 +338,93 @@ __global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(ViewBatch vb,
         // Entries this wave must visit (at or below its walk bound, not culled), one bit each.
         uint64_t vis[BATCH / 64];
         wave_visit_masks<BATCH>(s0, s1, s2, jtop + 1, qcx, qcy, lane, vis);
+        // One visited entry for the whole wave (uniform control flow).
+        const auto visit = [&](int j, const float4 &r0, const float4 &r1, const float4 &r2) {
+            const uint32_t pos = (uint32_t)(start + j + 1);
+            const float rb = r2.x;
+            const SplatEval e = eval_splat(fpx, fpy, r0.x, r0.y, r0.z, r0.w, r1.x, r1.y);
+            const bool walked = pos <= nc;
+            const bool active = walked && e.pass;
+            // the ballot as the AND of the three compares' own lane masks
+            const uint64_t am = __ballot(walked) & __ballot(!(e.lp > 0.0f)) & __ballot(e.alpha >= kAlphaMin);
+            // Lanes that skip this entry run the same arithmetic with alpha, G and o G set to
+            // zero: their nine values come out as zeros and T, S stay as they are.
+            const float al = active ? e.alpha : 0.0f;
+            const float gz = active ? e.G : 0.0f;
+            const float rz = active ? e.raw : 0.0f;
+            // Transmittance in front of this entry; hardware reciprocal (1 ulp) instead of the
+            // IEEE division sequence.
+            const float Tin = T * __builtin_amdgcn_rcpf(1.0f - al);
+            T = active ? Tin : T;
+            float v[9];
+            const float w = al * T;
+            v[6] = w * G0;
+            v[7] = w * G1;
+            v[8] = w * G2;
+            const float dc = (r1.z * G0 + r1.w * G1 + rb * G2) - S;
+            const float dL_dalpha = T * dc;
+            S = fmaf(al, dc, S);
+            const float dL_doG = rz > kAlphaMax ? 0.0f : dL_dalpha; // alpha = min(0.99, o G)
+            v[5] = gz * dL_doG;
+            // Moments of dL/dpower over the pixel offsets; the conic, the same for every pixel,
+            // turns them into the mean and conic gradients once per Gaussian.
+            const float dL_dp = rz * dL_doG;
+            const float mx = dL_dp * e.dx, my = dL_dp * e.dy;
+            v[0] = mx;
+            v[1] = my;
+            v[2] = mx * e.dx;
+            v[3] = mx * e.dy;
+            v[4] = my * e.dy;
+            // The record carries its Gaussian's id (the same in every lane): the row address is
+            // formed in scalar registers.
+            const uint32_t gid = (uint32_t)__builtin_amdgcn_readfirstlane((int)__float_as_uint(r2.y));
+            AccT *dst = static_cast<AccT *>(a.acc) + (size_t)gid * GSR_ACC_STRIDE;
+            uint64_t red_mask = 0;
+            if (BLOCK) {
+                if (__popcll(am) >= p.threshold) {
+                    red_mask = am;
+                    const float mine = wave_sum9_scatter(v, lane);
+                    if (sum9_issues(lane)) atomicAdd(&s_acc[j * 9 + sum9_slot(lane)], mine);
+                    if (lane == 0) s_touch[j] = 1u;
+                } else if (active) {
+    #pragma unroll
+                    for (int k = 0; k < 9; ++k) atomic_acc(dst + k, v[k]);
+                    issued += 9;
+                }
+            } else {
+                issued += emit9<MODE, SPLIT>(active, am, v, dst, p.threshold, lane, red_mask);
+            }
+            if (COUNT) {
+                const int ca = __popcll(am);
+                c_visit += 1;
+                c_active += ca;
+                if (ca) {
+                    c_we += 1;
+                    if (red_mask) {
+                        c_red += 1;
+                        c_instr += BLOCK ? 0 : ((SPLIT || MODE == GSR_BWD_SERIAL_REDUCE) ? 1 : 9);
+                    } else {
+                        c_plain += ca;
+                        c_instr += 9;
+                    }
+                    if (lane == 0) atomicAdd(&s_cnt[CNT_HIST + ca], 1ull);
+                }
+            }
+        };
 #pragma unroll
         for (int q = BATCH / 64 - 1; q >= 0; --q) {
+            // Visited entries two at a time, last first: both records are read before the first
+            // is processed (an odd last one is paired with itself and not processed twice).
             for (uint64_t mq = vis[q]; mq;) {
-                const int b = 63 - __builtin_clzll(mq);
-                mq ^= 1ull << b;
-                const int j = q * 64 + b;
-                const uint32_t pos = (uint32_t)(start + j + 1);
-                const float4 r0 = s0[j], r2 = s2[j];
-                const float4 r1 = s1[j];
-                const float rb = r2.x;
-                const SplatEval e = eval_splat(fpx, fpy, r0.x, r0.y, r0.z, r0.w, r1.x, r1.y);
-                const bool walked = pos <= nc;
-                const bool active = walked && e.pass;
-                // the ballot as the AND of the three compares' own lane masks
-                const uint64_t am = __ballot(walked) & __ballot(!(e.lp > 0.0f)) & __ballot(e.alpha >= kAlphaMin);
-                // Lanes that skip this entry run the same arithmetic with alpha, G and o G set to
-                // zero: their nine values come out as zeros and T, Q stay as they are.
-                const float al = active ? e.alpha : 0.0f;
-                const float gz = active ? e.G : 0.0f;
-                const float rz = active ? e.raw : 0.0f;
-                // Transmittance in front of this entry; hardware reciprocal (1 ulp) instead of the
-                // IEEE division sequence.
-                const float Tin = T * __builtin_amdgcn_rcpf(1.0f - al);
-                T = active ? Tin : T;
-                float v[9];
-                const float w = al * T;
-                v[6] = w * G0;
-                v[7] = w * G1;
-                v[8] = w * G2;
-                const float dc = (r1.z * G0 + r1.w * G1 + rb * G2) - S;
-                const float dL_dalpha = T * dc;
-                S = fmaf(al, dc, S);
-                const float dL_doG = rz > kAlphaMax ? 0.0f : dL_dalpha; // alpha = min(0.99, o G)
-                v[5] = gz * dL_doG;
-                // Moments of dL/dpower over the pixel offsets; the conic, the same for every pixel,
-                // turns them into the mean and conic gradients once per Gaussian.
-                const float dL_dp = rz * dL_doG;
-                const float mx = dL_dp * e.dx, my = dL_dp * e.dy;
-                v[0] = mx;
-                v[1] = my;
-                v[2] = mx * e.dx;
-                v[3] = mx * e.dy;
-                v[4] = my * e.dy;
-                // The record carries its Gaussian's id (the same in every lane): the row address is
-                // formed in scalar registers.
-                const uint32_t gid = (uint32_t)__builtin_amdgcn_readfirstlane((int)__float_as_uint(r2.y));
-                AccT *dst = static_cast<AccT *>(a.acc) + (size_t)gid * GSR_ACC_STRIDE;
-                uint64_t red_mask = 0;
-                if (BLOCK) {
-                    if (__popcll(am) >= p.threshold) {
-                        red_mask = am;
-                        const float mine = wave_sum9_scatter(v, lane);
-                        if (sum9_issues(lane)) atomicAdd(&s_acc[j * 9 + sum9_slot(lane)], mine);
-                        if (lane == 0) s_touch[j] = 1u;
-                    } else if (active) {
-    #pragma unroll
-                        for (int k = 0; k < 9; ++k) atomic_acc(dst + k, v[k]);
-                        issued += 9;
-                    }
-                } else {
-                    issued += emit9<MODE, SPLIT>(active, am, v, dst, p.threshold, lane, red_mask);
-                }
-                if (COUNT) {
-                    const int ca = __popcll(am);
-                    c_visit += 1;
-                    c_active += ca;
-                    if (ca) {
-                        c_we += 1;
-                        if (red_mask) {
-                            c_red += 1;
-                            c_instr += BLOCK ? 0 : ((SPLIT || MODE == GSR_BWD_SERIAL_REDUCE) ? 1 : 9);
-                        } else {
-                            c_plain += ca;
-                            c_instr += 9;
-                        }
-                        if (lane == 0) atomicAdd(&s_cnt[CNT_HIST + ca], 1ull);
-                    }
-                }
+                const int j1 = q * 64 + 63 - __builtin_clzll(mq);
+                mq ^= 1ull << (j1 - q * 64);
+                const bool two = mq != 0;
+                const int j2 = two ? q * 64 + 63 - __builtin_clzll(mq) : j1;
+                mq = two ? mq ^ (1ull << (j2 - q * 64)) : mq;
+                const float4 a0 = s0[j1], a1 = s1[j1], a2 = s2[j1];
+                const float4 b0 = s0[j2], b1 = s1[j2], b2 = s2[j2];
+                visit(j1, a0, a1, a2);
+                if (two) visit(j2, b0, b1, b2);
             }
         }
         if (BLOCK) {
@@ -484,41 +493,86 @@ __global__ __launch_bounds__(256) void l1_grad_kernel(const float *image, const 
 // is one pool of tiles). Work = the tile's deepest n_contrib (tile_walk) or
 // its list length. Counting sort on a log-scale bucket of the work (16
 // buckets per octave), one block.
-__device__ __forceinline__ uint2 locate(const ViewBatch &vb, uint32_t i) {
-    int v = 0;
-    while (v + 1 < vb.n && i >= vb.base[v + 1]) ++v;
-    return make_uint2((uint32_t)v, i - vb.base[v]);
-}
 
 __global__ __launch_bounds__(1024) void order_tiles_kernel(ViewBatch vb, int mode, uint2 *work) {
     __shared__ uint32_t s_count[256];
+    // The views' tile bases and work arrays, copied once: indexing the by-value argument with a
+    // per-item view number would reload them from memory for every item.
+    __shared__ uint32_t s_base[kMaxViews + 1];
+    __shared__ const uint32_t *s_walk[kMaxViews];
+    __shared__ const uint2 *s_ranges[kMaxViews];
     const uint32_t n = vb.base[vb.n];
-    if (mode == ORDER_IDENTITY) {
-        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) work[i] = locate(vb, i);
-        return;
+    if (threadIdx.x <= (unsigned)vb.n) s_base[threadIdx.x] = vb.base[threadIdx.x];
+    if (threadIdx.x < (unsigned)vb.n) {
+        s_walk[threadIdx.x] = vb.v[threadIdx.x].tile_walk;
+        s_ranges[threadIdx.x] = vb.v[threadIdx.x].ranges;
     }
     if (threadIdx.x < 256) s_count[threadIdx.x] = 0;
     __syncthreads();
+    const int nv = vb.n;
+    const auto locate_s = [&](uint32_t i) {
+        int v = 0;
+        while (v + 1 < nv && i >= s_base[v + 1]) ++v;
+        return make_uint2((uint32_t)v, i - s_base[v]);
+    };
+    if (mode == ORDER_IDENTITY) {
+        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) work[i] = locate_s(i);
+        return;
+    }
     const auto bucket = [&](uint2 vt) -> uint32_t {
-        const ViewDesc &d = vb.v[vt.x];
-        const uint32_t w = mode == ORDER_BY_WALK ? d.tile_walk[vt.y] : d.ranges[vt.y].y - d.ranges[vt.y].x;
+        uint32_t w;
+        if (mode == ORDER_BY_WALK) {
+            w = s_walk[vt.x][vt.y];
+        } else {
+            const uint2 r = s_ranges[vt.x][vt.y];
+            w = r.y - r.x;
+        }
         const int b = w ? min(255, 1 + (int)(16.0f * __log2f((float)w))) : 0;
         return 255u - (uint32_t)b; // ascending key = descending work
     };
-    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) atomicAdd(&s_count[bucket(locate(vb, i))], 1u);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t run = 0;
-        for (int b = 0; b < 256; ++b) {
-            const uint32_t c = s_count[b];
-            s_count[b] = run;
-            run += c;
-        }
+    // Four items per thread and round, their work values loaded together (positions clamped to
+    // the last item instead of a test around each load, which would serialise the loads).
+    constexpr int U = 4;
+    for (uint32_t i0 = threadIdx.x; i0 < n; i0 += U * blockDim.x) {
+        uint32_t b[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) b[u] = bucket(locate_s(min(i0 + u * blockDim.x, n - 1)));
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (i0 + u * blockDim.x < n) atomicAdd(&s_count[b[u]], 1u);
     }
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
-        const uint2 vt = locate(vb, i);
-        work[atomicAdd(&s_count[bucket(vt)], 1u)] = vt;
+    // Exclusive scan of the 256 bucket counts by the first four waves.
+    __shared__ uint32_t s_part[4];
+    uint32_t c = 0, inc = 0;
+    if (threadIdx.x < 256) {
+        c = s_count[threadIdx.x];
+        inc = c;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t o = __shfl_up(inc, d, 64);
+            if ((threadIdx.x & 63) >= d) inc += o;
+        }
+        if ((threadIdx.x & 63) == 63) s_part[threadIdx.x >> 6] = inc;
+    }
+    __syncthreads();
+    if (threadIdx.x < 256) {
+        uint32_t off = 0;
+        for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) off += s_part[w];
+        s_count[threadIdx.x] = off + inc - c;
+    }
+    __syncthreads();
+    for (uint32_t i0 = threadIdx.x; i0 < n; i0 += U * blockDim.x) {
+        uint2 vt[U];
+        uint32_t b[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            vt[u] = locate_s(min(i0 + u * blockDim.x, n - 1));
+            b[u] = bucket(vt[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (i0 + u * blockDim.x < n) work[atomicAdd(&s_count[b[u]], 1u)] = vt[u];
     }
 }
 

@@ -65,6 +65,52 @@ __device__ __forceinline__ void load_items(const uint32_t *in, const uint32_t *g
     for (int k = 0; k < K; ++k) v[k] = pos(k) < n ? v[k] : 0u;
 }
 
+// A thread's kItems consecutive items [base, base + kItems): four 16-byte
+// loads when the chunk is whole, ungathered and 16-byte aligned (a wave's
+// scalar loads of consecutive chunks would fetch every line kItems times
+// through the CU's L1), else the clamped scalar loads.
+template <bool GATHER>
+__device__ __forceinline__ void load_chunk(const uint32_t *in, const uint32_t *gather, int64_t n, int64_t base,
+                                           uint32_t (&v)[kItems]) {
+    if (!GATHER && base + kItems <= n && ((reinterpret_cast<uintptr_t>(in) & 15) == 0)) {
+        const uint4 *p = reinterpret_cast<const uint4 *>(in + base);
+        uint4 q[kItems / 4];
+#pragma unroll
+        for (int c = 0; c < kItems / 4; ++c) q[c] = p[c];
+#pragma unroll
+        for (int c = 0; c < kItems / 4; ++c) {
+            v[4 * c] = q[c].x;
+            v[4 * c + 1] = q[c].y;
+            v[4 * c + 2] = q[c].z;
+            v[4 * c + 3] = q[c].w;
+        }
+        return;
+    }
+    load_items<kItems, GATHER>(in, gather, n, [&](int k) { return base + k; }, v);
+}
+
+// out[base + k] = run + v[0] + ... + v[k-1] for the positions below n (16-byte stores when whole
+// and aligned); returns run plus all kItems values.
+__device__ __forceinline__ uint32_t store_chunk_scan(uint32_t *out, int64_t n, int64_t base, uint32_t run,
+                                                     const uint32_t (&v)[kItems]) {
+    uint32_t o[kItems];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        o[k] = run;
+        run += v[k];
+    }
+    if (base + kItems <= n && ((reinterpret_cast<uintptr_t>(out) & 15) == 0)) {
+        uint4 *p = reinterpret_cast<uint4 *>(out + base);
+#pragma unroll
+        for (int c = 0; c < kItems / 4; ++c) p[c] = make_uint4(o[4 * c], o[4 * c + 1], o[4 * c + 2], o[4 * c + 3]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < kItems; ++k)
+            if (base + k < n) out[base + k] = o[k];
+    }
+    return run;
+}
+
 // Per-block sums of 4096 consecutive items.
 template <bool GATHER>
 __global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const uint32_t *in, const uint32_t *gather,
@@ -91,18 +137,13 @@ __global__ __launch_bounds__(kThreads) void scan_apply_kernel(const uint32_t *in
     __shared__ uint32_t s_wave[kWaves];
     const int64_t base = (int64_t)blockIdx.x * kTileItems + (int64_t)threadIdx.x * kItems;
     uint32_t v[kItems];
-    load_items<kItems, GATHER>(in, gather, n, [&](int k) { return base + k; }, v);
+    load_chunk<GATHER>(in, gather, n, base, v);
     uint32_t s = 0;
 #pragma unroll
     for (int k = 0; k < kItems; ++k) s += v[k];
     uint32_t total;
     uint32_t run = block_exclusive_scan(s, s_wave, total) + (offsets ? offsets[blockIdx.x] : 0u);
-#pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-        int64_t i = base + k;
-        if (i < n) out[i] = run;
-        run += v[k];
-    }
+    run = store_chunk_scan(out, n, base, run, v);
     if (total_out && blockIdx.x == gridDim.x - 1 && threadIdx.x == kThreads - 1) {
         // Last item of the last block: its exclusive prefix plus itself is the grand total.
         *total_out = run;
@@ -125,7 +166,7 @@ __global__ __launch_bounds__(kOneThreads) void scan_one_block_kernel(const uint3
     for (int64_t tile = 0; tile < n; tile += (int64_t)kOneThreads * kItems) {
         const int64_t base = tile + (int64_t)threadIdx.x * kItems;
         uint32_t v[kItems];
-        load_items<kItems, GATHER>(in, gather, n, [&](int k) { return base + k; }, v);
+        load_chunk<GATHER>(in, gather, n, base, v);
         uint32_t sum = 0;
 #pragma unroll
         for (int k = 0; k < kItems; ++k) sum += v[k];
@@ -140,13 +181,7 @@ __global__ __launch_bounds__(kOneThreads) void scan_one_block_kernel(const uint3
             tot += x;
         }
         __syncthreads();
-        uint32_t run = carry + off + inc - sum;
-#pragma unroll
-        for (int k = 0; k < kItems; ++k) {
-            const int64_t i = base + k;
-            if (i < n) out[i] = run;
-            run += v[k];
-        }
+        store_chunk_scan(out, n, base, carry + off + inc - sum, v);
         carry += tot;
     }
     if (total_out && threadIdx.x == 0) *total_out = carry;
