@@ -186,6 +186,13 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"libgsr is not built ({path} missing); run python -m paper_2401_05345_amd.build")
+    try:
+        # torch first: its wheel brings its own HIP runtime, and the library must bind to that one
+        # (loaded the other way round, both runtimes end up in the process and context creation
+        # fails).
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     for name, (res, args) in _PROTOS.items():
         fn = getattr(lib, name)
