@@ -142,8 +142,9 @@ typedef struct {
  *  composited entry, 0 = none), acc [n,GSR_ACC_STRIDE] (the last backward's
  *  accumulators as fp32 gradients in the column order of GSR_ACC_STRIDE,
  *  whatever their precision; rows of culled Gaussians read 0. The composite
- *  accumulates moments of dL/dpower, which the export turns into mean and
- *  conic gradients with the state's current conics). */
+ *  accumulates moments of each pixel's dL/do over the pixel offsets, which
+ *  the export turns into mean and conic gradients with the state's current
+ *  opacities and conics). */
 typedef struct {
     float *mean2d;
     float *conic_opacity;

@@ -7,8 +7,8 @@
 //   offsets    [n] uint32 exclusive scan of tiles_touched in depth order
 //   pair_tile / pair_id [P] uint32 (+ alternates for the radix sort)
 //   ranges     [tiles] uint2, T_final [HW] f32, n_contrib [HW] uint32
-//   acc        [n][GSR_ACC_STRIDE] f32 or f64 backward accumulators: five moments of dL/dpower
-//              over the pixel offsets, dL/do, dL/drgb
+//   acc        [n][GSR_ACC_STRIDE] f32 or f64 backward accumulators: five moments of the
+//              pixels' dL/do over the pixel offsets, dL/do, dL/drgb
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -68,7 +68,8 @@ hipError_t launch_preprocess_bwd(const gsr_scene &s, const DevCamera &cam, const
 // Zero the accumulator rows of Gaussians with radius > 0 (the only rows the composite writes).
 hipError_t launch_zero_visible_rows(const int32_t *radius, int64_t n, void *acc, bool acc_f64, hipStream_t st);
 // Accumulator rows as fp32 gradients [n][GSR_ACC_STRIDE] (dL/du, dL/dv, dL/dA, dL/dB, dL/dC,
-// dL/do, dL/drgb: the moments converted with the record's conic), culled rows as zeros.
+// dL/do, dL/drgb: the moments converted with the record's opacity and conic), culled rows as
+// zeros.
 hipError_t launch_export_acc(const int32_t *radius, const float4 *rec, int64_t n, const void *acc, bool acc_f64,
                              float *dst, hipStream_t st);
 

@@ -351,7 +351,6 @@ __global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(ViewBatch vb,
             // zero: their nine values come out as zeros and T, S stay as they are.
             const float al = active ? e.alpha : 0.0f;
             const float gz = active ? e.G : 0.0f;
-            const float rz = active ? e.raw : 0.0f;
             // Transmittance in front of this entry; hardware reciprocal (1 ulp) instead of the
             // IEEE division sequence.
             const float Tin = T * __builtin_amdgcn_rcpf(1.0f - al);
@@ -364,12 +363,14 @@ __global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(ViewBatch vb,
             const float dc = (r1.z * G0 + r1.w * G1 + rb * G2) - S;
             const float dL_dalpha = T * dc;
             S = fmaf(al, dc, S);
-            const float dL_doG = rz > kAlphaMax ? 0.0f : dL_dalpha; // alpha = min(0.99, o G)
-            v[5] = gz * dL_doG;
-            // Moments of dL/dpower over the pixel offsets; the conic, the same for every pixel,
-            // turns them into the mean and conic gradients once per Gaussian.
-            const float dL_dp = rz * dL_doG;
-            const float mx = dL_dp * e.dx, my = dL_dp * e.dy;
+            // h = dL/do of this pixel = G dL/d(oG), zero where alpha = min(0.99, o G) saturates
+            // (and, through gz, for lanes that skip the entry).
+            const float h = gz * (e.raw > kAlphaMax ? 0.0f : dL_dalpha);
+            v[5] = h;
+            // dL/dpower = o G dL/d(oG) = o h. Moments of h over the pixel offsets: o and the conic,
+            // the same for every pixel, turn them into the mean and conic gradients once per
+            // Gaussian.
+            const float mx = h * e.dx, my = h * e.dy;
             v[0] = mx;
             v[1] = my;
             v[2] = mx * e.dx;

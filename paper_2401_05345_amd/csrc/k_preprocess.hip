@@ -241,21 +241,24 @@ __global__ __launch_bounds__(256) void preprocess_bwd_kernel(int n, const float 
     }
 }
 
-// The backward composite adds, per Gaussian, the five moments of g = dL/dpower
-// over the pixel offsets (dx, dy) = (px - u, py - v):
-//   m = (sum g dx, sum g dy, sum g dx^2, sum g dx dy, sum g dy^2).
-// With power = -0.5 (A dx^2 + C dy^2) - B dx dy and (A, B, C) the same for
-// every pixel, the mean and conic gradients follow as
-//   dL/du = A m0 + B m1, dL/dv = B m0 + C m1,
-//   dL/dA = -0.5 m2, dL/dB = -m3, dL/dC = -0.5 m4,
+// The backward composite adds, per Gaussian, the five moments of h = dL/do
+// (each pixel's G dL/d(oG)) over the pixel offsets (dx, dy) = (px - u, py - v):
+//   m = (sum h dx, sum h dy, sum h dx^2, sum h dx dy, sum h dy^2).
+// A pixel's dL/dpower is o h. With power = -0.5 (A dx^2 + C dy^2) - B dx dy
+// and o, (A, B, C) the same for every pixel, the mean and conic gradients
+// follow as
+//   dL/du = o (A m0 + B m1), dL/dv = o (B m0 + C m1),
+//   dL/dA = -o m2 / 2, dL/dB = -o m3, dL/dC = -o m4 / 2,
 // in the accumulators' precision.
 template <typename AccT>
-__device__ __forceinline__ void moments_to_grads(const AccT *m, float A, float B, float C, float (&g)[5]) {
-    g[0] = (float)((AccT)A * m[0] + (AccT)B * m[1]);
-    g[1] = (float)((AccT)B * m[0] + (AccT)C * m[1]);
-    g[2] = (float)((AccT)-0.5 * m[2]);
-    g[3] = (float)(-m[3]);
-    g[4] = (float)((AccT)-0.5 * m[4]);
+__device__ __forceinline__ void moments_to_grads(const AccT *m, float o, float A, float B, float C,
+                                                 float (&g)[5]) {
+    const AccT w = (AccT)o;
+    g[0] = (float)(w * ((AccT)A * m[0] + (AccT)B * m[1]));
+    g[1] = (float)(w * ((AccT)B * m[0] + (AccT)C * m[1]));
+    g[2] = (float)((AccT)-0.5 * w * m[2]);
+    g[3] = (float)(-w * m[3]);
+    g[4] = (float)((AccT)-0.5 * w * m[4]);
 }
 
 // Everything of one Gaussian except the SH gradient, which the caller writes
@@ -290,8 +293,10 @@ __device__ __forceinline__ void preprocess_bwd_one(int i, const float *__restric
     project_splat(cam, mx, my, mz, tz, log_scales + 3 * i, quats + 4 * i, p);
     float g5[5];
     {
-        const float idet = 1.0f / p.det; // the conic as the forward computed it
-        moments_to_grads(g, p.c * idet, -p.b * idet, p.a * idet, g5);
+        // the opacity and the conic as the forward computed them
+        const float o = 1.0f / (1.0f + expf(-opacity_logits[i]));
+        const float idet = 1.0f / p.det;
+        moments_to_grads(g, o, p.c * idet, -p.b * idet, p.a * idet, g5);
     }
     const float gu = g5[0], gv = g5[1], gA = g5[2], gB = g5[3], gC = g5[4], go = (float)g[5];
     const float grgb[3] = {(float)g[6], (float)g[7], (float)g[8]};
@@ -481,8 +486,8 @@ __global__ __launch_bounds__(256) void zero_visible_rows_kernel(const int32_t *r
 }
 
 // Row i of dst: (dL/du, dL/dv, dL/dA, dL/dB, dL/dC, dL/do, dL/drgb) from the
-// accumulated moments and the conic in the record, as fp32; zeros for rows
-// never written (radius <= 0).
+// accumulated moments and the opacity and conic in the record, as fp32; zeros
+// for rows never written (radius <= 0).
 template <typename AccT>
 __global__ __launch_bounds__(256) void export_acc_kernel(const int32_t *radius, const float4 *rec, int64_t n,
                                                           const AccT *acc, float *dst) {
@@ -494,9 +499,9 @@ __global__ __launch_bounds__(256) void export_acc_kernel(const int32_t *radius, 
     for (int k = 0; k < GSR_ACC_STRIDE; ++k) row[k] = 0.0f;
     if (radius[i] > 0) {
         const AccT *m = acc + i * GSR_ACC_STRIDE;
-        const float4 r0 = rec[3 * i];
+        const float4 r0 = rec[3 * i], r1 = rec[3 * i + 1];
         float g5[5];
-        moments_to_grads(m, r0.z, r0.w, rec[3 * i + 1].x, g5);
+        moments_to_grads(m, r1.y, r0.z, r0.w, r1.x, g5);
 #pragma unroll
         for (int k = 0; k < 5; ++k) row[k] = g5[k];
 #pragma unroll
