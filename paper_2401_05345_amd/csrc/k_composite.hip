@@ -347,14 +347,14 @@ __global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(ViewBatch vb,
             const bool active = walked && e.pass;
             // the ballot as the AND of the three compares' own lane masks
             const uint64_t am = __ballot(walked) & __ballot(!(e.lp > 0.0f)) & __ballot(e.alpha >= kAlphaMin);
-            // Lanes that skip this entry run the same arithmetic with alpha, G and o G set to
-            // zero: their nine values come out as zeros and T, S stay as they are.
+            // Lanes that skip this entry run the same arithmetic with alpha and G set to zero:
+            // their nine values come out as zeros and T, S stay as they are (the hardware
+            // reciprocal of 1 is exactly 1).
             const float al = active ? e.alpha : 0.0f;
             const float gz = active ? e.G : 0.0f;
             // Transmittance in front of this entry; hardware reciprocal (1 ulp) instead of the
             // IEEE division sequence.
-            const float Tin = T * __builtin_amdgcn_rcpf(1.0f - al);
-            T = active ? Tin : T;
+            T = T * __builtin_amdgcn_rcpf(1.0f - al);
             float v[9];
             const float w = al * T;
             v[6] = w * G0;
