@@ -66,7 +66,7 @@ def parse():
     p.add_argument("--profile-only", action="store_true", help="only the timed steps (for rocprofv3 runs)")
     p.add_argument("--mode", default="reduce", choices=list(MODES), help="backward mode of --profile-only")
     p.add_argument("--no-lane-split", action="store_true",
-                   help="reduced sums issued by one lane (default: lanes 0..8, one instruction)")
+                   help="reduced sums issued by one lane (default: nine lanes, one instruction)")
     p.add_argument("--no-batch", action="store_true", help="skip the 16-view batched leg")
     p.add_argument("--no-serve", action="store_true", help="skip the served request stream")
     p.add_argument("--serve-seconds", type=float, default=1.5, help="seconds of arrivals per rate")

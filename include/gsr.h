@@ -1,6 +1,6 @@
 /*
  * gsr.h - 3D Gaussian Splatting render and backward pass for AMD MI355X
- * (gfx950), with a per-wavefront choice between a register butterfly
+ * (gfx950), with a per-wavefront choice between a register (cross-lane)
  * reduction plus one lane's atomics and plain per-lane global atomics.
  *
  * The calls follow the problem the paper (DISTWAR, arXiv 2401.05345) states
@@ -46,10 +46,10 @@ typedef enum {
 
 typedef enum {
     GSR_BWD_PLAIN_ATOMIC = 0, /* every active lane issues its own 9 atomic adds */
-    GSR_BWD_WAVE_REDUCE = 1,  /* butterfly + one lane's atomics when active lanes >= threshold */
+    GSR_BWD_WAVE_REDUCE = 1,  /* wave reduction + one lane's atomics when active lanes >= threshold */
     GSR_BWD_SERIAL_REDUCE = 2, /* ablation: the sums built one active lane at a time (readlane loop, the
                                   paper's serialised SW-S form) when active lanes >= threshold; lanes 0..8 issue */
-    GSR_BWD_BLOCK_REDUCE = 3  /* extension: waves at or above the threshold reduce by butterfly into LDS; the
+    GSR_BWD_BLOCK_REDUCE = 3  /* extension: waves at or above the threshold reduce into LDS; the
                                  block issues one atomic per (tile, Gaussian, value) after each LDS batch */
 } gsr_bwd_mode;
 
@@ -164,7 +164,7 @@ typedef struct {
  *  evaluated     E: (pixel, entry) pairs walked with entry <= n_contrib
  *  active        A: pairs that contributed (the paper's participating threads)
  *  wave_entries  (wave, entry) steps with at least one active lane
- *  reduced       W_R: wave-entries that took the butterfly path
+ *  reduced       W_R: wave-entries that took the reduction path
  *  plain_lanes   A_<: active lanes of wave-entries that issued per-lane atomics
  *  lane_atomics  atomic lane-operations issued (each lane of each atomic instruction)
  *  atomic_instrs atomic instructions issued

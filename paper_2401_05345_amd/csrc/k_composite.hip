@@ -14,7 +14,7 @@
 //      transformation of Detailed Design, "Butterfly Reduction"). The update
 //      is either nine plain atomic adds per active lane, or - when the
 //      wave's active-lane count reaches the balancing threshold (Approach,
-//      "Scheduling Atomic Updates Between Core and L2") - a DPP butterfly
+//      "Scheduling Atomic Updates Between Core and L2") - a cross-lane reduction
 //      over the 64 lanes and one lane's (or nine lanes') atomics.
 #include "device_common.hpp"
 

@@ -146,7 +146,7 @@ def test_wave_reduce_primitive_sums_and_atomic_counts(renderer, split):
             torch.cuda.synchronize()
             got = sums.cpu().numpy().astype(np.float64)
             assert np.abs(got - want).max() <= 1e-5 * scale, (mode, thr)
-            # A reduced wave issues nine lane-operations either way: lane 63 nine times, or lanes 0..8 once.
+            # A reduced wave issues nine lane-operations either way: lane 63 nine times, or nine lanes once.
             assert int(cnt.item()) == _model_atomics(active, mode, thr, split), (mode, thr)
 
 
