@@ -298,7 +298,7 @@ void gsr_graph_destroy(gsr_ctx *ctx, gsr_graph *graph);
 typedef struct {
     int32_t n_tiles, tiles[3];           /* subset of {8, 16, 32} */
     int32_t n_batches, batches[3];       /* subset of {64, 128, 256} */
-    int32_t n_thresholds, thresholds[8]; /* 1..65 */
+    int32_t n_thresholds, thresholds[12]; /* 1..65 */
     int32_t reps;                        /* >= 1 */
     int32_t flags;
 } gsr_tune_space;

@@ -1227,7 +1227,7 @@ namespace {
 gsr_status check_space(gsr_ctx *ctx, const gsr_tune_space *sp) {
     if (!sp) return fail(ctx, GSR_EINVAL, "tune space is null");
     if (sp->n_tiles < 1 || sp->n_tiles > 3 || sp->n_batches < 1 || sp->n_batches > 3 || sp->n_thresholds < 1 ||
-        sp->n_thresholds > 8 || sp->reps < 1 || sp->reps > 100)
+        sp->n_thresholds > 12 || sp->reps < 1 || sp->reps > 100)
         return fail(ctx, GSR_EINVAL, "tune space sizes out of range");
     for (int i = 0; i < sp->n_tiles; ++i)
         if (sp->tiles[i] != 8 && sp->tiles[i] != 16 && sp->tiles[i] != 32)

@@ -80,7 +80,7 @@ class gsr_stage_times_t(ctypes.Structure):
 
 class gsr_tune_space(ctypes.Structure):
     _fields_ = [("n_tiles", c_int32), ("tiles", c_int32 * 3), ("n_batches", c_int32), ("batches", c_int32 * 3),
-                ("n_thresholds", c_int32), ("thresholds", c_int32 * 8), ("reps", c_int32), ("flags", c_int32)]
+                ("n_thresholds", c_int32), ("thresholds", c_int32 * 12), ("reps", c_int32), ("flags", c_int32)]
 
 
 class gsr_tune_entry(ctypes.Structure):
@@ -350,8 +350,10 @@ def gsr_graph_destroy(ctx, graph):
     load().gsr_graph_destroy(ctx, graph)
 
 
-def make_tune_space(tiles=(8, 16, 32), batches=(64, 128, 256), thresholds=(8, 16, 24, 32, 48, 64), reps=3,
+def make_tune_space(tiles=(8, 16, 32), batches=(64, 128, 256), thresholds=(1, 2, 4, 8, 16, 24, 32, 48, 64), reps=3,
                     flags=0) -> gsr_tune_space:
+    """Candidate space of the autotuner. The default thresholds are the paper's 8..64 range plus
+    1, 2 and 4, where the optimum lies on MI355X (each plain lane-atomic is a fabric request)."""
     sp = gsr_tune_space()
     sp.n_tiles, sp.n_batches, sp.n_thresholds = len(tiles), len(batches), len(thresholds)
     for i, v in enumerate(tiles):

@@ -294,10 +294,10 @@ def test_autotune_picks_fastest_measured(renderer, small):
     gss = _gpu_views(scenes, views)
     space = gsr.make_tune_space(reps=2, flags=SPLIT)
     best, entries = gsr.gsr_autotune(renderer.ctx, [g.scene for g in gss], [g.cam for g in gss], space)
-    # (8,64), (16,64/128/256), (32,64/128/256) times six thresholds
-    assert len(entries) == 7 * 6
+    # (8,64), (16,64/128/256), (32,64/128/256) times nine thresholds
+    assert len(entries) == 7 * 9
     seen = {(e.config.tile, e.config.lds_batch, e.config.reduce_threshold) for e in entries}
-    assert len(seen) == 42
+    assert len(seen) == 63
     tot = [e.render_ms + e.backward_ms for e in entries]
     k = int(np.argmin(tot))
     assert (best.tile, best.lds_batch, best.reduce_threshold) == \
