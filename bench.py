@@ -182,20 +182,20 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel_hash, workload):
-    """HBM bytes per launch of the backward composite from committed rocprofv3 counter runs
-    (FETCH_SIZE and WRITE_SIZE scaled by the copy calibration), or None when the kernel changed
-    since they were taken."""
+def measured_counters(kernel_hash, workload):
+    """Per-launch figures of the backward composite from committed rocprofv3 counter runs: HBM
+    bytes (FETCH_SIZE and WRITE_SIZE scaled by the copy calibration) and the VALU issue fraction
+    (SQ_INSTS_VALU x 4 cycles over the SIMD cycles of the traced launch); {} when the kernel
+    changed since they were taken."""
     path = os.path.join(ROOT, "profiles", "composite_bwd_traffic.json")
     if not os.path.exists(path):
-        return None
+        return {}
     with open(path) as f:
         d = json.load(f)
     if d.get("kernel_source_hash") != kernel_hash:
-        return None
+        return {}
     key = "object" if workload.startswith("object") else "large"
-    w = d.get("workloads", {}).get(key)
-    return w.get("bytes_per_launch") if w else None
+    return d.get("workloads", {}).get(key) or {}
 
 
 def timed_ms(torch, fn, reps):
@@ -476,13 +476,16 @@ def main():
     hw = wl.camera.width * wl.camera.height
     alg_bytes = BYTES_PER_PIXEL * hw + BYTES_PER_VISIBLE * n_vis + BYTES_PER_RECORD * int(stats.n_pairs)
     khash = source_hash()
-    traffic = measured_traffic(khash, wl.name)
+    measured = measured_counters(khash, wl.name)
+    traffic = measured.get("bytes_per_launch")
     roofline = {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": PEAK_FP32_VALU_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_FP32_VALU_TFLOPS, 4),
                 "traffic": traffic, "kernel": "composite_bwd_kernel<16,256,wave_reduce>",
                 "algorithmic_flops": int(flops), "hbm_GBs_algorithmic": round(alg_bytes / (a6_ms * 1e-3) / 1e9, 1),
                 "hbm_frac_algorithmic": round(alg_bytes / (a6_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
                 "kernel_source_hash": khash}
+    if "valu_issue_frac" in measured:
+        roofline["valu_issue_frac"] = measured["valu_issue_frac"]
 
     out = {
         "metric": "3DGS backward ms/iter + TCC atomics, wave-reduce vs plain atomics; p99 step lat",
