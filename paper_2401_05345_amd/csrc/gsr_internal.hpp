@@ -65,8 +65,10 @@ hipError_t launch_preprocess_fwd(const gsr_scene &s, const DevCamera &cam, float
 hipError_t launch_preprocess_bwd(const gsr_scene &s, const DevCamera &cam, const int32_t *radius, const void *acc,
                                  bool acc_f64, const gsr_grads &out, int accumulate, hipStream_t st);
 
-// Zero the accumulator rows of Gaussians with radius > 0 (the only rows the composite writes).
-hipError_t launch_zero_visible_rows(const int32_t *radius, int64_t n, void *acc, bool acc_f64, hipStream_t st);
+// Zero the accumulator rows of Gaussians with radius > 0 (the only rows the composite writes):
+// those listed in visible_ids[0, n_visible) when the list is given, else found from radius.
+hipError_t launch_zero_visible_rows(const int32_t *radius, int64_t n, const uint32_t *visible_ids, int64_t n_visible,
+                                    void *acc, bool acc_f64, hipStream_t st);
 // Accumulator rows as fp32 gradients [n][GSR_ACC_STRIDE] (dL/du, dL/dv, dL/dA, dL/dB, dL/dC,
 // dL/do, dL/drgb: the moments converted with the record's opacity and conic), culled rows as
 // zeros.
@@ -107,7 +109,10 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream
 hipError_t launch_count_positive(const int32_t *r, int64_t n, uint32_t *out, hipStream_t st);
 
 // flags[i] = (r[i] > 0); and the compaction of the flagged (key[i], i) to positions pos[i].
-hipError_t launch_positive_flags(const int32_t *r, int64_t n, uint32_t *flags, hipStream_t st);
+// With range != nullptr also range[0] = max of ~key, range[1] = max of key over the flagged entries
+// (0 when none).
+hipError_t launch_positive_flags(const int32_t *r, int64_t n, uint32_t *flags, const uint32_t *key, uint32_t *range,
+                                 hipStream_t st);
 hipError_t launch_compact_keys(const uint32_t *flags, const uint32_t *pos, int64_t n, const uint32_t *key,
                                uint32_t *key_out, uint32_t *id_out, hipStream_t st);
 
@@ -208,7 +213,7 @@ struct gsr_fwd {
     bool overflowed = false;            // the last capacity-mode render dropped pairs
     bool capacity_mode = false;         // re-rendered in capacity mode (counts live on the device)
     // Scratch kept for re-renders without reallocation (capacity mode, graph capture).
-    uint32_t *totals = nullptr;         // [0] P, [1] n_visible, [2] overflow flag
+    uint32_t *totals = nullptr;         // [0] P, [1] n_visible, [2] overflow flag, [4..5] depth-key range
     uint32_t *dsort_hist = nullptr, *dsort_partials = nullptr, *scan_partials = nullptr;
     uint32_t *tsort_hist = nullptr, *tsort_partials = nullptr;
     uint32_t *vis_flags = nullptr;      // radius > 0, for the compaction before the depth sort

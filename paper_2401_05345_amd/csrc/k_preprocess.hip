@@ -90,6 +90,28 @@ __device__ __forceinline__ void project_splat(const DevCamera &cam, float mx, fl
 // operations are written in this scope with contraction off: helper
 // intrinsics would be inlined as plain products and sums, which the default
 // contraction mode may fuse into FMAs.
+// A Gaussian's NS colour coefficients: 16-byte loads when the row is a whole number of them and
+// the array is 16-byte aligned (a wave's scalar loads of 192-byte rows would each touch 64
+// separate lines), else scalar loads.
+template <int NS>
+__device__ __forceinline__ void load_coeffs(const float *__restrict__ sh, int64_t i, float (&f)[NS]) {
+    const float *p = sh + i * NS;
+    if (NS % 4 == 0 && (reinterpret_cast<uintptr_t>(sh) & 15) == 0) {
+        const float4 *q = reinterpret_cast<const float4 *>(p);
+#pragma unroll
+        for (int c = 0; c < NS / 4; ++c) {
+            const float4 x = q[c];
+            f[4 * c] = x.x;
+            f[4 * c + 1] = x.y;
+            f[4 * c + 2] = x.z;
+            f[4 * c + 3] = x.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < NS; ++k) f[k] = p[k];
+    }
+}
+
 __device__ __forceinline__ float depth_of(const DevCamera &cam, float mx, float my, float mz) {
 #pragma clang fp contract(off)
     const float a = cam.R[6] * mx;
@@ -156,7 +178,8 @@ __global__ __launch_bounds__(256) void preprocess_fwd_kernel(int n, const float 
     dx *= il; dy *= il; dz *= il;
     float Y[K];
     sh_basis<DEG>(dx, dy, dz, Y);
-    const float *f = sh + (int64_t)i * K * 3;
+    float f[3 * K];
+    load_coeffs<3 * K>(sh, i, f);
     float rgb[3] = {0.5f, 0.5f, 0.5f};
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -307,7 +330,8 @@ __device__ __forceinline__ void preprocess_bwd_one(int i, const float *__restric
     const float dxn = ex * il, dyn = ey * il, dzn = ez * il;
     float Y[K];
     sh_basis<DEG>(dxn, dyn, dzn, Y);
-    const float *f = sh + (int64_t)i * K * 3;
+    float f[3 * K];
+    load_coeffs<3 * K>(sh, i, f);
     float raw[3] = {0.5f, 0.5f, 0.5f};
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -476,13 +500,23 @@ hipError_t launch_preprocess_bwd(const gsr_scene &s, const DevCamera &cam, const
 namespace {
 // Rows of the Gaussians that can appear in a tile list (radius > 0) are the only ones the
 // backward composite adds into and a7 reads: only they are cleared.
-// One thread per 16-byte chunk, so a wave's stores cover consecutive rows' chunks.
 __global__ __launch_bounds__(256) void zero_visible_rows_kernel(const int32_t *radius, int64_t n, uint4 *acc,
                                                                  int chunks_per_row) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t i = t / chunks_per_row;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n || radius[i] <= 0) return;
-    acc[t] = make_uint4(0u, 0u, 0u, 0u);
+    uint4 *row = acc + i * chunks_per_row;
+    for (int c = 0; c < chunks_per_row; ++c) row[c] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// The same for a list of the visible Gaussians (the depth-sorted ids of a render): one thread per
+// 16-byte chunk of a listed row, so consecutive threads fill whole 128-byte lines, and no thread
+// is spent on culled Gaussians.
+__global__ __launch_bounds__(256) void zero_listed_rows_kernel(const uint32_t *ids, int64_t m, uint4 *acc,
+                                                                int chunks_per_row) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t v = t / chunks_per_row;
+    if (v >= m) return;
+    acc[(int64_t)ids[v] * chunks_per_row + (t - v * chunks_per_row)] = make_uint4(0u, 0u, 0u, 0u);
 }
 
 // Row i of dst: (dL/du, dL/dv, dL/dA, dL/dB, dL/dC, dL/do, dL/drgb) from the
@@ -512,12 +546,18 @@ __global__ __launch_bounds__(256) void export_acc_kernel(const int32_t *radius, 
 }
 } // namespace
 
-hipError_t launch_zero_visible_rows(const int32_t *radius, int64_t n, void *acc, bool acc_f64, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
+hipError_t launch_zero_visible_rows(const int32_t *radius, int64_t n, const uint32_t *visible_ids, int64_t n_visible,
+                                    void *acc, bool acc_f64, hipStream_t st) {
     const int chunks = GSR_ACC_STRIDE * (acc_f64 ? 8 : 4) / 16;
-    const int64_t threads = n * chunks;
-    zero_visible_rows_kernel<<<(unsigned)((threads + 255) / 256), 256, 0, st>>>(radius, n, static_cast<uint4 *>(acc),
-                                                                                chunks);
+    if (visible_ids) {
+        if (n_visible <= 0) return hipSuccess;
+        const int64_t threads = n_visible * chunks;
+        zero_listed_rows_kernel<<<(unsigned)((threads + 255) / 256), 256, 0, st>>>(
+            visible_ids, n_visible, static_cast<uint4 *>(acc), chunks);
+        return hipGetLastError();
+    }
+    if (n <= 0) return hipSuccess;
+    zero_visible_rows_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(radius, n, static_cast<uint4 *>(acc), chunks);
     return hipGetLastError();
 }
 

@@ -522,10 +522,42 @@ __global__ __launch_bounds__(256) void count_positive_kernel(const int32_t *r, i
 
 } // namespace
 
-// flags[i] = (r[i] > 0)
-__global__ __launch_bounds__(256) void positive_flags_kernel(const int32_t *r, int64_t n, uint32_t *flags) {
+// flags[i] = (r[i] > 0); with range != nullptr also the largest ~key and the largest key over the
+// flagged entries (atomic maxima into range[0], range[1], one pair per block), so that the smallest
+// key is ~range[0].
+__global__ __launch_bounds__(256) void positive_flags_kernel(const int32_t *r, int64_t n, uint32_t *flags,
+                                                             const uint32_t *key, uint32_t *range) {
+    __shared__ uint32_t s_lo[4], s_hi[4];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) flags[i] = r[i] > 0 ? 1u : 0u;
+    uint32_t lo = 0, hi = 0;
+    if (i < n) {
+        const bool vis = r[i] > 0;
+        flags[i] = vis ? 1u : 0u;
+        if (range && vis) {
+            const uint32_t k = key[i];
+            lo = ~k;
+            hi = k;
+        }
+    }
+    if (!range) return;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        lo = max(lo, (uint32_t)__shfl_xor((int)lo, d, 64));
+        hi = max(hi, (uint32_t)__shfl_xor((int)hi, d, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        s_lo[threadIdx.x >> 6] = lo;
+        s_hi[threadIdx.x >> 6] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        lo = max(max(s_lo[0], s_lo[1]), max(s_lo[2], s_lo[3]));
+        hi = max(max(s_hi[0], s_hi[1]), max(s_hi[2], s_hi[3]));
+        if (lo | hi) {
+            atomicMax(&range[0], lo);
+            atomicMax(&range[1], hi);
+        }
+    }
 }
 
 // Entry i with flags[i] set goes to position pos[i]: (key[i], i).
@@ -538,9 +570,14 @@ __global__ __launch_bounds__(256) void compact_keys_kernel(const uint32_t *flags
     }
 }
 
-hipError_t launch_positive_flags(const int32_t *r, int64_t n, uint32_t *flags, hipStream_t st) {
+hipError_t launch_positive_flags(const int32_t *r, int64_t n, uint32_t *flags, const uint32_t *key, uint32_t *range,
+                                 hipStream_t st) {
+    if (range) {
+        const hipError_t e = launch_fill_u32(range, 0u, 2, st);
+        if (e != hipSuccess) return e;
+    }
     if (n <= 0) return hipSuccess;
-    positive_flags_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(r, n, flags);
+    positive_flags_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(r, n, flags, key, range);
     return hipGetLastError();
 }
 

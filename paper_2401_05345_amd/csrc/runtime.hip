@@ -211,7 +211,7 @@ gsr_status gsr_ctx_create(gsr_ctx **out, int device, void *hip_stream) {
     ctx->stream = static_cast<hipStream_t>(hip_stream);
     ctx->pool = new (std::nothrow) Pool(device);
     void *hp = nullptr;
-    if (!ctx->pool || hipHostMalloc(&hp, 256, hipHostMallocDefault) != hipSuccess) {
+    if (!ctx->pool || hipHostMalloc(&hp, 1024, hipHostMallocDefault) != hipSuccess) {
         gsr_ctx_destroy(ctx);
         return GSR_ENOMEM;
     }
@@ -314,7 +314,7 @@ gsr_status alloc_view(gsr_ctx *ctx, gsr_fwd *st) {
     GSR_TRY(pool_alloc(ctx, st, &st->ranges, st->n_tiles));
     GSR_TRY(pool_alloc(ctx, st, &st->T_final, hw));
     GSR_TRY(pool_alloc(ctx, st, &st->n_contrib, hw));
-    GSR_TRY(pool_alloc(ctx, st, &st->totals, 4));
+    GSR_TRY(pool_alloc(ctx, st, &st->totals, 8));
     if (n > 1) {
         const size_t hc = radix_hist_count(n);
         GSR_TRY(pool_alloc(ctx, st, &st->dsort_hist, hc));
@@ -453,24 +453,29 @@ gsr_status render_views(gsr_ctx *ctx, int nv, const gsr_scene *scenes, const gsr
     // P = sum of tile counts taken; the counts of all views are read back at once.
     for (int v = 0; v < nv; ++v) {
         gsr_fwd *st = sts[v];
-        GSR_RH(launch_positive_flags(st->radius, st->n, st->vis_flags, s));
+        GSR_RH(launch_positive_flags(st->radius, st->n, st->vis_flags, st->depth_key, st->totals + 4, s));
         GSR_RH(device_exclusive_scan(st->vis_flags, nullptr, st->offsets, st->n, st->totals + 1, st->scan_partials, s));
         GSR_RH(launch_compact_keys(st->vis_flags, st->offsets, st->n, st->depth_key, st->key_alt, st->ids_alt, s));
         GSR_RH(device_exclusive_scan(st->tiles_touched, nullptr, st->offsets, st->n, st->totals, st->scan_partials,
                                      s));
-        GSR_RH(hipMemcpyAsync(ctx->host_pinned + 2 * v, st->totals, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        GSR_RH(hipMemcpyAsync(ctx->host_pinned + 6 * v, st->totals, 6 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     }
     GSR_RH(hipStreamSynchronize(s));
     for (int v = 0; v < nv; ++v) {
         gsr_fwd *st = sts[v];
-        st->P = st->n > 0 ? (int64_t)ctx->host_pinned[2 * v] : 0;
-        st->n_visible = st->n > 0 ? (int64_t)ctx->host_pinned[2 * v + 1] : 0;
+        const uint32_t *h = ctx->host_pinned + 6 * v;
+        st->P = st->n > 0 ? (int64_t)h[0] : 0;
+        st->n_visible = st->n > 0 ? (int64_t)h[1] : 0;
         st->p_known = true;
         // a2/a3 (depth digits): stable sort of the visible Gaussians by fp32 depth (ties keep
-        // index order).
+        // index order). Bits above the highest one in which the smallest and the largest key
+        // differ are the same in every key: only the bits below it are sorted (for an object
+        // seen from outside, the exponent byte of every depth is the same: three passes).
+        const uint32_t kmin = ~h[4], kmax = h[5];
+        const int bits = kmin < kmax ? 32 - __builtin_clz(kmin ^ kmax) : 0;
         int which = 0;
-        if (st->n_visible > 1)
-            GSR_RH(radix_sort_pairs(st->key_alt, st->ids_alt, st->depth_key, st->ids, st->n_visible, 32,
+        if (st->n_visible > 1 && bits > 0)
+            GSR_RH(radix_sort_pairs(st->key_alt, st->ids_alt, st->depth_key, st->ids, st->n_visible, bits,
                                     st->dsort_hist, st->dsort_partials, &which, s));
         st->sorted_ids_by_depth = which ? st->ids : st->ids_alt;
     }
@@ -610,7 +615,11 @@ gsr_status bwd_enqueue(gsr_ctx *ctx, int nv, gsr_fwd *const *sts, const gsr_conf
     for (int v = 0; v < nv; ++v) sts[v]->counters_valid = false;
     mark(ctx, tm, EV_B0);
     for (int v = 0; v < nv; ++v) {
-        GSR_HIP(ctx, launch_zero_visible_rows(sts[v]->radius, sts[v]->n, sts[v]->acc, f64, s));
+        // After a render that read its counts back, the depth-sorted ids are exactly the visible
+        // Gaussians; a capacity-mode re-render leaves the count on the device.
+        const gsr_fwd *sv = sts[v];
+        GSR_HIP(ctx, launch_zero_visible_rows(sv->radius, sv->n, sv->p_known ? sv->sorted_ids_by_depth : nullptr,
+                                              sv->n_visible, sv->acc, f64, s));
         sts[v]->acc_f64 = f64;
     }
     if (count) GSR_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t *>(sts[0]->counters), 0u, 160, s));
