@@ -109,12 +109,14 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream
 hipError_t launch_count_positive(const int32_t *r, int64_t n, uint32_t *out, hipStream_t st);
 
 // flags[i] = (r[i] > 0); and the compaction of the flagged (key[i], i) to positions pos[i].
-// With range != nullptr also range[0] = max of ~key, range[1] = max of key over the flagged entries
-// (0 when none).
-hipError_t launch_positive_flags(const int32_t *r, int64_t n, uint32_t *flags, const uint32_t *key, uint32_t *range,
-                                 hipStream_t st);
-hipError_t launch_compact_keys(const uint32_t *flags, const uint32_t *pos, int64_t n, const uint32_t *key,
-                               uint32_t *key_out, uint32_t *id_out, hipStream_t st);
+// Visible Gaussians (r > 0) in index order: key_out/id_out[0, n_visible) = (key[i], i);
+// totals[0] = sum of tiles[i] over them (the pair count P), totals[1] = n_visible, totals[4] =
+// max of ~key and totals[5] = max of key over them (0, 0 when none). part: visible_partial_count(n)
+// entries of scratch.
+size_t visible_partial_count(int64_t n);
+hipError_t launch_compact_visible(const int32_t *r, int64_t n, const uint32_t *key, const uint32_t *tiles,
+                                  uint4 *part, uint32_t *totals, uint32_t *key_out, uint32_t *id_out,
+                                  hipStream_t st);
 
 // One view of a composite launch. A launch covers up to kMaxViews views (same
 // tile size and LDS batch): the views travel by value in the kernel
@@ -216,7 +218,7 @@ struct gsr_fwd {
     uint32_t *totals = nullptr;         // [0] P, [1] n_visible, [2] overflow flag, [4..5] depth-key range
     uint32_t *dsort_hist = nullptr, *dsort_partials = nullptr, *scan_partials = nullptr;
     uint32_t *tsort_hist = nullptr, *tsort_partials = nullptr;
-    uint32_t *vis_flags = nullptr;      // radius > 0, for the compaction before the depth sort
+    uint4 *vis_part = nullptr;          // per-block statistics of the visible-Gaussian compaction
     uint2 *ranges = nullptr;
     uint32_t *tile_walk = nullptr; // deepest n_contrib per tile (ordered renders)
     uint2 *order_bwd = nullptr;    // this view's tiles by decreasing walk (single-view backward)

@@ -520,71 +520,181 @@ __global__ __launch_bounds__(256) void count_positive_kernel(const int32_t *r, i
     if (threadIdx.x == 0 && total) atomicAdd(out, total);
 }
 
-} // namespace
+// Compaction of the visible Gaussians (radius > 0) in index order, in three launches over blocks
+// of 1024 Gaussians (four per thread, at stride 256): per-block statistics, one block that scans
+// the blocks' counts and reduces the rest, and the scatter. Per-block partials rather than
+// atomics into one word: same-address atomics from thousands of blocks serialise at one L2
+// channel.
+constexpr int kVisItems = 4;
+constexpr int kVisBlock = 256 * kVisItems;
 
-// flags[i] = (r[i] > 0); with range != nullptr also the largest ~key and the largest key over the
-// flagged entries (atomic maxima into range[0], range[1], one pair per block), so that the smallest
-// key is ~range[0].
-__global__ __launch_bounds__(256) void positive_flags_kernel(const int32_t *r, int64_t n, uint32_t *flags,
-                                                             const uint32_t *key, uint32_t *range) {
-    __shared__ uint32_t s_lo[4], s_hi[4];
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t lo = 0, hi = 0;
-    if (i < n) {
-        const bool vis = r[i] > 0;
-        flags[i] = vis ? 1u : 0u;
-        if (range && vis) {
-            const uint32_t k = key[i];
-            lo = ~k;
-            hi = k;
-        }
+// part[b] = (visible count, max ~key, max key, sum of tile counts) over block b's visible entries.
+__global__ __launch_bounds__(256) void visible_stats_kernel(const int32_t *r, int64_t n, const uint32_t *key,
+                                                            const uint32_t *tiles, uint4 *part) {
+    __shared__ uint4 s_w[4];
+    const int64_t base = (int64_t)blockIdx.x * kVisBlock + threadIdx.x;
+    // loads from clamped positions, all issued before any is used (no bounds test around a load)
+    int32_t rv[kVisItems];
+    uint32_t kv[kVisItems], tv[kVisItems];
+#pragma unroll
+    for (int j = 0; j < kVisItems; ++j) {
+        const int64_t i = base + 256 * j < n ? base + 256 * j : n - 1;
+        rv[j] = r[i];
+        kv[j] = key[i];
+        tv[j] = tiles[i];
     }
-    if (!range) return;
+    uint32_t c = 0, lo = 0, hi = 0, t = 0;
+#pragma unroll
+    for (int j = 0; j < kVisItems; ++j)
+        if (base + 256 * j < n && rv[j] > 0) {
+            c += 1;
+            lo = max(lo, ~kv[j]);
+            hi = max(hi, kv[j]);
+            t += tv[j];
+        }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
+        c += (uint32_t)__shfl_xor((int)c, d, 64);
+        t += (uint32_t)__shfl_xor((int)t, d, 64);
         lo = max(lo, (uint32_t)__shfl_xor((int)lo, d, 64));
         hi = max(hi, (uint32_t)__shfl_xor((int)hi, d, 64));
     }
-    if ((threadIdx.x & 63) == 0) {
-        s_lo[threadIdx.x >> 6] = lo;
-        s_hi[threadIdx.x >> 6] = hi;
-    }
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = make_uint4(c, lo, hi, t);
     __syncthreads();
     if (threadIdx.x == 0) {
-        lo = max(max(s_lo[0], s_lo[1]), max(s_lo[2], s_lo[3]));
-        hi = max(max(s_hi[0], s_hi[1]), max(s_hi[2], s_hi[3]));
-        if (lo | hi) {
-            atomicMax(&range[0], lo);
-            atomicMax(&range[1], hi);
+        uint4 a = s_w[0];
+#pragma unroll
+        for (int w = 1; w < 4; ++w) {
+            const uint4 b = s_w[w];
+            a = make_uint4(a.x + b.x, max(a.y, b.y), max(a.z, b.z), a.w + b.w);
         }
+        part[blockIdx.x] = a;
     }
 }
 
-// Entry i with flags[i] set goes to position pos[i]: (key[i], i).
-__global__ __launch_bounds__(256) void compact_keys_kernel(const uint32_t *flags, const uint32_t *pos, int64_t n,
-                                                            const uint32_t *key, uint32_t *key_out, uint32_t *id_out) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n && flags[i]) {
-        key_out[pos[i]] = key[i];
-        id_out[pos[i]] = (uint32_t)i;
+// One block of 1024 threads: part[b].x becomes the exclusive prefix of the blocks' visible counts;
+// totals[0] = sum of tile counts (P), totals[1] = visible count, totals[4] = max ~key,
+// totals[5] = max key. Thread t takes four consecutive blocks of each 4096-block chunk.
+constexpr int kTotThreads = 1024;
+__global__ __launch_bounds__(kTotThreads) void visible_totals_kernel(uint4 *part, int64_t nb, uint32_t *totals) {
+    __shared__ uint32_t s_wave[kTotThreads / 64];
+    __shared__ uint4 s_red[kTotThreads / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t carry = 0, lo = 0, hi = 0, t = 0;
+    for (int64_t chunk = 0; chunk < nb; chunk += 4 * kTotThreads) {
+        const int64_t b0 = chunk + 4 * (int64_t)threadIdx.x;
+        uint4 v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = part[b0 + k < nb ? b0 + k : nb - 1];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (b0 + k < nb) {
+                sum += v[k].x;
+                lo = max(lo, v[k].y);
+                hi = max(hi, v[k].z);
+                t += v[k].w;
+            }
+        const uint32_t inc = wave_inclusive_scan(sum, lane);
+        if (lane == 63) s_wave[wave] = inc;
+        __syncthreads();
+        uint32_t off = 0, tot = 0;
+#pragma unroll
+        for (int w = 0; w < kTotThreads / 64; ++w) {
+            const uint32_t x = s_wave[w];
+            off += (w < wave) ? x : 0u;
+            tot += x;
+        }
+        __syncthreads();
+        uint32_t run = carry + off + inc - sum;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (b0 + k < nb) {
+                reinterpret_cast<uint32_t *>(part)[4 * (b0 + k)] = run;
+                run += v[k].x;
+            }
+        carry += tot;
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        t += (uint32_t)__shfl_xor((int)t, d, 64);
+        lo = max(lo, (uint32_t)__shfl_xor((int)lo, d, 64));
+        hi = max(hi, (uint32_t)__shfl_xor((int)hi, d, 64));
+    }
+    if (lane == 0) s_red[wave] = make_uint4(0u, lo, hi, t);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint4 a = s_red[0];
+        for (int w = 1; w < kTotThreads / 64; ++w) {
+            const uint4 b = s_red[w];
+            a = make_uint4(0u, max(a.y, b.y), max(a.z, b.z), a.w + b.w);
+        }
+        totals[0] = a.w;
+        totals[1] = carry;
+        totals[4] = a.y;
+        totals[5] = a.z;
     }
 }
 
-hipError_t launch_positive_flags(const int32_t *r, int64_t n, uint32_t *flags, const uint32_t *key, uint32_t *range,
-                                 hipStream_t st) {
-    if (range) {
-        const hipError_t e = launch_fill_u32(range, 0u, 2, st);
-        if (e != hipSuccess) return e;
+// Visible entry i of block b goes to part[b].x plus its rank among the block's visible entries
+// (index order: item j of every wave before item j + 1, waves in order, lanes in order).
+__global__ __launch_bounds__(256) void compact_visible_kernel(const int32_t *r, int64_t n, const uint32_t *key,
+                                                              const uint4 *part, uint32_t *key_out,
+                                                              uint32_t *id_out) {
+    __shared__ uint32_t s_cnt[kVisItems][4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t base = (int64_t)blockIdx.x * kVisBlock + threadIdx.x;
+    const uint32_t boff = part[blockIdx.x].x;
+    int32_t rv[kVisItems];
+    uint32_t kv[kVisItems];
+#pragma unroll
+    for (int j = 0; j < kVisItems; ++j) {
+        const int64_t i = base + 256 * j < n ? base + 256 * j : n - 1;
+        rv[j] = r[i];
+        kv[j] = key[i];
     }
-    if (n <= 0) return hipSuccess;
-    positive_flags_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(r, n, flags, key, range);
-    return hipGetLastError();
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    bool vis[kVisItems];
+    uint32_t rank[kVisItems];
+#pragma unroll
+    for (int j = 0; j < kVisItems; ++j) {
+        vis[j] = base + 256 * j < n && rv[j] > 0;
+        const uint64_t m = __ballot(vis[j]);
+        rank[j] = (uint32_t)__popcll(m & below);
+        if (lane == 0) s_cnt[j][wave] = (uint32_t)__popcll(m);
+    }
+    __syncthreads();
+    uint32_t before = boff;
+#pragma unroll
+    for (int j = 0; j < kVisItems; ++j) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w)
+            if (w < wave) before += s_cnt[j][w];
+        if (vis[j]) {
+            key_out[before + rank[j]] = kv[j];
+            id_out[before + rank[j]] = (uint32_t)(base + 256 * j);
+        }
+#pragma unroll
+        for (int w = 0; w < 4; ++w)
+            if (w >= wave) before += s_cnt[j][w];
+    }
 }
 
-hipError_t launch_compact_keys(const uint32_t *flags, const uint32_t *pos, int64_t n, const uint32_t *key,
-                               uint32_t *key_out, uint32_t *id_out, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    compact_keys_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(flags, pos, n, key, key_out, id_out);
+} // namespace
+
+size_t visible_partial_count(int64_t n) { return (size_t)((n + kVisBlock - 1) / kVisBlock) + 1; }
+
+hipError_t launch_compact_visible(const int32_t *r, int64_t n, const uint32_t *key, const uint32_t *tiles,
+                                  uint4 *part, uint32_t *totals, uint32_t *key_out, uint32_t *id_out,
+                                  hipStream_t st) {
+    if (n <= 0) {
+        hipError_t e = launch_fill_u32(totals, 0u, 2, st);
+        return e != hipSuccess ? e : launch_fill_u32(totals + 4, 0u, 2, st);
+    }
+    const int64_t nb = (n + kVisBlock - 1) / kVisBlock;
+    visible_stats_kernel<<<(unsigned)nb, 256, 0, st>>>(r, n, key, tiles, part);
+    visible_totals_kernel<<<1, kTotThreads, 0, st>>>(part, nb, totals);
+    compact_visible_kernel<<<(unsigned)nb, 256, 0, st>>>(r, n, key, part, key_out, id_out);
     return hipGetLastError();
 }
 

@@ -321,7 +321,7 @@ gsr_status alloc_view(gsr_ctx *ctx, gsr_fwd *st) {
         GSR_TRY(pool_alloc(ctx, st, &st->dsort_partials, scan_partial_count((int64_t)hc)));
     }
     GSR_TRY(pool_alloc(ctx, st, &st->scan_partials, scan_partial_count(nn) + 8));
-    GSR_TRY(pool_alloc(ctx, st, &st->vis_flags, nn));
+    GSR_TRY(pool_alloc(ctx, st, &st->vis_part, visible_partial_count(nn)));
     return GSR_OK;
 }
 
@@ -453,11 +453,8 @@ gsr_status render_views(gsr_ctx *ctx, int nv, const gsr_scene *scenes, const gsr
     // P = sum of tile counts taken; the counts of all views are read back at once.
     for (int v = 0; v < nv; ++v) {
         gsr_fwd *st = sts[v];
-        GSR_RH(launch_positive_flags(st->radius, st->n, st->vis_flags, st->depth_key, st->totals + 4, s));
-        GSR_RH(device_exclusive_scan(st->vis_flags, nullptr, st->offsets, st->n, st->totals + 1, st->scan_partials, s));
-        GSR_RH(launch_compact_keys(st->vis_flags, st->offsets, st->n, st->depth_key, st->key_alt, st->ids_alt, s));
-        GSR_RH(device_exclusive_scan(st->tiles_touched, nullptr, st->offsets, st->n, st->totals, st->scan_partials,
-                                     s));
+        GSR_RH(launch_compact_visible(st->radius, st->n, st->depth_key, st->tiles_touched, st->vis_part, st->totals,
+                                      st->key_alt, st->ids_alt, s));
         GSR_RH(hipMemcpyAsync(ctx->host_pinned + 6 * v, st->totals, 6 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     }
     GSR_RH(hipStreamSynchronize(s));
