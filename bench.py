@@ -533,6 +533,9 @@ def main():
             "lane_atomics_block_lds": int(ck.lane_atomics), "atomic_instrs_block_lds": int(ck.atomic_instrs),
         },
         "forward_ms": round(float(fwd.mean()), 4),
+        "forward_stages_ms": {k: round(float(np.mean([getattr(s, k) for s in per])), 4)
+                              for k in ("preprocess", "depth_sort", "scan_emit", "tile_sort", "ranges",
+                                        "composite_fwd")},
         "p99_step_ms": None,
     }
 

@@ -86,7 +86,23 @@ __device__ __forceinline__ void load_chunk(const uint32_t *in, const uint32_t *g
         }
         return;
     }
-    load_items<kItems, GATHER>(in, gather, n, [&](int k) { return base + k; }, v);
+    if (base >= n) {
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) v[k] = 0u;
+        return;
+    }
+    // clamped loads at 32-bit offsets from the chunk's start (64-bit positions would take two
+    // registers each)
+    const int last = n - base < kItems ? (int)(n - base) - 1 : kItems - 1;
+    const uint32_t *src = GATHER ? gather + base : in + base;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) v[k] = src[k < last ? k : last];
+    if (GATHER) {
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) v[k] = in[v[k]];
+    }
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) v[k] = k <= last ? v[k] : 0u;
 }
 
 // out[base + k] = run + v[0] + ... + v[k-1] for the positions below n (16-byte stores when whole
@@ -157,34 +173,66 @@ __global__ __launch_bounds__(kThreads) void scan_apply_kernel(const uint32_t *in
 constexpr int kOneThreads = 1024;
 constexpr int64_t kOneBlockMax = 4 * kOneThreads * kItems; // 65536
 
-template <bool GATHER>
+template <bool GATHER, int NT>
 __global__ __launch_bounds__(kOneThreads) void scan_one_block_kernel(const uint32_t *in, const uint32_t *gather,
                                                                      int64_t n, uint32_t *out, uint32_t *total_out) {
-    __shared__ uint32_t s_wave[kOneThreads / 64];
+    // Rounds of NT tiles of kOneThreads * kItems items; a round's loads are all issued before its
+    // first scan, so the block waits for memory once per round, not once per tile (more than two
+    // tiles in flight would exceed the 128 registers a 1024-thread block allows). In-place use
+    // (out == in) is safe: each thread stores only the items it loaded itself.
+    constexpr int64_t TILE = (int64_t)kOneThreads * kItems;
+    __shared__ uint32_t s_wave[NT][kOneThreads / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint32_t carry = 0;
-    for (int64_t tile = 0; tile < n; tile += (int64_t)kOneThreads * kItems) {
-        const int64_t base = tile + (int64_t)threadIdx.x * kItems;
-        uint32_t v[kItems];
-        load_chunk<GATHER>(in, gather, n, base, v);
-        uint32_t sum = 0;
+    for (int64_t round = 0; round < n; round += NT * TILE) {
+        uint32_t v[NT][kItems];
 #pragma unroll
-        for (int k = 0; k < kItems; ++k) sum += v[k];
-        const uint32_t inc = wave_inclusive_scan(sum, lane);
-        if (lane == 63) s_wave[wave] = inc;
-        __syncthreads();
-        uint32_t off = 0, tot = 0;
+        for (int t = 0; t < NT; ++t)
+            load_chunk<GATHER>(in, gather, n, round + t * TILE + (int64_t)threadIdx.x * kItems, v[t]);
+        uint32_t sum[NT], inc[NT];
 #pragma unroll
-        for (int w = 0; w < kOneThreads / 64; ++w) {
-            const uint32_t x = s_wave[w];
-            off += (w < wave) ? x : 0u;
-            tot += x;
+        for (int t = 0; t < NT; ++t) {
+            sum[t] = 0;
+#pragma unroll
+            for (int k = 0; k < kItems; ++k) sum[t] += v[t][k];
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) inc[t] = wave_inclusive_scan(sum[t], lane);
+        if (lane == 63) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) s_wave[t][wave] = inc[t];
         }
         __syncthreads();
-        store_chunk_scan(out, n, base, carry + off + inc - sum, v);
-        carry += tot;
+        uint32_t off[NT], tot[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            off[t] = 0;
+            tot[t] = 0;
+#pragma unroll
+            for (int w = 0; w < kOneThreads / 64; ++w) {
+                const uint32_t x = s_wave[t][w];
+                off[t] += (w < wave) ? x : 0u;
+                tot[t] += x;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            store_chunk_scan(out, n, round + t * TILE + (int64_t)threadIdx.x * kItems, carry + off[t] + inc[t] - sum[t],
+                             v[t]);
+            carry += tot[t];
+        }
     }
     if (total_out && threadIdx.x == 0) *total_out = carry;
+}
+
+template <bool GATHER>
+void launch_scan_one_block(const uint32_t *in, const uint32_t *gather, int64_t n, uint32_t *out, uint32_t *total,
+                           hipStream_t st) {
+    if (n <= (int64_t)kOneThreads * kItems)
+        scan_one_block_kernel<GATHER, 1><<<1, kOneThreads, 0, st>>>(in, gather, n, out, total);
+    else
+        scan_one_block_kernel<GATHER, 2><<<1, kOneThreads, 0, st>>>(in, gather, n, out, total);
 }
 
 } // namespace
@@ -213,8 +261,8 @@ hipError_t device_exclusive_scan(const uint32_t *in, const uint32_t *gather, uin
         return hipGetLastError();
     }
     if (n <= kOneBlockMax) {
-        if (gather) scan_one_block_kernel<true><<<1, kOneThreads, 0, st>>>(in, gather, n, out, total);
-        else scan_one_block_kernel<false><<<1, kOneThreads, 0, st>>>(in, gather, n, out, total);
+        if (gather) launch_scan_one_block<true>(in, gather, n, out, total, st);
+        else launch_scan_one_block<false>(in, gather, n, out, total, st);
         return hipGetLastError();
     }
     if (gather) scan_reduce_kernel<true><<<(unsigned)blocks, kThreads, 0, st>>>(in, gather, n, partials);

@@ -1,10 +1,11 @@
 """Tile lists at scene sizes that take every path of the device scans and
-radix sorts: a single scan block, the one-launch scan of up to 64k items, the
-two-level scan; 1024-item radix tiles below two million items. For each size
-the exported lists must be the sorted order of the pairs: the tile ranges
-partition [0, P), the entries increase strictly in (tile, fp32 depth bits,
-id), every Gaussian appears exactly tiles_touched times, and the visible
-count is the number of positive radii."""
+radix sorts: a single scan block, the one-launch scan of up to 64k items in
+one or two rounds, the two-level scan; 1024-item radix tiles below two
+million items. For each size the exported lists must be the sorted order of
+the pairs: the tile ranges partition [0, P), the entries increase strictly
+in (tile, fp32 depth bits, id), every Gaussian appears exactly
+tiles_touched times, and the visible count is the number of positive
+radii."""
 import numpy as np
 import pytest
 
@@ -25,7 +26,7 @@ def renderer(gsr):
 
 
 @pytest.mark.parametrize("n,width,height", [(1, 64, 64), (2, 64, 64), (3000, 320, 240), (30_000, 640, 480),
-                                            (300_000, 1280, 720)])
+                                            (50_000, 800, 600), (300_000, 1280, 720)])
 def test_lists_are_sorted_at_every_size(renderer, n, width, height):
     say(f"[gpu] sort sizes n={n} {width}x{height}")
     wl = sg.object_100k(seed=11, n=n, width=width, height=height)
