@@ -83,10 +83,13 @@ hipError_t device_exclusive_scan(const uint32_t *in, const uint32_t *gather, uin
 
 // Stable LSD radix sort of (key, value) pairs on key bits [0, bits). Buffers
 // ping-pong between (k0,v0) and (k1,v1); returns the index (0/1) holding the
-// result in *which.
+// result in *which. With n_dev the item count is read on the device (at most n,
+// which sizes the launches); with range_dev = (max ~key, max key) on the device,
+// passes above the keys' highest varying bit copy instead of sorting.
 size_t radix_hist_count(int64_t n);
 hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n, int bits,
-                            uint32_t *hist, uint32_t *partials, int *which, hipStream_t st);
+                            uint32_t *hist, uint32_t *partials, int *which, hipStream_t st,
+                            const uint32_t *n_dev = nullptr, const uint32_t *range_dev = nullptr);
 
 // a2: expand each depth-ordered Gaussian into its (tile, id) pairs; pairs at positions >= cap
 // are dropped.
@@ -192,6 +195,7 @@ struct gsr_ctx {
     gsr::Pool *pool = nullptr;
     uint32_t *host_pinned = nullptr; // small readback area
     hipEvent_t ev[12] = {};
+    hipEvent_t ev_counts = nullptr;  // counts of a render read back (no timing)
     bool timing_render = false, timing_bwd = false;
 };
 

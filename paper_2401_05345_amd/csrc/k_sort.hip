@@ -293,11 +293,33 @@ __host__ __device__ __forceinline__ int64_t sort_blocks(int64_t n) {
     return (n + t - 1) / t;
 }
 
+// A sort whose item count and key range exist only on the device (enqueued before the host has
+// read them back): n_dev (nullable) holds the item count, at most the launch's n, and range_dev
+// (nullable) holds (max ~key, max key). A pass whose digit lies wholly above the keys' highest
+// varying bit copies its items unchanged: a stable pass over a digit that every key shares is the
+// identity, and the copy keeps the host's buffer parity.
+__device__ __forceinline__ int64_t dev_items(int64_t n, const uint32_t *n_dev) {
+    return n_dev ? (n < (int64_t)*n_dev ? n : (int64_t)*n_dev) : n;
+}
+__device__ __forceinline__ bool dev_skip(int shift, const uint32_t *range_dev) {
+    if (!range_dev) return false;
+    const uint32_t lo = ~range_dev[0], hi = range_dev[1];
+    const int bits = lo < hi ? 32 - __clz((int)(lo ^ hi)) : 0;
+    return shift >= bits;
+}
+
 // Digit histogram of each block of ITEMS * 256 items, written digit-major so
 // one exclusive scan of the whole table yields every block's output offsets.
 template <int ITEMS>
 __global__ __launch_bounds__(kThreads) void radix_hist_kernel(const uint32_t *keys, int64_t n, int shift,
-                                                              uint32_t mask, uint32_t *hist, int64_t blocks) {
+                                                              uint32_t mask, uint32_t *hist, int64_t blocks,
+                                                              const uint32_t *n_dev, const uint32_t *range_dev) {
+    n = dev_items(n, n_dev);
+    if (n <= 0 || dev_skip(shift, range_dev)) return; // the scatter then ignores the table
+    if ((int64_t)blockIdx.x * (kThreads * ITEMS) >= n) { // past the device-side count: an empty column
+        hist[(int64_t)threadIdx.x * blocks + blockIdx.x] = 0u;
+        return;
+    }
     __shared__ uint32_t s_count[kBins];
     s_count[threadIdx.x] = 0;
     __syncthreads();
@@ -321,8 +343,22 @@ template <int ITEMS>
 __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(const uint32_t *keys_in, const uint32_t *vals_in,
                                                                  uint32_t *keys_out, uint32_t *vals_out, int64_t n,
                                                                  int shift, int nbits, const uint32_t *offsets,
-                                                                 int64_t blocks) {
+                                                                 int64_t blocks, const uint32_t *n_dev,
+                                                                 const uint32_t *range_dev) {
     constexpr int TILE_ITEMS = kThreads * ITEMS;
+    n = dev_items(n, n_dev);
+    if ((int64_t)blockIdx.x * TILE_ITEMS >= n) return; // past the device-side count: no items
+    if (dev_skip(shift, range_dev)) {
+#pragma unroll
+        for (int r = 0; r < ITEMS; ++r) {
+            const int64_t i = (int64_t)blockIdx.x * TILE_ITEMS + (int64_t)r * kThreads + threadIdx.x;
+            if (i < n) {
+                keys_out[i] = keys_in[i];
+                vals_out[i] = vals_in[i];
+            }
+        }
+        return;
+    }
     __shared__ uint32_t s_wcount[kWaves][kBins];
     __shared__ uint32_t s_dstart[kBins];
     __shared__ uint32_t s_wave[kWaves];
@@ -392,14 +428,16 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(const uint32_t 
 
 template <int ITEMS>
 hipError_t radix_pass(const uint32_t *k_in, const uint32_t *v_in, uint32_t *k_out, uint32_t *v_out, int64_t n,
-                      int shift, int nb, int64_t blocks, uint32_t *hist, uint32_t *partials, hipStream_t st) {
-    radix_hist_kernel<ITEMS><<<(unsigned)blocks, kThreads, 0, st>>>(k_in, n, shift, (1u << nb) - 1u, hist, blocks);
+                      int shift, int nb, int64_t blocks, uint32_t *hist, uint32_t *partials, const uint32_t *n_dev,
+                      const uint32_t *range_dev, hipStream_t st) {
+    radix_hist_kernel<ITEMS><<<(unsigned)blocks, kThreads, 0, st>>>(k_in, n, shift, (1u << nb) - 1u, hist, blocks,
+                                                                     n_dev, range_dev);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = device_exclusive_scan(hist, nullptr, hist, blocks * kBins, nullptr, partials, st);
     if (e != hipSuccess) return e;
     radix_scatter_kernel<ITEMS><<<(unsigned)blocks, kThreads, 0, st>>>(k_in, v_in, k_out, v_out, n, shift, nb, hist,
-                                                                        blocks);
+                                                                        blocks, n_dev, range_dev);
     return hipGetLastError();
 }
 
@@ -414,7 +452,8 @@ size_t radix_hist_count(int64_t n) {
 }
 
 hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n, int bits,
-                            uint32_t *hist, uint32_t *partials, int *which, hipStream_t st) {
+                            uint32_t *hist, uint32_t *partials, int *which, hipStream_t st, const uint32_t *n_dev,
+                            const uint32_t *range_dev) {
     *which = 0;
     if (n <= 1 || bits <= 0) return hipSuccess;
     const int64_t blocks = sort_blocks(n);
@@ -424,9 +463,10 @@ hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *
     for (int shift = 0; shift < bits; shift += 8) {
         const int nb = (bits - shift) < 8 ? (bits - shift) : 8;
         const hipError_t e =
-            small ? radix_pass<4>(ks[cur], vs[cur], ks[cur ^ 1], vs[cur ^ 1], n, shift, nb, blocks, hist, partials, st)
+            small ? radix_pass<4>(ks[cur], vs[cur], ks[cur ^ 1], vs[cur ^ 1], n, shift, nb, blocks, hist, partials,
+                                  n_dev, range_dev, st)
                   : radix_pass<kItems>(ks[cur], vs[cur], ks[cur ^ 1], vs[cur ^ 1], n, shift, nb, blocks, hist,
-                                       partials, st);
+                                       partials, n_dev, range_dev, st);
         if (e != hipSuccess) return e;
         cur ^= 1;
     }

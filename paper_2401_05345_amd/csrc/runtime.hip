@@ -222,6 +222,10 @@ gsr_status gsr_ctx_create(gsr_ctx **out, int device, void *hip_stream) {
             return GSR_EHIP;
         }
     }
+    if (hipEventCreateWithFlags(&ctx->ev_counts, hipEventDisableTiming) != hipSuccess) {
+        gsr_ctx_destroy(ctx);
+        return GSR_EHIP;
+    }
     *out = ctx;
     return GSR_OK;
 }
@@ -232,6 +236,7 @@ void gsr_ctx_destroy(gsr_ctx *ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     for (auto &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
+    if (ctx->ev_counts) (void)hipEventDestroy(ctx->ev_counts);
     delete ctx->pool;
     if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
     delete ctx;
@@ -457,17 +462,30 @@ gsr_status render_views(gsr_ctx *ctx, int nv, const gsr_scene *scenes, const gsr
                                       st->key_alt, st->ids_alt, s));
         GSR_RH(hipMemcpyAsync(ctx->host_pinned + 6 * v, st->totals, 6 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     }
-    GSR_RH(hipStreamSynchronize(s));
+    GSR_RH(hipEventRecord(ctx->ev_counts, s));
+    // a2/a3 (depth digits): stable sort of the visible Gaussians by fp32 depth (ties keep index
+    // order). Bits above the highest one in which the smallest and the largest visible key differ
+    // are the same in every key and need no pass (for an object seen from outside the exponent
+    // byte of every depth is the same). One view: the sort is enqueued before the host waits for
+    // the counts, launched for all n Gaussians and bounded by the visible count and key range
+    // on the device (passes above the varying bits copy), so the GPU sorts while the counts
+    // travel. Several views share one wait: each view's sort is sized by its read-back count.
+    const bool overlap = nv == 1;
+    if (overlap) {
+        gsr_fwd *st = sts[0];
+        int which = 0;
+        GSR_RH(radix_sort_pairs(st->key_alt, st->ids_alt, st->depth_key, st->ids, st->n, 32, st->dsort_hist,
+                                st->dsort_partials, &which, s, st->totals + 1, st->totals + 4));
+        st->sorted_ids_by_depth = which ? st->ids : st->ids_alt;
+    }
+    GSR_RH(hipEventSynchronize(ctx->ev_counts));
     for (int v = 0; v < nv; ++v) {
         gsr_fwd *st = sts[v];
         const uint32_t *h = ctx->host_pinned + 6 * v;
         st->P = st->n > 0 ? (int64_t)h[0] : 0;
         st->n_visible = st->n > 0 ? (int64_t)h[1] : 0;
         st->p_known = true;
-        // a2/a3 (depth digits): stable sort of the visible Gaussians by fp32 depth (ties keep
-        // index order). Bits above the highest one in which the smallest and the largest key
-        // differ are the same in every key: only the bits below it are sorted (for an object
-        // seen from outside, the exponent byte of every depth is the same: three passes).
+        if (overlap) continue;
         const uint32_t kmin = ~h[4], kmax = h[5];
         const int bits = kmin < kmax ? 32 - __builtin_clz(kmin ^ kmax) : 0;
         int which = 0;
