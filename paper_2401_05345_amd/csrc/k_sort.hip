@@ -308,8 +308,9 @@ __device__ __forceinline__ bool dev_skip(int shift, const uint32_t *range_dev) {
     return shift >= bits;
 }
 
-// Digit histogram of each block of ITEMS * 256 items, written digit-major so
-// one exclusive scan of the whole table yields every block's output offsets.
+// Digit histogram of each block of ITEMS * 256 items, written digit-major (mask + 1
+// rows of `blocks` entries) so one exclusive scan of the whole table yields every
+// block's output offsets.
 template <int ITEMS>
 __global__ __launch_bounds__(kThreads) void radix_hist_kernel(const uint32_t *keys, int64_t n, int shift,
                                                               uint32_t mask, uint32_t *hist, int64_t blocks,
@@ -317,7 +318,7 @@ __global__ __launch_bounds__(kThreads) void radix_hist_kernel(const uint32_t *ke
     n = dev_items(n, n_dev);
     if (n <= 0 || dev_skip(shift, range_dev)) return; // the scatter then ignores the table
     if ((int64_t)blockIdx.x * (kThreads * ITEMS) >= n) { // past the device-side count: an empty column
-        hist[(int64_t)threadIdx.x * blocks + blockIdx.x] = 0u;
+        if (threadIdx.x <= mask) hist[(int64_t)threadIdx.x * blocks + blockIdx.x] = 0u;
         return;
     }
     __shared__ uint32_t s_count[kBins];
@@ -331,7 +332,7 @@ __global__ __launch_bounds__(kThreads) void radix_hist_kernel(const uint32_t *ke
     for (int r = 0; r < ITEMS; ++r)
         if (pos(r) < n) atomicAdd(&s_count[(k[r] >> shift) & mask], 1u);
     __syncthreads();
-    hist[(int64_t)threadIdx.x * blocks + blockIdx.x] = s_count[threadIdx.x];
+    if (threadIdx.x <= mask) hist[(int64_t)threadIdx.x * blocks + blockIdx.x] = s_count[threadIdx.x];
 }
 
 // Stable scatter of one block of ITEMS * 256 items. Wave w ranks items
@@ -434,7 +435,7 @@ hipError_t radix_pass(const uint32_t *k_in, const uint32_t *v_in, uint32_t *k_ou
                                                                      n_dev, range_dev);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = device_exclusive_scan(hist, nullptr, hist, blocks * kBins, nullptr, partials, st);
+    e = device_exclusive_scan(hist, nullptr, hist, blocks << nb, nullptr, partials, st); // (1 << nb) rows
     if (e != hipSuccess) return e;
     radix_scatter_kernel<ITEMS><<<(unsigned)blocks, kThreads, 0, st>>>(k_in, v_in, k_out, v_out, n, shift, nb, hist,
                                                                         blocks, n_dev, range_dev);
@@ -459,8 +460,11 @@ hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *
     const int64_t blocks = sort_blocks(n);
     const bool small = sort_items(n) == 4;
     uint32_t *ks[2] = {k0, k1}, *vs[2] = {v0, v1};
+    // 8-bit digits, the remainder in the last pass, whose table has only 1 << remainder rows (12
+    // bits as 8 + 4 measured faster than as 6 + 6: the narrow last pass has a one-launch scan).
+    const int passes = (bits + 7) / 8;
     int cur = 0;
-    for (int shift = 0; shift < bits; shift += 8) {
+    for (int p = 0, shift = 0; p < passes; ++p) {
         const int nb = (bits - shift) < 8 ? (bits - shift) : 8;
         const hipError_t e =
             small ? radix_pass<4>(ks[cur], vs[cur], ks[cur ^ 1], vs[cur ^ 1], n, shift, nb, blocks, hist, partials,
@@ -469,6 +473,7 @@ hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *
                                        partials, n_dev, range_dev, st);
         if (e != hipSuccess) return e;
         cur ^= 1;
+        shift += nb;
     }
     *which = cur;
     return hipSuccess;
