@@ -97,7 +97,10 @@ __device__ __forceinline__ uint32_t emit9(bool active, uint64_t m, float (&v)[9]
     if (sparse) return issued;
     reduced_mask_out = m; // threshold >= 1, so cnt > 0 here
     if (SPLIT) {
-        const float mine = wave_sum9_scatter(v, lane);
+        float mine = wave_sum9_scatter(v, lane);
+        // The last exchange's add stays with its exchange (one DPP add at full exec) instead of
+        // sinking into the issuing lanes' branch as a separate move, clear and add.
+        asm volatile("" : "+v"(mine));
         if (sum9_issues(lane)) {
             atomic_acc(dst + sum9_slot(lane), mine);
             issued = 1;
