@@ -30,15 +30,18 @@ __device__ __forceinline__ void rect_of(float u, float v, int r, const DevCamera
 // reach 2 ln(255 o) of the splat is rescaled to the same units
 // (log2(255 o)). Everything else is the record as stored.
 constexpr float kLog2e = 1.4426950408889634f;
+__device__ __forceinline__ void prescale_record(float4 &r0, float4 &r1, float4 &r2) {
+    r0.z *= -0.5f * kLog2e;
+    r0.w *= -kLog2e;
+    r1.x *= -0.5f * kLog2e;
+    r2.z *= 0.5f * kLog2e;
+}
 __device__ __forceinline__ void stage_record(const float4 *__restrict__ rec, uint32_t g, float4 &r0, float4 &r1,
                                              float4 &r2) {
     r0 = rec[3 * (size_t)g];
     r1 = rec[3 * (size_t)g + 1];
     r2 = rec[3 * (size_t)g + 2];
-    r0.z *= -0.5f * kLog2e;
-    r0.w *= -kLog2e;
-    r1.x *= -0.5f * kLog2e;
-    r2.z *= 0.5f * kLog2e;
+    prescale_record(r0, r1, r2);
 }
 
 // One (pixel, splat) evaluation on a staged record. The forward composite and

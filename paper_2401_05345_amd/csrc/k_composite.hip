@@ -206,11 +206,34 @@ __global__ __launch_bounds__(TILE *TILE) void composite_fwd_kernel(ViewBatch vb,
     float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
     uint32_t last = 0;
     bool done = !inside;
+    // The next batch's records are loaded while this batch is walked (and the list ids of the
+    // batch after it), so staging a batch does not wait for memory.
+    const bool stager = tid < BATCH;
+    float4 n0 = make_float4(0.f, 0.f, 0.f, 0.f), n1 = n0, n2 = n0; // raw records of the next batch
+    uint32_t id_next = 0;                                              // list ids one batch further
+    if (stager && rg.x + tid < rg.y) {
+        const size_t g = 3 * (size_t)ids[rg.x + tid];
+        n0 = rec[g];
+        n1 = rec[g + 1];
+        n2 = rec[g + 2];
+    }
+    if (stager && rg.x + BATCH + tid < rg.y) id_next = ids[rg.x + BATCH + tid];
     for (uint32_t start = rg.x; start < rg.y; start += BATCH) {
         if (__syncthreads_count(done) == NT) break;
-        const uint32_t k = start + tid;
-        if (tid < BATCH && k < rg.y) stage_record(rec, ids[k], s0[tid], s1[tid], s2[tid]);
+        if (stager && start + tid < rg.y) {
+            prescale_record(n0, n1, n2);
+            s0[tid] = n0;
+            s1[tid] = n1;
+            s2[tid] = n2;
+        }
         __syncthreads();
+        if (stager && start + BATCH + tid < rg.y) {
+            const size_t g = 3 * (size_t)id_next;
+            n0 = rec[g];
+            n1 = rec[g + 1];
+            n2 = rec[g + 2];
+        }
+        if (stager && start + 2 * BATCH + tid < rg.y) id_next = ids[start + 2 * BATCH + tid];
         const int cnt = min(BATCH, (int)(rg.y - start));
         uint64_t vis[BATCH / 64];
         wave_visit_masks<BATCH>(s0, s1, s2, cnt, qcx, qcy, lane, vis);
