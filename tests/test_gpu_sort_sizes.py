@@ -30,7 +30,26 @@ def renderer(gsr):
 def test_lists_are_sorted_at_every_size(renderer, n, width, height):
     say(f"[gpu] sort sizes n={n} {width}x{height}")
     wl = sg.object_100k(seed=11, n=n, width=width, height=height)
-    gs = GpuScene(wl.scene, wl.camera)
+    _check_lists(renderer, wl.scene, wl.camera, n)
+
+
+def test_lists_sorted_when_depths_share_their_high_bits(renderer):
+    # Every depth in [4.5, 4.5001]: the visible depth keys differ only in their low bits, so the
+    # upper passes of the depth sort copy instead of sorting.
+    say("[gpu] sort with a narrow depth range")
+    n = 20_000
+    rng = np.random.default_rng(5)
+    sc = sg.random_scene(rng, n, means="uniform", half=1.0, log_scale=(-3.5, 0.3), sh_degree=0)
+    m = sc.means3d.copy()
+    m[:, 2] = np.float32(0.5) + rng.uniform(0.0, 1e-4, n).astype(np.float32)
+    sc = sg.Scene(m, sc.log_scales, sc.quats, sc.opacity_logits, sc.sh, 0)
+    out = _check_lists(renderer, sc, sg.make_camera(640, 480, (0.0, 0.0, -4.0)), n)
+    key = out["depth"].view(np.uint32)[out["radius"][:n] > 0]
+    assert key.size > 1000 and int(key.min() ^ key.max()).bit_length() <= 16
+
+
+def _check_lists(renderer, scene, camera, n):
+    gs = GpuScene(scene, camera)
     st, out = run_render(renderer, gs, gsr.make_config())
     try:
         stats = out["stats"]
@@ -40,7 +59,7 @@ def test_lists_are_sorted_at_every_size(renderer, n, width, height):
         touched = out["tiles_touched"][:n].astype(np.int64)
         assert int(touched.sum()) == P
         if P == 0:
-            return
+            return out
         ids = out["sorted_ids"].astype(np.int64)
         assert np.array_equal(np.bincount(ids, minlength=n), touched)
         rgs = out["ranges"].astype(np.int64)
@@ -54,5 +73,6 @@ def test_lists_are_sorted_at_every_size(renderer, n, width, height):
             step = np.stack([np.diff(tile_of), np.diff(key), np.diff(ids)], 1)
             first_nz = np.where(step[:, 0] != 0, step[:, 0], np.where(step[:, 1] != 0, step[:, 1], step[:, 2]))
             assert (first_nz > 0).all()
+        return out
     finally:
         gsr.gsr_fwd_release(renderer.ctx, st)
