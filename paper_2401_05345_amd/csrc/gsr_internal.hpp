@@ -75,8 +75,9 @@ hipError_t launch_zero_visible_rows(const int32_t *radius, int64_t n, const uint
 hipError_t launch_export_acc(const int32_t *radius, const float4 *rec, int64_t n, const void *acc, bool acc_f64,
                              float *dst, hipStream_t st);
 
-// Exclusive scan of n uint32 values (in[gather[i]] when gather != nullptr).
-// total (device, may be nullptr) receives the sum. Scratch sized by scan_scratch_count.
+// Exclusive scan of n uint32 values (in[gather[i]] when gather != nullptr; out may equal in when
+// gather is nullptr, and must alias neither in nor gather when it is not). total (device, may be
+// nullptr) receives the sum. Scratch sized by scan_partial_count.
 size_t scan_partial_count(int64_t n);
 hipError_t device_exclusive_scan(const uint32_t *in, const uint32_t *gather, uint32_t *out, int64_t n,
                                  uint32_t *total, uint32_t *partials, hipStream_t st);

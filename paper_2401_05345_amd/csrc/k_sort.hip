@@ -235,6 +235,13 @@ void launch_scan_one_block(const uint32_t *in, const uint32_t *gather, int64_t n
         scan_one_block_kernel<GATHER, 2><<<1, kOneThreads, 0, st>>>(in, gather, n, out, total);
 }
 
+// out[i] = in[gather[i]]
+__global__ __launch_bounds__(256) void gather_u32_kernel(const uint32_t *in, const uint32_t *gather, int64_t n,
+                                                         uint32_t *out) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) out[i] = in[gather[i]];
+}
+
 } // namespace
 
 size_t scan_partial_count(int64_t n) {
@@ -255,6 +262,15 @@ hipError_t device_exclusive_scan(const uint32_t *in, const uint32_t *gather, uin
         return hipSuccess;
     }
     const int64_t blocks = (n + kTileItems - 1) / kTileItems;
+    if (gather && blocks > 1) {
+        // More than one tile: gather into out first (index reads coalesced, one random read per
+        // item), then scan out in place; the scan kernels would each gather again, through
+        // thread-contiguous index chunks. out aliases neither in nor gather.
+        gather_u32_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(in, gather, n, out);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        return device_exclusive_scan(out, nullptr, out, n, total, partials, st);
+    }
     if (blocks == 1) {
         if (gather) scan_apply_kernel<true><<<1, kThreads, 0, st>>>(in, gather, n, nullptr, out, total);
         else scan_apply_kernel<false><<<1, kThreads, 0, st>>>(in, gather, n, nullptr, out, total);
