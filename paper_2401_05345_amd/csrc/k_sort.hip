@@ -498,21 +498,22 @@ hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *
 // ---------------------------------------------------------------------------
 namespace {
 
-// One thread per depth-ordered Gaussian writes its rectangle's pairs (row by
-// row). Rectangles of more than 32 tiles - the few Gaussians that cover much
-// of the screen - would hold their wave for thousands of serial stores, so
-// they are written by the whole wave instead, one rectangle at a time, lanes
-// striding over its tiles; the pair order is the same either way.
+// A wave takes 64 consecutive depth-ordered Gaussians and writes their pairs together: the
+// wave's pairs are one contiguous run of the list (each Gaussian's rectangle row by row, the
+// Gaussians in depth order), so lane l writes entries l, l + 64, ... of that run and each
+// store instruction covers consecutive addresses. Entry k belongs to the last of the 64
+// Gaussians whose exclusive prefix count is at most k (a six-step search over the wave's
+// prefix counts in LDS).
 __global__ __launch_bounds__(256) void emit_pairs_kernel(int64_t n, const uint32_t *sorted_ids,
                                                           const uint32_t *offsets, const float4 *rec,
                                                           const int32_t *radius, DevCamera cam, uint32_t *pair_tile,
                                                           uint32_t *pair_id, uint32_t cap) {
-    constexpr int kSerialMax = 32;
+    __shared__ uint32_t s_pre[4][64], s_off[4][64], s_g[4][64];
+    __shared__ int s_x0[4][64], s_y0[4][64], s_w[4][64];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int x0 = 0, x1 = 0, y0 = 0, y1 = 0;
     uint32_t o = 0, g = 0;
-    bool big = false;
     if (i < n) {
         g = sorted_ids[i];
         const int r = radius[g];
@@ -520,34 +521,35 @@ __global__ __launch_bounds__(256) void emit_pairs_kernel(int64_t n, const uint32
             const float4 r0 = rec[3 * (int64_t)g];
             rect_of(r0.x, r0.y, r, cam, x0, x1, y0, y1);
             o = offsets[i];
-            if ((x1 - x0) * (y1 - y0) > kSerialMax) {
-                big = true;
-            } else {
-                uint32_t oo = o;
-                for (int ty = y0; ty < y1; ++ty)
-                    for (int tx = x0; tx < x1; ++tx) {
-                        if (oo < cap) { // pairs past the buffer's capacity are dropped (pad_pairs flags it)
-                            pair_tile[oo] = (uint32_t)(ty * cam.grid_x + tx);
-                            pair_id[oo] = g;
-                        }
-                        ++oo;
-                    }
-            }
         }
     }
-    for (uint64_t bigm = __ballot(big); bigm; bigm &= bigm - 1) {
-        const int l = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(bigm));
-        const int bx0 = __builtin_amdgcn_readlane(x0, l), bx1 = __builtin_amdgcn_readlane(x1, l);
-        const int by0 = __builtin_amdgcn_readlane(y0, l), by1 = __builtin_amdgcn_readlane(y1, l);
-        const uint32_t bo = (uint32_t)__builtin_amdgcn_readlane((int)o, l);
-        const uint32_t bg = (uint32_t)__builtin_amdgcn_readlane((int)g, l);
-        const int w = bx1 - bx0, cnt = w * (by1 - by0);
-        for (int k = lane; k < cnt; k += 64) {
-            const uint32_t oo = bo + (uint32_t)k;
-            if (oo < cap) {
-                pair_tile[oo] = (uint32_t)((by0 + k / w) * cam.grid_x + bx0 + k % w);
-                pair_id[oo] = bg;
-            }
+    const uint32_t cnt = (uint32_t)((x1 - x0) * (y1 - y0));
+    uint32_t inc = cnt;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t t = (uint32_t)__shfl_up((int)inc, d, 64);
+        if (lane >= d) inc += t;
+    }
+    s_pre[wave][lane] = inc - cnt;
+    s_off[wave][lane] = o;
+    s_g[wave][lane] = g;
+    s_x0[wave][lane] = x0;
+    s_y0[wave][lane] = y0;
+    s_w[wave][lane] = x1 - x0;
+    __syncthreads();
+    const uint32_t total = (uint32_t)__shfl((int)inc, 63, 64);
+    for (uint32_t k = (uint32_t)lane; k < total; k += 64) {
+        int j = 0;
+#pragma unroll
+        for (int step = 32; step >= 1; step >>= 1)
+            if (s_pre[wave][j + step] <= k) j += step;
+        const uint32_t local = k - s_pre[wave][j];
+        const uint32_t w = (uint32_t)s_w[wave][j];
+        const uint32_t row = local / w;
+        const uint32_t oo = s_off[wave][j] + local;
+        if (oo < cap) { // pairs past the buffer's capacity are dropped (pad_pairs flags it)
+            pair_tile[oo] = (uint32_t)((s_y0[wave][j] + (int)row) * cam.grid_x + s_x0[wave][j] + (int)(local - row * w));
+            pair_id[oo] = s_g[wave][j];
         }
     }
 }
