@@ -559,11 +559,26 @@ __global__ __launch_bounds__(1024) void order_tiles_kernel(ViewBatch vb, int mod
     };
     // Four items per thread and round, their work values loaded together (positions clamped to
     // the last item instead of a test around each load, which would serialise the loads).
+    // The first round's items stay in registers for the scatter pass (one round covers every
+    // tile of a single view up to 4096 tiles), so that pass reloads nothing for them.
     constexpr int U = 4;
+    uint2 vt0[U];
+    uint32_t b0[U];
     for (uint32_t i0 = threadIdx.x; i0 < n; i0 += U * blockDim.x) {
+        uint2 vt[U];
         uint32_t b[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) b[u] = bucket(locate_s(min(i0 + u * blockDim.x, n - 1)));
+        for (int u = 0; u < U; ++u) {
+            vt[u] = locate_s(min(i0 + u * blockDim.x, n - 1));
+            b[u] = bucket(vt[u]);
+        }
+        if (i0 == threadIdx.x) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                vt0[u] = vt[u];
+                b0[u] = b[u];
+            }
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u)
             if (i0 + u * blockDim.x < n) atomicAdd(&s_count[b[u]], 1u);
@@ -592,10 +607,18 @@ __global__ __launch_bounds__(1024) void order_tiles_kernel(ViewBatch vb, int mod
     for (uint32_t i0 = threadIdx.x; i0 < n; i0 += U * blockDim.x) {
         uint2 vt[U];
         uint32_t b[U];
+        if (i0 == threadIdx.x) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            vt[u] = locate_s(min(i0 + u * blockDim.x, n - 1));
-            b[u] = bucket(vt[u]);
+            for (int u = 0; u < U; ++u) {
+                vt[u] = vt0[u];
+                b[u] = b0[u];
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                vt[u] = locate_s(min(i0 + u * blockDim.x, n - 1));
+                b[u] = bucket(vt[u]);
+            }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
