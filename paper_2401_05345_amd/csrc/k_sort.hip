@@ -298,6 +298,7 @@ hipError_t device_exclusive_scan(const uint32_t *in, const uint32_t *gather, uin
 namespace {
 
 constexpr int kBins = 256;
+constexpr int64_t kFusedScanBlocks = 128; // radix passes of at most this many blocks derive offsets in the scatter
 
 // Sorts of fewer than kSmallSort items use 1024-item blocks (4 per thread)
 // instead of 4096: the visible Gaussians and pairs of a single view would
@@ -355,12 +356,16 @@ __global__ __launch_bounds__(kThreads) void radix_hist_kernel(const uint32_t *ke
 // [w*64*ITEMS, (w+1)*64*ITEMS) of the block in ITEMS rounds of 64; lanes
 // with equal digits find each other with one ballot per digit bit. Items are
 // staged in LDS in digit order and written out with consecutive threads on
-// consecutive addresses.
+// consecutive addresses. offsets: the scanned digit-major table, or with
+// fused != 0 the unscanned histogram table, from which each block derives its
+// own offsets (thread d sums row d: its total and the part before this block;
+// a scan over the digit totals adds the rows before it) - for tables of few
+// blocks, where a separate scan launch costs more than these reads.
 template <int ITEMS>
 __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(const uint32_t *keys_in, const uint32_t *vals_in,
                                                                  uint32_t *keys_out, uint32_t *vals_out, int64_t n,
                                                                  int shift, int nbits, const uint32_t *offsets,
-                                                                 int64_t blocks, const uint32_t *n_dev,
+                                                                 int64_t blocks, int fused, const uint32_t *n_dev,
                                                                  const uint32_t *range_dev) {
     constexpr int TILE_ITEMS = kThreads * ITEMS;
     n = dev_items(n, n_dev);
@@ -381,9 +386,25 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(const uint32_t 
     __shared__ uint32_t s_wave[kWaves];
     __shared__ uint32_t s_key[TILE_ITEMS];
     __shared__ uint32_t s_val[TILE_ITEMS];
+    __shared__ uint32_t s_goff[kBins];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t mask = (1u << nbits) - 1u;
     for (int i = threadIdx.x; i < kWaves * kBins; i += kThreads) (&s_wcount[0][0])[i] = 0;
+    if (fused) {
+        const uint32_t d = threadIdx.x; // kThreads == kBins
+        uint32_t before = 0, all = 0;
+        if (d <= mask) {
+            const uint32_t *row = offsets + (int64_t)d * blocks;
+#pragma unroll 8
+            for (int64_t b2 = 0; b2 < blocks; ++b2) {
+                const uint32_t h = row[b2];
+                all += h;
+                before += b2 < (int64_t)blockIdx.x ? h : 0u;
+            }
+        }
+        uint32_t unused;
+        s_goff[d] = block_exclusive_scan(all, s_wave, unused) + before;
+    }
     __syncthreads();
 
     const int64_t base = (int64_t)blockIdx.x * TILE_ITEMS;
@@ -437,7 +458,7 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(const uint32_t 
     for (uint32_t i = threadIdx.x; i < block_total; i += kThreads) {
         const uint32_t k = s_key[i];
         const uint32_t d = (k >> shift) & mask;
-        const int64_t dst = (int64_t)offsets[(int64_t)d * blocks + blockIdx.x] + (i - s_dstart[d]);
+        const int64_t dst = (int64_t)(fused ? s_goff[d] : offsets[(int64_t)d * blocks + blockIdx.x]) + (i - s_dstart[d]);
         keys_out[dst] = k;
         vals_out[dst] = s_val[i];
     }
@@ -451,10 +472,14 @@ hipError_t radix_pass(const uint32_t *k_in, const uint32_t *v_in, uint32_t *k_ou
                                                                      n_dev, range_dev);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = device_exclusive_scan(hist, nullptr, hist, blocks << nb, nullptr, partials, st); // (1 << nb) rows
-    if (e != hipSuccess) return e;
+    // Few blocks: each scatter block reads the histogram rows itself instead of a scan launch.
+    const int fused = blocks <= kFusedScanBlocks ? 1 : 0;
+    if (!fused) {
+        e = device_exclusive_scan(hist, nullptr, hist, blocks << nb, nullptr, partials, st); // (1 << nb) rows
+        if (e != hipSuccess) return e;
+    }
     radix_scatter_kernel<ITEMS><<<(unsigned)blocks, kThreads, 0, st>>>(k_in, v_in, k_out, v_out, n, shift, nb, hist,
-                                                                        blocks, n_dev, range_dev);
+                                                                        blocks, fused, n_dev, range_dev);
     return hipGetLastError();
 }
 
