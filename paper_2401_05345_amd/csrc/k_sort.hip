@@ -772,15 +772,52 @@ __global__ __launch_bounds__(kTotThreads) void visible_totals_kernel(uint4 *part
     }
 }
 
-// Visible entry i of block b goes to part[b].x plus its rank among the block's visible entries
-// (index order: item j of every wave before item j + 1, waves in order, lanes in order).
+// Visible entry i of block b goes to the block's offset plus its rank among the block's visible
+// entries (index order: item j of every wave before item j + 1, waves in order, lanes in order).
+// The offset is part[b].x as scanned by visible_totals_kernel, or with totals != nullptr (few
+// blocks, no totals launch) the sum of the earlier blocks' counts, which the block reads itself;
+// the last block then also writes the totals.
 __global__ __launch_bounds__(256) void compact_visible_kernel(const int32_t *r, int64_t n, const uint32_t *key,
-                                                              const uint4 *part, uint32_t *key_out,
-                                                              uint32_t *id_out) {
+                                                              const uint4 *part, int64_t nb, uint32_t *totals,
+                                                              uint32_t *key_out, uint32_t *id_out) {
     __shared__ uint32_t s_cnt[kVisItems][4];
+    __shared__ uint4 s_red[4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t base = (int64_t)blockIdx.x * kVisBlock + threadIdx.x;
-    const uint32_t boff = part[blockIdx.x].x;
+    uint32_t boff;
+    if (totals) {
+        const bool last_block = (int64_t)blockIdx.x == nb - 1;
+        uint32_t before = 0, all = 0, lo = 0, hi = 0, t = 0;
+        for (int64_t j = threadIdx.x; j < nb; j += 256) {
+            const uint4 q = part[j];
+            before += j < (int64_t)blockIdx.x ? q.x : 0u;
+            all += q.x;
+            lo = max(lo, q.y);
+            hi = max(hi, q.z);
+            t += q.w;
+        }
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            before += (uint32_t)__shfl_xor((int)before, d, 64);
+            all += (uint32_t)__shfl_xor((int)all, d, 64);
+            lo = max(lo, (uint32_t)__shfl_xor((int)lo, d, 64));
+            hi = max(hi, (uint32_t)__shfl_xor((int)hi, d, 64));
+            t += (uint32_t)__shfl_xor((int)t, d, 64);
+        }
+        if (lane == 0) s_red[wave] = make_uint4(before, lo, hi, t);
+        if (lane == 0) s_cnt[0][wave] = all;
+        __syncthreads();
+        boff = s_red[0].x + s_red[1].x + s_red[2].x + s_red[3].x;
+        if (last_block && threadIdx.x == 0) {
+            totals[0] = s_red[0].w + s_red[1].w + s_red[2].w + s_red[3].w;
+            totals[1] = s_cnt[0][0] + s_cnt[0][1] + s_cnt[0][2] + s_cnt[0][3];
+            totals[4] = max(max(s_red[0].y, s_red[1].y), max(s_red[2].y, s_red[3].y));
+            totals[5] = max(max(s_red[0].z, s_red[1].z), max(s_red[2].z, s_red[3].z));
+        }
+        __syncthreads(); // s_cnt is reused below
+    } else {
+        boff = part[blockIdx.x].x;
+    }
     int32_t rv[kVisItems];
     uint32_t kv[kVisItems];
 #pragma unroll
@@ -829,8 +866,12 @@ hipError_t launch_compact_visible(const int32_t *r, int64_t n, const uint32_t *k
     }
     const int64_t nb = (n + kVisBlock - 1) / kVisBlock;
     visible_stats_kernel<<<(unsigned)nb, 256, 0, st>>>(r, n, key, tiles, part);
-    visible_totals_kernel<<<1, kTotThreads, 0, st>>>(part, nb, totals);
-    compact_visible_kernel<<<(unsigned)nb, 256, 0, st>>>(r, n, key, part, key_out, id_out);
+    // Up to 128 blocks every compaction block sums the earlier blocks' counts itself (at most 2 KB
+    // of reads) and the totals launch is skipped.
+    const bool fused = nb <= 128;
+    if (!fused) visible_totals_kernel<<<1, kTotThreads, 0, st>>>(part, nb, totals);
+    compact_visible_kernel<<<(unsigned)nb, 256, 0, st>>>(r, n, key, part, nb, fused ? totals : nullptr, key_out,
+                                                         id_out);
     return hipGetLastError();
 }
 
