@@ -144,21 +144,31 @@ __global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const uint32_t *i
 }
 
 // Exclusive scan of each block's 4096 items plus the block's offset
-// (offsets == nullptr: single block, offset 0). Thread t owns items
+// (offsets == nullptr: single block, offset 0; fused != 0: offsets holds the
+// blocks' unscanned sums and each block adds up those before it itself, for
+// grids too small to pay for a launch that scans them). Thread t owns items
 // [t*16, t*16+16) of the block so the order is the natural one.
 template <bool GATHER>
 __global__ __launch_bounds__(kThreads) void scan_apply_kernel(const uint32_t *in, const uint32_t *gather, int64_t n,
-                                                              const uint32_t *offsets, uint32_t *out,
+                                                              const uint32_t *offsets, int fused, uint32_t *out,
                                                               uint32_t *total_out) {
     __shared__ uint32_t s_wave[kWaves];
     const int64_t base = (int64_t)blockIdx.x * kTileItems + (int64_t)threadIdx.x * kItems;
     uint32_t v[kItems];
     load_chunk<GATHER>(in, gather, n, base, v);
+    uint32_t boff = 0;
+    if (offsets && fused) {
+        uint32_t acc = 0;
+        for (int64_t j = threadIdx.x; j < (int64_t)blockIdx.x; j += kThreads) acc += offsets[j];
+        block_exclusive_scan(acc, s_wave, boff);
+    } else if (offsets) {
+        boff = offsets[blockIdx.x];
+    }
     uint32_t s = 0;
 #pragma unroll
     for (int k = 0; k < kItems; ++k) s += v[k];
     uint32_t total;
-    uint32_t run = block_exclusive_scan(s, s_wave, total) + (offsets ? offsets[blockIdx.x] : 0u);
+    uint32_t run = block_exclusive_scan(s, s_wave, total) + boff;
     run = store_chunk_scan(out, n, base, run, v);
     if (total_out && blockIdx.x == gridDim.x - 1 && threadIdx.x == kThreads - 1) {
         // Last item of the last block: its exclusive prefix plus itself is the grand total.
@@ -272,8 +282,8 @@ hipError_t device_exclusive_scan(const uint32_t *in, const uint32_t *gather, uin
         return device_exclusive_scan(out, nullptr, out, n, total, partials, st);
     }
     if (blocks == 1) {
-        if (gather) scan_apply_kernel<true><<<1, kThreads, 0, st>>>(in, gather, n, nullptr, out, total);
-        else scan_apply_kernel<false><<<1, kThreads, 0, st>>>(in, gather, n, nullptr, out, total);
+        if (gather) scan_apply_kernel<true><<<1, kThreads, 0, st>>>(in, gather, n, nullptr, 0, out, total);
+        else scan_apply_kernel<false><<<1, kThreads, 0, st>>>(in, gather, n, nullptr, 0, out, total);
         return hipGetLastError();
     }
     if (n <= kOneBlockMax) {
@@ -285,11 +295,17 @@ hipError_t device_exclusive_scan(const uint32_t *in, const uint32_t *gather, uin
     else scan_reduce_kernel<false><<<(unsigned)blocks, kThreads, 0, st>>>(in, gather, n, partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // Scan the partials in place (recursively), then apply.
-    e = device_exclusive_scan(partials, nullptr, partials, blocks, nullptr, partials + blocks + 1, st);
-    if (e != hipSuccess) return e;
-    if (gather) scan_apply_kernel<true><<<(unsigned)blocks, kThreads, 0, st>>>(in, gather, n, partials, out, total);
-    else scan_apply_kernel<false><<<(unsigned)blocks, kThreads, 0, st>>>(in, gather, n, partials, out, total);
+    // Up to 128 blocks each applying block adds up the partials before it; else the partials are
+    // scanned in place (recursively) first.
+    const int fused = blocks <= 128 ? 1 : 0;
+    if (!fused) {
+        e = device_exclusive_scan(partials, nullptr, partials, blocks, nullptr, partials + blocks + 1, st);
+        if (e != hipSuccess) return e;
+    }
+    if (gather)
+        scan_apply_kernel<true><<<(unsigned)blocks, kThreads, 0, st>>>(in, gather, n, partials, fused, out, total);
+    else
+        scan_apply_kernel<false><<<(unsigned)blocks, kThreads, 0, st>>>(in, gather, n, partials, fused, out, total);
     return hipGetLastError();
 }
 
