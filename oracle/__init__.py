@@ -17,11 +17,11 @@ and central finite differences).
 from .preprocess import (project, params_backward, splat_params, sh_basis, quat_to_rot, depth_key_f32,
                          sh_constants, covariance3d)
 from .composite import render, backward, composite_backward, tile_lists, pixel_entries, build_raster_lib
-from .loss import loss_and_grad, ssim
+from .loss import loss_and_grad, ssim, ssim_map, gaussian_window
 from .adam import adam_step
 
 __all__ = [
     "project", "params_backward", "splat_params", "sh_basis", "quat_to_rot", "depth_key_f32", "sh_constants", "covariance3d",
     "render", "backward", "composite_backward", "tile_lists", "pixel_entries", "build_raster_lib",
-    "loss_and_grad", "ssim", "adam_step",
+    "loss_and_grad", "ssim", "ssim_map", "gaussian_window", "adam_step",
 ]

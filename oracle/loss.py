@@ -19,16 +19,17 @@ import torch
 import torch.nn.functional as F
 
 
-def _window(size=11, sigma=1.5):
+def gaussian_window(size=11, sigma=1.5):
+    """[size,size] float64 window: outer product of the sampled 1-D Gaussian, normalised to sum 1."""
     x = torch.arange(size, dtype=torch.float64) - (size - 1) / 2.0
     g = torch.exp(-(x * x) / (2 * sigma * sigma))
     g = g / g.sum()
     return torch.outer(g, g)
 
 
-def ssim(img: torch.Tensor, ref: torch.Tensor) -> torch.Tensor:
-    """Mean SSIM of two [3,H,W] float64 images."""
-    w = _window().expand(3, 1, 11, 11).contiguous()
+def ssim_map(img: torch.Tensor, ref: torch.Tensor) -> torch.Tensor:
+    """Per-pixel SSIM [3,H,W] of two [3,H,W] float64 images (window statistics with zero padding)."""
+    w = gaussian_window().expand(3, 1, 11, 11).contiguous()
     x, y = img[None], ref[None]
     mu_x = F.conv2d(x, w, padding=5, groups=3)
     mu_y = F.conv2d(y, w, padding=5, groups=3)
@@ -37,7 +38,12 @@ def ssim(img: torch.Tensor, ref: torch.Tensor) -> torch.Tensor:
     sxy = F.conv2d(x * y, w, padding=5, groups=3) - mu_x * mu_y
     c1, c2 = 0.01 ** 2, 0.03 ** 2
     s = ((2 * mu_x * mu_y + c1) * (2 * sxy + c2)) / ((mu_x * mu_x + mu_y * mu_y + c1) * (sxx + syy + c2))
-    return s.mean()
+    return s[0]
+
+
+def ssim(img: torch.Tensor, ref: torch.Tensor) -> torch.Tensor:
+    """Mean SSIM of two [3,H,W] float64 images (the mean of ssim_map over 3HW values)."""
+    return ssim_map(img, ref).mean()
 
 
 def loss_and_grad(image: np.ndarray, target: np.ndarray, kind: str = "l1", lam: float = 0.2):
