@@ -28,12 +28,12 @@ _LIB = os.path.join(_HERE, "_build", "liboracle_raster.so")
 
 
 def build_raster_lib(force: bool = False) -> str:
-    """Compile raster.c with gcc (plain -O2, no fast-math, no FMA contraction)."""
+    """Compile raster.c with gcc (plain -O2, no fast-math, no FMA contraction, OpenMP)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         os.makedirs(os.path.dirname(_LIB), exist_ok=True)
         tmp = _LIB + f".tmp{os.getpid()}"
         subprocess.run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
-                        "-fno-fast-math", "-o", tmp, _SRC, "-lm"], check=True)
+                        "-fno-fast-math", "-fopenmp", "-o", tmp, _SRC, "-lm"], check=True)
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -51,13 +51,23 @@ class _Frame(ctypes.Structure):
 _lib = None
 
 
+def default_threads() -> int:
+    """OpenMP threads of the per-pixel loops: OMP_NUM_THREADS when set, else the CPUs this
+    process may run on, at most 16."""
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        return int(env)
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
 def _raster():
     global _lib
     if _lib is None:
         lib = ctypes.CDLL(build_raster_lib())
-        lib.oracle_render.argtypes = [ctypes.POINTER(_Frame)] + [ctypes.c_void_p] * 6
+        lib.oracle_render.argtypes = [ctypes.POINTER(_Frame)] + [ctypes.c_void_p] * 6 + [ctypes.c_int]
         lib.oracle_render.restype = ctypes.c_int
-        lib.oracle_backward.argtypes = [ctypes.POINTER(_Frame), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
+        lib.oracle_backward.argtypes = [ctypes.POINTER(_Frame), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                        ctypes.c_int]
         lib.oracle_backward.restype = ctypes.c_int
         lib.oracle_pixel_entries.argtypes = [ctypes.POINTER(_Frame), ctypes.c_int, ctypes.c_int,
                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
@@ -138,7 +148,8 @@ def _frame(proj: Projected, lists: TileLists, cam, tile, tile_select, keep):
     return f
 
 
-def render(scene, cam, tile: int = 16, tile_select: np.ndarray | None = None) -> RenderResult:
+def render(scene, cam, tile: int = 16, tile_select: np.ndarray | None = None,
+           threads: int | None = None) -> RenderResult:
     """Forward pass: image [3,H,W] = sum_k alpha_k T_k c_k + T_final bg per pixel."""
     proj = project(scene, cam, tile)
     lists = tile_lists(proj, tile_select)
@@ -152,12 +163,13 @@ def render(scene, cam, tile: int = 16, tile_select: np.ndarray | None = None) ->
     keep = []
     f = _frame(proj, lists, cam, tile, tile_select, keep)
     rc = _raster().oracle_render(ctypes.byref(f), image.ctypes.data, T_final.ctypes.data,
-                                 n_contrib.ctypes.data, margin.ctypes.data, sig.ctypes.data, used.ctypes.data)
+                                 n_contrib.ctypes.data, margin.ctypes.data, sig.ctypes.data, used.ctypes.data,
+                                 threads or default_threads())
     assert rc == 0
     return RenderResult(image, T_final, n_contrib, margin, sig, used, proj, lists, cam, tile, tile_select)
 
 
-def composite_backward(rr: RenderResult, dl_dimage: np.ndarray) -> np.ndarray:
+def composite_backward(rr: RenderResult, dl_dimage: np.ndarray, threads: int | None = None) -> np.ndarray:
     """acc9 [n,9]: per-Gaussian dL/d(mean2d x,y, conic A,B,C, opacity, rgb) summed over pixels."""
     n = rr.proj.n
     acc = np.zeros((n, 9))
@@ -165,14 +177,15 @@ def composite_backward(rr: RenderResult, dl_dimage: np.ndarray) -> np.ndarray:
     keep = []
     f = _frame(rr.proj, rr.lists, rr.cam, rr.tile, rr.tile_select, keep)
     longest = int(np.max(np.diff(rr.lists.tile_start))) if rr.lists.tile_start.size > 1 else 1
-    rc = _raster().oracle_backward(ctypes.byref(f), g.ctypes.data, acc.ctypes.data, max(longest, 1))
+    rc = _raster().oracle_backward(ctypes.byref(f), g.ctypes.data, acc.ctypes.data, max(longest, 1),
+                                   threads or default_threads())
     assert rc == 0
     return acc
 
 
-def backward(scene, rr: RenderResult, dl_dimage: np.ndarray):
+def backward(scene, rr: RenderResult, dl_dimage: np.ndarray, threads: int | None = None):
     """Full backward: (acc9, [dL/dmeans3d, dL/dlog_scales, dL/dquats, dL/dopacity_logits, dL/dsh])."""
-    acc = composite_backward(rr, dl_dimage)
+    acc = composite_backward(rr, dl_dimage, threads)
     return acc, params_backward(scene, rr.cam, rr.proj, acc)
 
 

@@ -32,11 +32,18 @@
  *
  * Every value is double. Decision margins are reported per pixel so a caller
  * can tell which pixels sit within rounding of a discrete decision.
+ *
+ * Threads (OpenMP, n_threads >= 1) only split independent work: the forward
+ * takes image rows in parallel; the backward takes whole tiles, each adding
+ * its pixels' contributions into one slot per tile-list entry, and the slots
+ * are then added into the per-Gaussian sums in list order by one thread. The
+ * result does not depend on the number of threads.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <omp.h>
 
 #define ALPHA_MIN (1.0 / 255.0)
 #define ALPHA_MAX 0.99
@@ -129,9 +136,10 @@ static int selected(const oracle_frame *f, int x, int y)
  * (may be NULL): a hash of which entries were composited and whether their
  * alpha was clamped; n_used [H,W] (may be NULL): number of composited entries. Pixels of unselected tiles are left untouched. */
 int oracle_render(const oracle_frame *f, double *image, double *T_final, int32_t *n_contrib, double *margin,
-                  uint64_t *sig, int32_t *n_used)
+                  uint64_t *sig, int32_t *n_used, int n_threads)
 {
     int64_t hw = (int64_t)f->width * f->height;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads > 0 ? n_threads : 1)
     for (int y = 0; y < f->height; ++y)
         for (int x = 0; x < f->width; ++x) {
             if (!selected(f, x, y)) continue;
@@ -147,47 +155,74 @@ int oracle_render(const oracle_frame *f, double *image, double *T_final, int32_t
 
 /* acc [n,9] += per-Gaussian sums of dL/d(mu_x, mu_y, A, B, C, o, r, g, b)
  * given dl_dimage [3,H,W]. `scratch_len` bounds the longest tile list. */
-int oracle_backward(const oracle_frame *f, const double *dl_dimage, double *acc, int64_t scratch_len)
+int oracle_backward(const oracle_frame *f, const double *dl_dimage, double *acc, int64_t scratch_len,
+                    int n_threads)
 {
     int64_t hw = (int64_t)f->width * f->height;
-    entry *ent = (entry *)malloc(sizeof(entry) * (size_t)(scratch_len > 0 ? scratch_len : 1));
-    if (!ent) return -1;
-    for (int y = 0; y < f->height; ++y)
-        for (int x = 0; x < f->width; ++x) {
-            if (!selected(f, x, y)) continue;
-            int64_t p = (int64_t)y * f->width + x;
-            double col[3], Tf, mg;
-            int32_t nc;
-            int64_t n = pixel_forward(f, x, y, ent, col, &Tf, &nc, &mg, NULL);
-            double G[3] = {dl_dimage[p], dl_dimage[hw + p], dl_dimage[2 * hw + p]};
-            /* S = colour behind the current entry, starting with the background. */
-            double S[3] = {Tf * f->bg[0], Tf * f->bg[1], Tf * f->bg[2]};
-            for (int64_t i = n - 1; i >= 0; --i) {
-                const entry *e = &ent[i];
-                const double *c = &f->rgb[3 * e->id];
-                double *a = &acc[9 * (int64_t)e->id];
-                double dL_dalpha = 0.0;
-                for (int ch = 0; ch < 3; ++ch) {
-                    a[6 + ch] += e->alpha * e->T * G[ch];
-                    dL_dalpha += (e->T * c[ch] - S[ch] / (1.0 - e->alpha)) * G[ch];
-                }
-                for (int ch = 0; ch < 3; ++ch) S[ch] += e->alpha * e->T * c[ch];
-                /* alpha = min(0.99, o G): no dependence on o or power when clamped. */
-                if (e->clamped) continue;
-                double o = f->opacity[e->id];
-                a[5] += dL_dalpha * e->G;                 /* dalpha/do = G */
-                double dL_dpower = dL_dalpha * o * e->G;  /* dalpha/dpower = o G */
-                const double *K = &f->conic[3 * e->id];
-                /* d = p - mu, so dpower/dmu = (A dx + B dy, B dx + C dy). */
-                a[0] += dL_dpower * (K[0] * e->dx + K[1] * e->dy);
-                a[1] += dL_dpower * (K[1] * e->dx + K[2] * e->dy);
-                a[2] += dL_dpower * (-0.5 * e->dx * e->dx);
-                a[3] += dL_dpower * (-e->dx * e->dy);
-                a[4] += dL_dpower * (-0.5 * e->dy * e->dy);
-            }
+    int ntiles = f->grid_x * f->grid_y;
+    int64_t P = f->tile_start[ntiles];
+    /* slot[9 k + j]: value j summed over the pixels of the tile that list entry k belongs to */
+    double *slot = (double *)calloc((size_t)(P > 0 ? P : 1) * 9, sizeof(double));
+    if (!slot) return -1;
+    int failed = 0;
+#pragma omp parallel num_threads(n_threads > 0 ? n_threads : 1)
+    {
+        entry *ent = (entry *)malloc(sizeof(entry) * (size_t)(scratch_len > 0 ? scratch_len : 1));
+        if (!ent) {
+#pragma omp atomic write
+            failed = 1;
         }
-    free(ent);
-    return 0;
+#pragma omp for schedule(dynamic, 1)
+        for (int t = 0; t < ntiles; ++t) {
+            if (!ent) continue;
+            if (f->tile_select && !f->tile_select[t]) continue;
+            int64_t beg = f->tile_start[t];
+            int tx = t % f->grid_x, ty = t / f->grid_x;
+            int y1 = (ty + 1) * f->tile < f->height ? (ty + 1) * f->tile : f->height;
+            int x1 = (tx + 1) * f->tile < f->width ? (tx + 1) * f->tile : f->width;
+            for (int y = ty * f->tile; y < y1; ++y)
+                for (int x = tx * f->tile; x < x1; ++x) {
+                    int64_t p = (int64_t)y * f->width + x;
+                    double col[3], Tf, mg;
+                    int32_t nc;
+                    int64_t n = pixel_forward(f, x, y, ent, col, &Tf, &nc, &mg, NULL);
+                    double G[3] = {dl_dimage[p], dl_dimage[hw + p], dl_dimage[2 * hw + p]};
+                    /* S = colour behind the current entry, starting with the background. */
+                    double S[3] = {Tf * f->bg[0], Tf * f->bg[1], Tf * f->bg[2]};
+                    for (int64_t i = n - 1; i >= 0; --i) {
+                        const entry *e = &ent[i];
+                        const double *c = &f->rgb[3 * e->id];
+                        double *a = &slot[9 * (beg + e->pos - 1)];
+                        double dL_dalpha = 0.0;
+                        for (int ch = 0; ch < 3; ++ch) {
+                            a[6 + ch] += e->alpha * e->T * G[ch];
+                            dL_dalpha += (e->T * c[ch] - S[ch] / (1.0 - e->alpha)) * G[ch];
+                        }
+                        for (int ch = 0; ch < 3; ++ch) S[ch] += e->alpha * e->T * c[ch];
+                        /* alpha = min(0.99, o G): no dependence on o or power when clamped. */
+                        if (e->clamped) continue;
+                        double o = f->opacity[e->id];
+                        a[5] += dL_dalpha * e->G;                 /* dalpha/do = G */
+                        double dL_dpower = dL_dalpha * o * e->G;  /* dalpha/dpower = o G */
+                        const double *K = &f->conic[3 * e->id];
+                        /* d = p - mu, so dpower/dmu = (A dx + B dy, B dx + C dy). */
+                        a[0] += dL_dpower * (K[0] * e->dx + K[1] * e->dy);
+                        a[1] += dL_dpower * (K[1] * e->dx + K[2] * e->dy);
+                        a[2] += dL_dpower * (-0.5 * e->dx * e->dx);
+                        a[3] += dL_dpower * (-e->dx * e->dy);
+                        a[4] += dL_dpower * (-0.5 * e->dy * e->dy);
+                    }
+                }
+        }
+        free(ent);
+    }
+    if (!failed)
+        for (int64_t k = 0; k < P; ++k) {
+            double *a = &acc[9 * (int64_t)f->ids[k]];
+            for (int j = 0; j < 9; ++j) a[j] += slot[9 * k + j];
+        }
+    free(slot);
+    return failed ? -1 : 0;
 }
 
 /* Per-pixel list of composited entries (positions and Gaussian ids), for

@@ -149,3 +149,17 @@ def test_tile_select_renders_only_selected_tiles():
             assert np.array_equal(part.image[:, ys, xs], full.image[:, ys, xs])
         else:
             assert (part.image[:, ys, xs] == 0).all()
+
+
+def test_results_do_not_depend_on_the_thread_count():
+    # The per-pixel loops run on OpenMP threads; the split must not change a single bit.
+    wl = sg.tiny_scene(23, 400, 70, 45, sh_degree=1, log_scale=(-2.6, 0.5), half=0.7)
+    cam = wl.camera.with_bg((0.2, 0.1, 0.3))
+    r1 = oracle.render(wl.scene, cam, 16, threads=1)
+    r4 = oracle.render(wl.scene, cam, 16, threads=4)
+    for k in ("image", "T_final", "n_contrib", "margin", "signature"):
+        assert np.array_equal(getattr(r1, k), getattr(r4, k)), k
+    dl = np.random.default_rng(3).standard_normal((3, 45, 70))
+    a1 = oracle.composite_backward(r1, dl, threads=1)
+    a4 = oracle.composite_backward(r4, dl, threads=4)
+    assert np.array_equal(a1, a4)
