@@ -1,22 +1,24 @@
 """Benchmark: 3DGS backward ms/iter, wave-reduce vs plain atomics, on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload object_100k|large_3m]
-                    [--no-large] [--no-batch] [--no-serve] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large_3m|object_100k]
+                    [--no-object] [--no-batch] [--no-serve] [--no-cpu-baseline]
 
 A step is one pass of the whole path over one synthetic view: render
 (projection, binning with the device radix sort, forward composite), the
-workload's loss gradient (L1 + 0.2 D-SSIM for the object scene), and the
-backward (backward composite + per-Gaussian chain rule), inputs already
-resident in HBM. `value` is the backward's milliseconds per iteration
-(backward composite + preprocess backward) in wave-reduce mode at the
-balancing threshold picked by a one-iteration-per-candidate sweep (the
-paper's tuning rule); the plain-atomic backward on the same forward state is
-reported beside it, as are the atomic-count and roofline figures of the
-backward composite kernel and the fp64 oracle timed on the host. Further
-legs: the 3M-Gaussian 1080p view (A/B), the 16-view four-scene batch
-(autotuned, batched vs one view at a time, hipGraph replay) and the served
-request stream (continuous batching vs a sequential plain-atomic server,
-p50/p99 latency and steps/s at several Poisson arrival rates).
+workload's loss gradient (L1 for the 3M-Gaussian 1080p view, L1 + 0.2 D-SSIM
+for the object scene), and the backward (backward composite + per-Gaussian
+chain rule), inputs already resident in HBM. The default view is the large
+one: 3M Gaussians at 1920x1080 with the camera inside the cloud. `value` is
+the backward's milliseconds per iteration (backward composite + preprocess
+backward) in wave-reduce mode at the balancing threshold picked by a
+one-iteration-per-candidate sweep (the paper's tuning rule); the
+plain-atomic backward on the same forward state is reported beside it, as
+are the atomic counts, both backward kernels against their roofs and the
+fp64 oracle timed on the host cores. Further legs: the 100k-Gaussian 800x800
+object view (A/B), the 16-view four-scene batch (autotuned, batched vs one
+view at a time, hipGraph replay) and the served request stream (continuous
+batching vs a sequential plain-atomic server, p50/p99 latency and steps/s at
+several Poisson arrival rates).
 
 Prints exactly one JSON line.
 """
@@ -59,8 +61,8 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--workload", default="object_100k", choices=["object_100k", "large_3m"])
-    p.add_argument("--no-large", action="store_true", help="skip the 3M-Gaussian 1080p A/B")
+    p.add_argument("--workload", default="large_3m", choices=["object_100k", "large_3m"])
+    p.add_argument("--no-object", action="store_true", help="skip the 100k-Gaussian 800x800 A/B leg")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--threshold", type=int, default=None, help="fix the threshold (skip the sweep)")
     p.add_argument("--profile-only", action="store_true", help="only the timed steps (for rocprofv3 runs)")
@@ -74,6 +76,9 @@ def parse():
     p.add_argument("--no-tile-order", action="store_true", help="launch tiles in index order (no longest-first)")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                    help="only run a plain device copy of MIB MiB five times (reference for HBM counters)")
+    p.add_argument("--microbench", default=None, metavar="KIND:MIB",
+                   help="only run one library micro-benchmark (write, read, copy_nt, gather48) over MIB MiB, "
+                        "one untimed and five timed launches (references of known bytes for HBM counters)")
     return p.parse_args()
 
 
@@ -86,7 +91,11 @@ def measure_roofs(ctx):
         ms, ops = gsr.gsr_microbench(ctx, kind, nbytes, reps=5)
         return ops / (ms * 1e-3)
 
-    out = {"hbm_copy_GBs": round(rate(gsr.GSR_MB_COPY, 1024 * mib) / 1e9, 1), "atomic_Gops": {}}
+    out = {"hbm_copy_GBs": round(rate(gsr.GSR_MB_COPY, 1024 * mib) / 1e9, 1),
+           "hbm_copy_nt_GBs": round(rate(gsr.GSR_MB_COPY_NT, 1024 * mib) / 1e9, 1),
+           "hbm_write_GBs": round(rate(gsr.GSR_MB_WRITE, 1024 * mib) / 1e9, 1),
+           "hbm_read_GBs": round(rate(gsr.GSR_MB_READ, 1024 * mib) / 1e9, 1),
+           "gather48_GBs": round(rate(gsr.GSR_MB_GATHER48, 1024 * mib) / 1e9, 1), "atomic_Gops": {}}
     for name, kind, nbytes in [("f32_distinct_2MiB", gsr.GSR_MB_ATOMIC_F32_DISTINCT, 2 * mib),
                                ("f32_distinct_128MiB", gsr.GSR_MB_ATOMIC_F32_DISTINCT, 128 * mib),
                                ("f64_distinct_128MiB", gsr.GSR_MB_ATOMIC_F64_DISTINCT, 128 * mib),
@@ -172,30 +181,6 @@ class Bench:
         cfg = gsr.make_config(16, 256, mode, thr, gsr.GSR_FLAG_DEBUG_COUNTERS | self.extra_flags)
         gsr.gsr_backward(self.r.ctx, fr.state, self.dl, self.gstruct, 0, cfg)
         return gsr.gsr_bwd_counters(self.r.ctx, fr.state)
-
-
-def source_hash():
-    h = hashlib.sha256()
-    for f in ("k_composite.hip", "device_common.hpp"):
-        with open(os.path.join(ROOT, "paper_2401_05345_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
-def measured_counters(kernel_hash, workload):
-    """Per-launch figures of the backward composite from committed rocprofv3 counter runs: HBM
-    bytes (FETCH_SIZE and WRITE_SIZE scaled by the copy calibration) and the VALU issue fraction
-    (SQ_INSTS_VALU x 4 cycles over the SIMD cycles of the traced launch); {} when the kernel
-    changed since they were taken."""
-    path = os.path.join(ROOT, "profiles", "composite_bwd_traffic.json")
-    if not os.path.exists(path):
-        return {}
-    with open(path) as f:
-        d = json.load(f)
-    if d.get("kernel_source_hash") != kernel_hash:
-        return {}
-    key = "object" if workload.startswith("object") else "large"
-    return d.get("workloads", {}).get(key) or {}
 
 
 def timed_ms(torch, fn, reps):
@@ -370,22 +355,175 @@ def bench_serving(flags, seconds):
     return out
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(wl):
-    """The fp64 oracle's backward (composite C loop + autograd chain rule) for the full view,
-    single-threaded, on the host cores of this machine."""
+    """The fp64 oracle on the host cores, on the workload's view: its forward composite and its
+    backward (composite C loop + autograd chain rule), once on one thread and once on all the
+    threads this process may use (OpenMP in the per-pixel loops, torch threads in the chain
+    rule). The projection and tile lists that both consume are built once, untimed."""
     import torch
     import oracle
-    torch.set_num_threads(1)
-    rr = oracle.render(wl.scene, wl.camera)
-    target = oracle.render(wl.perturbed, wl.camera).image if wl.perturbed is not None else wl.target
-    _, dl = oracle.loss_and_grad(rr.image, target, wl.loss)
-    t0 = time.perf_counter()
-    oracle.backward(wl.scene, rr, dl)
-    dt = time.perf_counter() - t0
-    return {"value": round(dt * 1000.0, 1), "unit": "ms", "cores": 1, "kind": "oracle",
-            "sample": f"full backward of one {wl.camera.width}x{wl.camera.height} view of {wl.scene.n} Gaussians "
-                      f"(fp64 composite backward + fp64 autograd chain rule, 1 thread)",
-            "host_cpus": os.cpu_count()}
+    from oracle.composite import default_threads
+    nthr = default_threads()
+    out = {"kind": "oracle", "unit": "ms", "cpu_model": _cpu_model(), "host_cpus": os.cpu_count()}
+    target = None
+    for label, threads in (("single", 1), ("all", nthr)):
+        torch.set_num_threads(threads)
+        t0 = time.perf_counter()
+        rr = oracle.render(wl.scene, wl.camera, threads=threads)
+        t_fwd = time.perf_counter() - t0
+        if target is None:
+            target = oracle.render(wl.perturbed, wl.camera, threads=nthr).image if wl.perturbed is not None \
+                else wl.target
+            _, dl = oracle.loss_and_grad(rr.image, target, wl.loss)
+        t0 = time.perf_counter()
+        oracle.backward(wl.scene, rr, dl, threads=threads)
+        t_bwd = time.perf_counter() - t0
+        out[label] = {"threads": threads, "render_ms": round(t_fwd * 1000.0, 1),
+                      "backward_ms": round(t_bwd * 1000.0, 1)}
+        log(f"[bench] cpu baseline ({threads} threads): render {t_fwd:.2f} s, backward {t_bwd:.2f} s")
+    out["value"] = out["all"]["backward_ms"]
+    out["cores"] = nthr
+    out["sample"] = (f"full backward of one {wl.camera.width}x{wl.camera.height} view of {wl.scene.n} Gaussians "
+                     f"(fp64 composite backward in C + fp64 autograd chain rule) on {nthr} threads; the "
+                     f"1-thread run and the fp64 forward composite (render, projection included) beside it")
+    return out
+
+
+def kernel_counters(kernel: str, workload: str):
+    """Per-launch figures of one kernel from the committed rocprofv3 counter runs: HBM bytes
+    (FETCH_SIZE and WRITE_SIZE scaled by the copy calibration) and, where taken, the VALU issue
+    fraction; {} when the kernel's source changed since they were taken."""
+    path = os.path.join(ROOT, "profiles", "kernel_counters.json")
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        d = json.load(f).get(kernel)
+    if not d or d.get("source_hash") != source_hash(KERNEL_SOURCES[kernel]):
+        return {}
+    return d.get("workloads", {}).get(workload) or {}
+
+
+# Sources whose text decides each measured kernel's code (the counter runs are tied to them).
+KERNEL_SOURCES = {"composite_bwd": ("k_composite.hip", "device_common.hpp"),
+                  "preprocess_bwd": ("k_preprocess.hip", "device_common.hpp")}
+
+
+def source_hash(files=("k_composite.hip", "device_common.hpp")):
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_2401_05345_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def ab_legs(b, thr, iters, full=True):
+    """Backward A/B on one forward state: the plain-atomic kernel with fp32 accumulators (the
+    paper's baseline), the same with fp64 accumulators, and the wave-reduced kernel with both;
+    with `full`, the serial-leader and block-level reductions too. Medians in ms."""
+    gsr = b.gsr
+    F32 = gsr.GSR_FLAG_ACC_F32
+    fr = b.forward_state(b.cfg(gsr.GSR_BWD_WAVE_REDUCE, thr))
+    res = {}
+    legs = [("reduce_f64", gsr.GSR_BWD_WAVE_REDUCE, thr, 0, iters),
+            ("reduce_f32", gsr.GSR_BWD_WAVE_REDUCE, thr, F32, iters),
+            ("plain_f32", gsr.GSR_BWD_PLAIN_ATOMIC, 0, F32, max(3, iters // 4)),
+            ("plain_f64", gsr.GSR_BWD_PLAIN_ATOMIC, 0, 0, max(3, iters // 4))]
+    if full:
+        legs += [("serial_f64", gsr.GSR_BWD_SERIAL_REDUCE, thr, 0, iters),
+                 ("block_f64", gsr.GSR_BWD_BLOCK_REDUCE, thr, 0, iters)]
+    for name, mode, t, flags, n in legs:
+        a6, a7 = b.backward_only(fr, b.cfg(mode, t, flags), n)
+        res[name] = (float(np.median(a6)), float(np.median(a7)))
+    cnt = {"plain": b.counters(fr, gsr.GSR_BWD_PLAIN_ATOMIC, 0), "reduce": b.counters(fr, gsr.GSR_BWD_WAVE_REDUCE, thr)}
+    if full:
+        cnt["block"] = b.counters(fr, gsr.GSR_BWD_BLOCK_REDUCE, thr)
+    stats = fr.stats
+    b.r.release(fr)
+    return res, cnt, stats
+
+
+def ab_summary(res, cnt, stats, thr, sweep):
+    r6, r7 = res["reduce_f64"]
+    p6, p7 = res["plain_f32"]
+    q6, q7 = res["plain_f64"]
+    w6, w7 = res["reduce_f32"]
+    cp, cr = cnt["plain"], cnt["reduce"]
+    out = {
+        "n_pairs": int(stats.n_pairs), "n_visible": int(stats.n_visible), "threshold": thr,
+        "wave_reduce_ms": round(r6 + r7, 4),
+        "plain_atomic_ms": round(p6 + p7, 4),
+        "plain_atomic_f64_ms": round(q6 + q7, 4),
+        "wave_reduce_acc_f32_ms": round(w6 + w7, 4),
+        "composite_bwd_wave_reduce_ms": round(r6, 4),
+        "preprocess_bwd_ms": round(r7, 4),
+        "composite_bwd_plain_ms": round(p6, 4),
+        "speedup_composite_bwd": round(p6 / r6, 3),
+        "speedup_composite_bwd_both_f32": round(p6 / w6, 3),
+        "speedup_composite_bwd_both_f64": round(q6 / r6, 3),
+        "lane_atomics_plain": int(cp.lane_atomics), "lane_atomics_reduce": int(cr.lane_atomics),
+        "atomic_instrs_plain": int(cp.atomic_instrs), "atomic_instrs_reduce": int(cr.atomic_instrs),
+        "evaluated_E": int(cr.evaluated), "active_A": int(cr.active), "wave_entries": int(cr.wave_entries),
+        "visited_wave_entries": int(cr.visited), "longest_wave_walk": int(cr.max_wave_visits),
+        "reduced_W_R": int(cr.reduced), "plain_lanes_A_lt": int(cr.plain_lanes),
+        "threshold_sweep_ms": sweep,
+        "accumulator_note": ("fp64 accumulators (default) meet the 1e-3 gradient tolerance against the oracle; "
+                             "fp32 accumulators (the paper's setting, both *_acc_f32 / plain_atomic legs) add "
+                             "each value in an order the atomics decide, and on views with screen-filling "
+                             "splats (3M/1080p) their run-to-run spread exceeds 1e-3: outside parity there"),
+    }
+    if "serial_f64" in res:
+        out["composite_bwd_by_mode_ms"] = {
+            "f64_accumulators": {"wave_reduce": round(r6, 4), "serial_leader": round(res["serial_f64"][0], 4),
+                                 "block_lds": round(res["block_f64"][0], 4), "plain_atomic": round(q6, 4)},
+            "f32_accumulators": {"wave_reduce": round(w6, 4), "plain_atomic": round(p6, 4)}}
+        out["lane_atomics_block_lds"] = int(cnt["block"].lane_atomics)
+        out["atomic_instrs_block_lds"] = int(cnt["block"].atomic_instrs)
+    return out
+
+
+def rooflines(wl, stats, cr, a6_ms, a7_ms):
+    """Both backward kernels against their roofs, from the live event timings: the composite
+    (a6) against the fp32 vector peak, the per-Gaussian chain rule (a7) against HBM."""
+    hw = wl.camera.width * wl.camera.height
+    n, n_vis = wl.scene.n, int(stats.n_visible)
+    K3 = 3 * (wl.scene.sh_degree + 1) ** 2
+    flops = FLOPS_PER_EVAL * cr.evaluated + FLOPS_PER_CONTRIB * cr.active
+    a6_tflops = flops / (a6_ms * 1e-3) / 1e12
+    a6_bytes = BYTES_PER_PIXEL * hw + BYTES_PER_VISIBLE * n_vis + BYTES_PER_RECORD * int(stats.n_pairs)
+    a6 = {"bound": "alu", "achieved": round(a6_tflops, 3), "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
+          "frac": round(a6_tflops / PEAK_FP32_VALU_TFLOPS, 4), "kernel": "composite_bwd_kernel<16,256,wave_reduce>",
+          "ms": round(a6_ms, 4), "algorithmic_flops": int(flops),
+          "hbm_GBs_algorithmic": round(a6_bytes / (a6_ms * 1e-3) / 1e9, 1),
+          "hbm_frac_algorithmic": round(a6_bytes / (a6_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+    m6 = kernel_counters("composite_bwd", wl.name)
+    a6["traffic"] = m6.get("bytes_per_launch")
+    if "valu_issue_frac" in m6:
+        a6["valu_issue_frac"] = m6["valu_issue_frac"]
+    # a7: reads radius (4 B) of every Gaussian and, for the visible ones, the parameters and the nine
+    # fp64 accumulator sums; writes every Gaussian's gradient row (zeros for culled ones).
+    pbytes = 4 * (11 + K3)
+    a7_bytes = n * (4 + pbytes) + n_vis * (pbytes + 72)
+    a7_gbs = a7_bytes / (a7_ms * 1e-3) / 1e9
+    a7 = {"bound": "hbm", "achieved": round(a7_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+          "frac": round(a7_gbs / PEAK_HBM_GBS, 4), "kernel": f"preprocess_bwd_kernel<{wl.scene.sh_degree},double>",
+          "ms": round(a7_ms, 4), "algorithmic_bytes": int(a7_bytes)}
+    m7 = kernel_counters("preprocess_bwd", wl.name)
+    a7["traffic"] = m7.get("bytes_per_launch")
+    dom, other = (a7, a6) if a7_ms >= a6_ms else (a6, a7)
+    line = dict(dom)
+    line["other_backward_kernel"] = other
+    return line
 
 
 def main():
@@ -408,6 +546,16 @@ def main():
         print(json.dumps({"copy_calibration_bytes": n * 4, "launches": 5}))
         return
     gsr.load()
+    if args.microbench:
+        kind, mib = args.microbench.split(":")
+        kinds = {"write": gsr.GSR_MB_WRITE, "read": gsr.GSR_MB_READ, "copy_nt": gsr.GSR_MB_COPY_NT,
+                 "gather48": gsr.GSR_MB_GATHER48, "copy": gsr.GSR_MB_COPY}
+        r = gsr.Renderer(0)
+        ms, ops = gsr.gsr_microbench(r.ctx, kinds[kind], int(mib) << 20, reps=5)
+        r.close()
+        print(json.dumps({"microbench": kind, "bytes": int(mib) << 20, "bytes_per_launch": ops, "ms": ms,
+                          "GBs": round(ops / ms / 1e6, 1), "launches": 6}))
+        return
 
     wl = sg.WORKLOADS[args.workload]()
     log(f"[bench] workload {wl.name}: {wl.scene.n} Gaussians, {wl.camera.width}x{wl.camera.height}")
@@ -450,42 +598,12 @@ def main():
         return
 
     # A/B on one forward state: plain atomics vs wave reduce, same inputs.
-    fr = b.forward_state(cfg_r)
-    iters = max(10, args.steps)
-    F32 = gsr.GSR_FLAG_ACC_F32
-    # plain atomics with fp32 accumulators: the paper's baseline
-    p6, p7 = b.backward_only(fr, b.cfg(gsr.GSR_BWD_PLAIN_ATOMIC, 0, F32), iters)
-    r6, r7 = b.backward_only(fr, cfg_r, iters)
-    w6, w7 = b.backward_only(fr, b.cfg(gsr.GSR_BWD_WAVE_REDUCE, thr, F32), iters)
-    s6, _ = b.backward_only(fr, b.cfg(gsr.GSR_BWD_SERIAL_REDUCE, thr), iters)
-    k6, _ = b.backward_only(fr, b.cfg(gsr.GSR_BWD_BLOCK_REDUCE, thr), iters)
-    q6, _ = b.backward_only(fr, b.cfg(gsr.GSR_BWD_PLAIN_ATOMIC, 0), max(3, iters // 4))
-    cp = b.counters(fr, gsr.GSR_BWD_PLAIN_ATOMIC, 0)
-    cr = b.counters(fr, gsr.GSR_BWD_WAVE_REDUCE, thr)
-    ck = b.counters(fr, gsr.GSR_BWD_BLOCK_REDUCE, thr)
-    b.r.release(fr)
-    log(f"[bench] A/B a6: plain {np.median(p6):.3f} ms, reduce {np.median(r6):.3f} ms")
-
-    n_vis = int(stats.n_visible)
-    a6_ms = float(np.median(r6))
-    flops = FLOPS_PER_EVAL * cr.evaluated + FLOPS_PER_CONTRIB * cr.active
-    achieved_tflops = flops / (a6_ms * 1e-3) / 1e12
-    # Walked records: each wave reads every entry up to its block's deepest pixel once from LDS; the
-    # HBM-side minimum is one record per (tile, entry) walked.
-    walked_entries = None
-    hw = wl.camera.width * wl.camera.height
-    alg_bytes = BYTES_PER_PIXEL * hw + BYTES_PER_VISIBLE * n_vis + BYTES_PER_RECORD * int(stats.n_pairs)
-    khash = source_hash()
-    measured = measured_counters(khash, wl.name)
-    traffic = measured.get("bytes_per_launch")
-    roofline = {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": PEAK_FP32_VALU_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_FP32_VALU_TFLOPS, 4),
-                "traffic": traffic, "kernel": "composite_bwd_kernel<16,256,wave_reduce>",
-                "algorithmic_flops": int(flops), "hbm_GBs_algorithmic": round(alg_bytes / (a6_ms * 1e-3) / 1e9, 1),
-                "hbm_frac_algorithmic": round(alg_bytes / (a6_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
-                "kernel_source_hash": khash}
-    if "valu_issue_frac" in measured:
-        roofline["valu_issue_frac"] = measured["valu_issue_frac"]
+    res, cnt, fstats = ab_legs(b, thr, max(10, args.steps))
+    backward = ab_summary(res, cnt, fstats, thr, sweep)
+    backward["p50_backward_ms"] = round(float(np.percentile(bwd, 50)), 4)
+    backward["p99_backward_ms"] = round(float(np.percentile(bwd, 99)), 4)
+    log(f"[bench] A/B a6: plain {res['plain_f32'][0]:.3f} ms, reduce {res['reduce_f64'][0]:.3f} ms")
+    roofline = rooflines(wl, fstats, cnt["reduce"], res["reduce_f64"][0], res["reduce_f64"][1])
 
     out = {
         "metric": "3DGS backward ms/iter + TCC atomics, wave-reduce vs plain atomics; p99 step lat",
@@ -503,35 +621,9 @@ def main():
         "config": {"workload": wl.name, "n_gaussians": wl.scene.n, "width": wl.camera.width,
                    "height": wl.camera.height, "sh_degree": wl.scene.sh_degree, "tile": 16, "lds_batch": 256,
                    "bwd_mode": "wave_reduce", "reduce_threshold": thr, "accumulators": "f64",
-                   "n_pairs": int(stats.n_pairs),
-                   "n_visible": n_vis},
+                   "loss": wl.loss, "n_pairs": int(stats.n_pairs), "n_visible": int(stats.n_visible)},
         "roofline": roofline,
-        "backward": {
-            "wave_reduce_ms": round(float(np.median(r6) + np.median(r7)), 4),
-            "plain_atomic_ms": round(float(np.median(p6) + np.median(p7)), 4),
-            "wave_reduce_acc_f32_ms": round(float(np.median(w6) + np.median(w7)), 4),
-            "composite_bwd_wave_reduce_ms": round(float(np.median(r6)), 4),
-            "composite_bwd_plain_ms": round(float(np.median(p6)), 4),
-            "speedup_composite_bwd": round(float(np.median(p6) / np.median(r6)), 3),
-            "speedup_composite_bwd_both_f32": round(float(np.median(p6) / np.median(w6)), 3),
-            "speedup_composite_bwd_both_f64": round(float(np.median(q6) / np.median(r6)), 3),
-            "p50_backward_ms": round(float(np.percentile(bwd, 50)), 4),
-            "p99_backward_ms": round(float(np.percentile(bwd, 99)), 4),
-            "lane_atomics_plain": int(cp.lane_atomics), "lane_atomics_reduce": int(cr.lane_atomics),
-            "atomic_instrs_plain": int(cp.atomic_instrs), "atomic_instrs_reduce": int(cr.atomic_instrs),
-            "evaluated_E": int(cr.evaluated), "active_A": int(cr.active), "wave_entries": int(cr.wave_entries),
-            "visited_wave_entries": int(cr.visited), "longest_wave_walk": int(cr.max_wave_visits),
-            "reduced_W_R": int(cr.reduced), "plain_lanes_A_lt": int(cr.plain_lanes),
-            "threshold_sweep_ms": sweep,
-            "composite_bwd_by_mode_ms": {
-                "f64_accumulators": {"wave_reduce": round(float(np.median(r6)), 4),
-                                     "serial_leader": round(float(np.median(s6)), 4),
-                                     "block_lds": round(float(np.median(k6)), 4),
-                                     "plain_atomic": round(float(np.median(q6)), 4)},
-                "f32_accumulators": {"wave_reduce": round(float(np.median(w6)), 4),
-                                     "plain_atomic": round(float(np.median(p6)), 4)}},
-            "lane_atomics_block_lds": int(ck.lane_atomics), "atomic_instrs_block_lds": int(ck.atomic_instrs),
-        },
+        "backward": backward,
         "forward_ms": round(float(fwd.mean()), 4),
         "forward_stages_ms": {k: round(float(np.mean([getattr(s, k) for s in per])), 4)
                               for k in ("preprocess", "depth_sort", "scan_emit", "tile_sort", "ranges",
@@ -539,64 +631,63 @@ def main():
         "p99_step_ms": None,
     }
 
-    # Measured roofs (micro-benchmarks of the kernel's memory patterns) and a6 against them.
-    if not args.profile_only:
-        try:
-            roofs = measure_roofs(b.r.ctx)
-            out["roofs"] = roofs
-            plain_rate = cp.lane_atomics / (float(np.median(p6)) * 1e-3)
-            red_rate = cr.lane_atomics / (float(np.median(r6)) * 1e-3)
-            out["backward"]["atomic_roofline"] = {
-                "plain": {"pattern": "f32_same_address_16MiB", "achieved_lane_ops_s": round(plain_rate / 1e9, 3),
-                          "peak_lane_ops_s": roofs["atomic_Gops"]["f32_same_address_16MiB"],
-                          "frac": round(plain_rate / 1e9 / roofs["atomic_Gops"]["f32_same_address_16MiB"], 4),
-                          "unit": "G lane-ops/s"},
-                "wave_reduce": {"pattern": "f64_nine_lanes_16MiB", "achieved_lane_ops_s": round(red_rate / 1e9, 3),
-                                "peak_lane_ops_s": roofs["atomic_Gops"]["f64_nine_lanes_16MiB"],
-                                "frac": round(red_rate / 1e9 / roofs["atomic_Gops"]["f64_nine_lanes_16MiB"], 4),
-                                "unit": "G lane-ops/s"}}
-            roofline["hbm_frac_measured_peak"] = round(roofline["hbm_GBs_algorithmic"] / roofs["hbm_copy_GBs"], 4)
-        except Exception as e:  # noqa: BLE001
-            log(f"[bench] roof micro-benchmarks failed: {e!r}")
-            out["roofs"] = {"error": repr(e)}
+    # Measured roofs (micro-benchmarks of the kernels' memory patterns) and a6 against them.
+    try:
+        roofs = measure_roofs(b.r.ctx)
+        out["roofs"] = roofs
+        cp, cr = cnt["plain"], cnt["reduce"]
+        plain_rate = cp.lane_atomics / (res["plain_f32"][0] * 1e-3)
+        red_rate = cr.lane_atomics / (res["reduce_f64"][0] * 1e-3)
+        out["backward"]["atomic_roofline"] = {
+            "plain": {"pattern": "f32_same_address_16MiB", "achieved_lane_ops_s": round(plain_rate / 1e9, 3),
+                      "peak_lane_ops_s": roofs["atomic_Gops"]["f32_same_address_16MiB"],
+                      "frac": round(plain_rate / 1e9 / roofs["atomic_Gops"]["f32_same_address_16MiB"], 4),
+                      "unit": "G lane-ops/s"},
+            "wave_reduce": {"pattern": "f64_nine_lanes_16MiB", "achieved_lane_ops_s": round(red_rate / 1e9, 3),
+                            "peak_lane_ops_s": roofs["atomic_Gops"]["f64_nine_lanes_16MiB"],
+                            "frac": round(red_rate / 1e9 / roofs["atomic_Gops"]["f64_nine_lanes_16MiB"], 4),
+                            "unit": "G lane-ops/s"}}
+        if roofline["unit"] == "GB/s":
+            roofline["frac_of_measured_write_roof"] = round(roofline["achieved"] / roofs["hbm_write_GBs"], 4)
+    except Exception as e:  # noqa: BLE001
+        log(f"[bench] roof micro-benchmarks failed: {e!r}")
+        out["roofs"] = {"error": repr(e)}
+    b.r.close()
 
-    if not args.no_large and args.workload != "large_3m":
-        wl3 = sg.large_3m()
-        log(f"[bench] A/B at {wl3.name}")
-        b3 = Bench(wl3)
-        fr3 = b3.forward_state(b3.cfg(gsr.GSR_BWD_WAVE_REDUCE, 32))
-        s3 = b3.sweep(fr3, iters=2)
-        thr3 = min(s3, key=s3.get)
-        p6, p7 = b3.backward_only(fr3, b3.cfg(gsr.GSR_BWD_PLAIN_ATOMIC, 0, gsr.GSR_FLAG_ACC_F32), 5)
-        w6, w7 = b3.backward_only(fr3, b3.cfg(gsr.GSR_BWD_WAVE_REDUCE, 2, gsr.GSR_FLAG_ACC_F32), 5)
-        r6, r7 = b3.backward_only(fr3, b3.cfg(gsr.GSR_BWD_WAVE_REDUCE, thr3), 5)
-        c3 = b3.counters(fr3, gsr.GSR_BWD_WAVE_REDUCE, thr3)
-        c3p = b3.counters(fr3, gsr.GSR_BWD_PLAIN_ATOMIC, 0)
-        out["large_3m_1080p"] = {
-            "n_pairs": int(fr3.stats.n_pairs), "n_visible": int(fr3.stats.n_visible), "threshold": thr3,
-            "wave_reduce_bwd_ms": round(float(np.median(r6) + np.median(r7)), 4),
-            "plain_atomic_bwd_ms": round(float(np.median(p6) + np.median(p7)), 4),
-            "composite_bwd_wave_reduce_ms": round(float(np.median(r6)), 4),
-            "composite_bwd_plain_ms": round(float(np.median(p6)), 4),
-            "speedup_composite_bwd": round(float(np.median(p6) / np.median(r6)), 3),
-            "wave_reduce_acc_f32_bwd_ms": round(float(np.median(w6) + np.median(w7)), 4),
-            "lane_atomics_plain": int(c3p.lane_atomics), "lane_atomics_reduce": int(c3.lane_atomics),
-            "wave_entries": int(c3.wave_entries), "visited_wave_entries": int(c3.visited),
-            "longest_wave_walk": int(c3.max_wave_visits),
-            "threshold_sweep_ms": s3,
-        }
-        b3.r.release(fr3)
-        b3.r.close()
+    # The object-centred 100k-Gaussian 800x800 view: the same A/B as an extra leg.
+    if not args.no_object and args.workload != "object_100k":
+        wl2 = sg.object_100k()
+        log(f"[bench] A/B at {wl2.name}")
+        b2 = Bench(wl2)
+        fr2 = b2.forward_state(b2.cfg(gsr.GSR_BWD_WAVE_REDUCE, 32))
+        s2 = b2.sweep(fr2, iters=2)
+        thr2 = min(s2, key=s2.get)
+        b2.r.release(fr2)
+        per2 = []
+        for k in range(13):
+            st2, _ = b2.step(b2.cfg(gsr.GSR_BWD_WAVE_REDUCE, thr2))
+            if k >= 3:
+                per2.append(st2)
+        res2, cnt2, stats2 = ab_legs(b2, thr2, 10)
+        leg = ab_summary(res2, cnt2, stats2, thr2, s2)
+        leg["roofline"] = rooflines(wl2, stats2, cnt2["reduce"], res2["reduce_f64"][0], res2["reduce_f64"][1])
+        leg["step_render_ms"] = round(float(np.mean([s.preprocess + s.depth_sort + s.scan_emit + s.tile_sort +
+                                                     s.ranges + s.composite_fwd for s in per2])), 4)
+        leg["forward_stages_ms"] = {k: round(float(np.mean([getattr(s, k) for s in per2])), 4)
+                                    for k in ("preprocess", "depth_sort", "scan_emit", "tile_sort", "ranges",
+                                              "composite_fwd")}
+        out[wl2.name] = leg
+        b2.r.close()
 
     # The extra legs report their own failure instead of losing the line.
-    if not args.no_batch and not args.profile_only:
+    if not args.no_batch:
         try:
             out["multi_view_16"] = bench_multi_view(Bench.extra_flags)
         except Exception as e:  # noqa: BLE001
             log(f"[bench] multi-view leg failed: {e!r}")
             out["multi_view_16"] = {"error": repr(e)}
 
-    if not args.no_serve and not args.profile_only:
+    if not args.no_serve:
         try:
             out["serving"] = bench_serving(Bench.extra_flags, args.serve_seconds)
             out["p99_step_ms"] = out["serving"]["rates"]["200"]["batched_reduce"]["p99_ms"]
@@ -607,7 +698,6 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(wl)
-    b.r.close()
     print(json.dumps(out), flush=True)
 
 

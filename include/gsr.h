@@ -208,6 +208,11 @@ gsr_status gsr_ctx_set_stream(gsr_ctx *ctx, void *hip_stream);
 
 /* Forward pass (3DGS rasterisation: per-Gaussian projection, tile binning
  * with a device radix sort on (tile, depth), front-to-back composite).
+ * Defined by: the rendering of the primitives into a 2D image (Background,
+ * "Differentiable Rendering for Rasterization Pipelines", steps 1-2 of the
+ * rasterisation pipeline figure; the forward pass of the training pipeline
+ * figure), which also produces the per-pixel primitive lists the gradient
+ * kernel consumes (Motivation, "Atomic Reduction Bottleneck").
  * image_chw [3,H,W] is written. *state_out receives a library-owned state
  * holding the projected Gaussians, the sorted lists, per-tile ranges and
  * per-pixel T_final / n_contrib; it borrows the scene's arrays, which must
@@ -220,7 +225,14 @@ gsr_status gsr_render(gsr_ctx *ctx, const gsr_scene *scene, const gsr_camera *ca
 /* Backward pass for a forward state: walks every tile list in reverse,
  * accumulates the nine per-Gaussian gradients (2D mean, conic, opacity,
  * colour) with the configured reduction mode, then turns them into
- * gradients of the raw parameters. dl_dimage_chw [3,H,W]. out: caller-owned
+ * gradients of the raw parameters. Defined by: the loss backpropagated to
+ * the gradients of every parameter of each primitive that influences the
+ * image (Background, rasterisation pipeline figure, steps 4-6). The
+ * accumulation is the gradient computation kernel (Motivation, "Atomic
+ * Reduction Bottleneck": one thread per pixel walks its list, conditions
+ * decide participation, participants add atomically); the wave reduction
+ * and its balancing threshold are Approach, "Key Components" (butterfly
+ * reduction; scheduling between core and L2) and Detailed Design (SW-B). dl_dimage_chw [3,H,W]. out: caller-owned
  * gradients; accumulate = 0 overwrites, 1 adds. Culled Gaussians get 0 (or
  * keep their value when accumulating). May be called several times per
  * state, with any mode/threshold in `config` (NULL = the render config). */
@@ -228,18 +240,27 @@ gsr_status gsr_backward(gsr_ctx *ctx, gsr_fwd *state, const float *dl_dimage_chw
                         const gsr_grads *out, int accumulate, const gsr_config *config);
 
 /* Only the composite part of the backward: fills the state's accumulators
- * (exported as `acc`). Same arguments as gsr_backward. */
+ * (exported as `acc`). Same arguments as gsr_backward. Defined by: the
+ * gradient computation kernel alone (Motivation, "Atomic Reduction
+ * Bottleneck"), the step the paper measures. */
 gsr_status gsr_backward_composite(gsr_ctx *ctx, gsr_fwd *state, const float *dl_dimage_chw,
                                   const gsr_config *config);
 
 /* Only the per-Gaussian part: raw-parameter gradients from the state's
- * accumulators of the last gsr_backward_composite. */
+ * accumulators of the last gsr_backward_composite. Defined by: step 6 of the
+ * rasterisation pipeline figure (gradients for all the parameters of each
+ * primitive), through the 3D Gaussian Splatting projection. Writes every
+ * Gaussian's rows of the five outputs (zeros for culled Gaussians when
+ * accumulate = 0); outputs need no alignment (16-byte aligned ones are
+ * written with wider stores). */
 gsr_status gsr_backward_params(gsr_ctx *ctx, gsr_fwd *state, const gsr_grads *out, int accumulate);
 
 /* Most views one batched call takes. */
 #define GSR_MAX_BATCH 16
 
-/* Forward pass over n_views (1..GSR_MAX_BATCH) views at once: scenes[i] seen
+/* Forward pass over n_views (1..GSR_MAX_BATCH) views at once (the training
+ * loop repeats the forward pass for images from different view points:
+ * Background, "Differentiable Rendering for 3D Scene Reconstruction"): scenes[i] seen
  * by cameras[i] into images_chw[i] [3,H_i,W_i], states_out[i] receiving view
  * i's state (as gsr_render). Views may share a scene and may differ in
  * resolution and Gaussian count; one config (tile, LDS batch, flags) serves
@@ -289,7 +310,9 @@ gsr_status gsr_graph_launch(gsr_ctx *ctx, gsr_graph *graph);
 void gsr_graph_destroy(gsr_ctx *ctx, gsr_graph *graph);
 
 /* Autotuner (the paper's rule: time one gradient-kernel iteration per
- * candidate, keep the fastest, repeat periodically). Candidates are every
+ * candidate, keep the fastest, repeat periodically; Detailed Design,
+ * "Determining Balancing Threshold", and Approach, the balancing threshold
+ * as a hyperparameter tuned per workload). Candidates are every
  * valid (tile, lds_batch) pair of the space (lds_batch <= tile*tile) times
  * every threshold; each is timed as one batched render plus one batched
  * backward of the given views with HIP events (median of `reps` runs), with
@@ -470,7 +493,9 @@ gsr_status gsr_bwd_counters(gsr_ctx *ctx, const gsr_fwd *state, gsr_bwd_counters
  * (synchronises on the events). */
 gsr_status gsr_ctx_stage_times(gsr_ctx *ctx, gsr_stage_times_t *out);
 
-/* L1 loss gradient (harness step, outside the timed backward):
+/* L1 loss gradient (harness step, outside the timed backward; the loss as
+ * the difference of rendered and reference RGB values, Background, "3D Scene
+ * Reconstruction"):
  * dl_dimage = sign(image - target) / count over `count` floats, sign(0) = 0. */
 gsr_status gsr_l1_grad(gsr_ctx *ctx, const float *image, const float *target, int64_t count, float *dl_dimage);
 
@@ -484,7 +509,9 @@ gsr_status gsr_l1_grad(gsr_ctx *ctx, const float *image, const float *target, in
 gsr_status gsr_l1_dssim_grad(gsr_ctx *ctx, const float *image, const float *target, int32_t height, int32_t width,
                              float lambda, float *dl_dimage, float *loss);
 
-/* Run the per-wave reduce-or-atomic primitive on synthetic data: wave w,
+/* The paper's primitive exposed as a callable (Approach, "Key Components":
+ * SW-B is a function call inserted in GPU code). Runs the per-wave
+ * reduce-or-atomic primitive on synthetic data: wave w,
  * lane l contributes vals[(w*64+l)*9 + k] to sums[k] (k < 9) when
  * active[w*64+l] != 0. mode (plain, wave or serial reduce; not block) and
  * threshold as in gsr_config. lane_atomics[0]
@@ -510,8 +537,17 @@ gsr_status gsr_wave_reduce_selftest(gsr_ctx *ctx, const float *vals, const uint8
  *                                 per instruction; ops = lane-ops)
  *   GSR_MB_ATOMIC_F64_NINE_LANES  lanes 0..8 add to nine consecutive doubles
  *                                 (the reduced kernel's nine-lane issue)
+ *   GSR_MB_WRITE                  non-temporal 16-byte stores over `bytes`
+ *                                 (ops = bytes written)
+ *   GSR_MB_READ                   16-byte loads over `bytes` less 16
+ *                                 (ops = bytes read)
+ *   GSR_MB_COPY_NT                as GSR_MB_COPY with non-temporal loads and
+ *                                 stores, eight 16-byte chunks in flight
+ *   GSR_MB_GATHER48               every 48-byte record of the largest power
+ *                                 of two of them that fits read once, in a
+ *                                 scattered (permuted) order (ops = bytes read)
  * The atomic patterns sweep a working set of `bytes` (128-byte slots for the
- * last three) with 8192 workgroups of 256 threads, 64 operations each.
+ * last three of them) with 8192 workgroups of 256 threads, 64 operations each.
  * bytes: a power of two in [1 MiB, 4 GiB], allocated and cleared by the call
  * from the context's pool. Runs one untimed launch, then `reps` (1..100)
  * timed ones on the context's stream and synchronises; ms_per_launch and
@@ -523,7 +559,11 @@ enum {
     GSR_MB_ATOMIC_F64_DISTINCT = 2,
     GSR_MB_ATOMIC_F32_SAME_ADDRESS = 3,
     GSR_MB_ATOMIC_F32_ONE_LANE = 4,
-    GSR_MB_ATOMIC_F64_NINE_LANES = 5
+    GSR_MB_ATOMIC_F64_NINE_LANES = 5,
+    GSR_MB_WRITE = 6,
+    GSR_MB_READ = 7,
+    GSR_MB_COPY_NT = 8,
+    GSR_MB_GATHER48 = 9
 };
 gsr_status gsr_microbench(gsr_ctx *ctx, int32_t kind, int64_t bytes, int32_t reps, double *ms_per_launch,
                           double *ops_per_launch);

@@ -1,7 +1,10 @@
-// Micro-benchmarks of the memory operations the backward composite is made
-// of, to measure the roofs it is held against on this GPU: a streaming copy
-// (HBM bandwidth) and no-return atomic adds in the access patterns of the
-// plain and the reduced kernels (the atomic rate of the L2/fabric). Every
+// Micro-benchmarks of the memory operations the backward is made of, to
+// measure the roofs it is held against on this GPU: streaming copies, a
+// write-only and a read-only stream (HBM bandwidth), a gather of 48-byte
+// records (the composite kernels' record reads, also a reference of known
+// bytes for the hardware traffic counters) and no-return atomic adds in the
+// access patterns of the plain and the reduced kernels (the atomic rate of
+// the L2/fabric). Every
 // kernel runs a fixed number of iterations per thread over a power-of-two
 // working set; nothing here is on the rendering path.
 #include "gsr_internal.hpp"
@@ -24,6 +27,66 @@ __global__ __launch_bounds__(kBlock) void copy_kernel(const float4 *__restrict__
         dst[i + 3 * stride] = d;
     }
     for (; i < n4; i += stride) dst[i] = src[i];
+}
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Write-only stream: eight 16-byte non-temporal stores per thread and round, consecutive lanes
+// on consecutive chunks (the store pattern of the per-Gaussian gradient writes).
+__global__ __launch_bounds__(kBlock) void write_kernel(v4f *__restrict__ dst, int64_t n4) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const v4f z = {0.f, 0.f, 0.f, 0.f};
+    for (; i + 7 * stride < n4; i += 8 * stride) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) __builtin_nontemporal_store(z, dst + i + k * stride);
+    }
+    for (; i < n4; i += stride) __builtin_nontemporal_store(z, dst + i);
+}
+
+// Read-only stream: eight 16-byte loads in flight per thread; the sum is stored only when it
+// takes a value the data cannot produce, so the loads stay.
+__global__ __launch_bounds__(kBlock) void read_kernel(const v4f *__restrict__ src, int64_t n4, float *sink) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    v4f acc = {0.f, 0.f, 0.f, 0.f};
+    for (; i + 7 * stride < n4; i += 8 * stride) {
+        v4f x[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) x[k] = __builtin_nontemporal_load(src + i + k * stride);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc += x[k];
+    }
+    for (; i < n4; i += stride) acc += src[i];
+    if (acc.x + acc.y + acc.z + acc.w == -1.0f) sink[0] = acc.x;
+}
+
+// Copy with eight non-temporal 16-byte loads in flight per thread, then eight non-temporal stores.
+__global__ __launch_bounds__(kBlock) void copy_nt_kernel(const v4f *__restrict__ src, v4f *__restrict__ dst,
+                                                         int64_t n4) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    for (; i + 7 * stride < n4; i += 8 * stride) {
+        v4f x[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) x[k] = __builtin_nontemporal_load(src + i + k * stride);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) __builtin_nontemporal_store(x[k], dst + i + k * stride);
+    }
+    for (; i < n4; i += stride) __builtin_nontemporal_store(src[i], dst + i);
+}
+
+// Gather of 48-byte records (the composite kernels' splat records): thread t reads record
+// (t * 40503) mod R, a permutation of the R = 2^k records, so every record is read exactly once
+// per launch in scattered order; three 16-byte loads per record.
+__global__ __launch_bounds__(kBlock) void gather48_kernel(const float4 *__restrict__ rec, uint64_t mask,
+                                                          float *sink) {
+    const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t > mask) return;
+    const uint64_t r = (t * 40503ull) & mask;
+    const float4 a = rec[3 * r], b = rec[3 * r + 1], c = rec[3 * r + 2];
+    const float s = a.x + a.y + a.z + a.w + b.x + b.y + b.z + b.w + c.x + c.y + c.z + c.w;
+    if (s == -1.0f) sink[0] = s;
 }
 
 // Every lane its own address: lanes of a wave on consecutive elements, the
@@ -93,6 +156,35 @@ hipError_t launch_microbench(int kind, void *buf, int64_t bytes, int64_t *ops, h
                                                                    (uint64_t)bytes / 128 - 1, iters);
         *ops = (int64_t)(waves * iters * 9);
         break;
+    case GSR_MB_WRITE: {
+        const int64_t n4 = bytes / 16;
+        write_kernel<<<grid, kBlock, 0, st>>>(static_cast<v4f *>(buf), n4);
+        *ops = n4 * 16;
+        break;
+    }
+    case GSR_MB_READ: {
+        // the last 16 bytes hold the sink
+        const int64_t n4 = bytes / 16 - 1;
+        read_kernel<<<grid, kBlock, 0, st>>>(static_cast<const v4f *>(buf), n4,
+                                             reinterpret_cast<float *>(static_cast<v4f *>(buf) + n4));
+        *ops = n4 * 16;
+        break;
+    }
+    case GSR_MB_COPY_NT: {
+        const int64_t n4 = bytes / 2 / 16;
+        copy_nt_kernel<<<grid, kBlock, 0, st>>>(static_cast<const v4f *>(buf), static_cast<v4f *>(buf) + n4, n4);
+        *ops = 2 * n4 * 16;
+        break;
+    }
+    case GSR_MB_GATHER48: {
+        // R = the largest power of two with 48 R + 16 <= bytes; the sink follows the records
+        uint64_t R = 1;
+        while ((R * 2) * 48 + 16 <= (uint64_t)bytes) R *= 2;
+        gather48_kernel<<<(unsigned)((R + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+            static_cast<const float4 *>(buf), R - 1, reinterpret_cast<float *>(static_cast<uint8_t *>(buf) + 48 * R));
+        *ops = (int64_t)(R * 48);
+        break;
+    }
     default:
         return hipErrorInvalidValue;
     }

@@ -213,57 +213,6 @@ __global__ __launch_bounds__(256) void preprocess_fwd_kernel(int n, const float 
     clamp_mask[i] = cm;
 }
 
-template <int DEG, typename AccT>
-__device__ __forceinline__ void preprocess_bwd_one(int i, const float *__restrict__ means,
-                                                   const float *__restrict__ log_scales,
-                                                   const float *__restrict__ quats,
-                                                   const float *__restrict__ opacity_logits,
-                                                   const float *__restrict__ sh, const DevCamera &cam,
-                                                   const int32_t *__restrict__ radius,
-                                                   const AccT *__restrict__ acc, const gsr_grads &out,
-                                                   int accumulate, float *Ysh, float *gsh);
-
-template <int DEG, typename AccT>
-__global__ __launch_bounds__(256) void preprocess_bwd_kernel(int n, const float *__restrict__ means,
-                                                             const float *__restrict__ log_scales,
-                                                             const float *__restrict__ quats,
-                                                             const float *__restrict__ opacity_logits,
-                                                             const float *__restrict__ sh, DevCamera cam,
-                                                             const int32_t *__restrict__ radius,
-                                                             const AccT *__restrict__ acc, gsr_grads out,
-                                                             int accumulate) {
-    constexpr int K = (DEG + 1) * (DEG + 1);
-    constexpr int NS = 3 * K;      // SH gradient floats per Gaussian
-    constexpr int PITCH = NS + 1;  // odd LDS pitch: lanes of a wave hit distinct banks
-    __shared__ float s_sh[4][64 * PITCH];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wave_base = blockIdx.x * blockDim.x + wave * 64;
-    if (wave_base >= n) return; // whole wave past the end
-    const int i = wave_base + lane;
-    float Ysh[K], gsh[3];
-#pragma unroll
-    for (int k = 0; k < K; ++k) Ysh[k] = 0.0f;
-    gsh[0] = gsh[1] = gsh[2] = 0.0f;
-    if (i < n) preprocess_bwd_one<DEG, AccT>(i, means, log_scales, quats, opacity_logits, sh, cam, radius, acc, out,
-                                       accumulate, Ysh, gsh);
-    // SH gradients (Y_k * dL/drgb_c, zero for culled Gaussians) leave through LDS so that the
-    // wave's 64 x 3K floats are written with consecutive lanes on consecutive addresses.
-    float *stage = s_sh[wave];
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) stage[lane * PITCH + 3 * k + ch] = Ysh[k] * gsh[ch];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const int count = min(64, n - wave_base);
-    float *dst = out.sh + (int64_t)wave_base * NS;
-    for (int t = lane; t < count * NS; t += 64) {
-        const float val = stage[(t / NS) * PITCH + t % NS];
-        dst[t] = accumulate ? dst[t] + val : val;
-    }
-}
-
 // The backward composite adds, per Gaussian, the five moments of h = dL/do
 // (each pixel's G dL/d(oG)) over the pixel offsets (dx, dy) = (px - u, py - v):
 //   m = (sum h dx, sum h dy, sum h dx^2, sum h dx dy, sum h dy^2).
@@ -284,31 +233,19 @@ __device__ __forceinline__ void moments_to_grads(const AccT *m, float o, float A
     g[4] = (float)((AccT)-0.5 * w * m[4]);
 }
 
-// Everything of one Gaussian except the SH gradient, which the caller writes
-// (Y receives the basis values, g the dL/drgb passed through the clamp; both
-// stay zero for a culled Gaussian).
+// Gradients of one visible Gaussian (radius > 0): o[0..2] means, o[3..5] log-scales,
+// o[6..9] quaternion, o[10] opacity logit; the SH gradient is Y[k] * g[ch] (the basis values
+// along the view direction times dL/drgb passed through the colour clamp), which the caller
+// expands when it writes the rows.
 template <int DEG, typename AccT>
-__device__ __forceinline__ void preprocess_bwd_one(int i, const float *__restrict__ means,
-                                                   const float *__restrict__ log_scales,
-                                                   const float *__restrict__ quats,
-                                                   const float *__restrict__ opacity_logits,
-                                                   const float *__restrict__ sh, const DevCamera &cam,
-                                                   const int32_t *__restrict__ radius,
-                                                   const AccT *__restrict__ acc, const gsr_grads &out,
-                                                   int accumulate, float *Ysh, float *gsh) {
+__device__ __forceinline__ void gaussian_grads(int64_t i, const float *__restrict__ means,
+                                               const float *__restrict__ log_scales,
+                                               const float *__restrict__ quats,
+                                               const float *__restrict__ opacity_logits,
+                                               const float *__restrict__ sh, const DevCamera &cam,
+                                               const AccT *__restrict__ acc, float (&o)[11],
+                                               float (&Ysh)[(DEG + 1) * (DEG + 1)], float (&gsh)[3]) {
     constexpr int K = (DEG + 1) * (DEG + 1);
-    float *o_m = out.means3d + 3 * (int64_t)i;
-    float *o_s = out.log_scales + 3 * (int64_t)i;
-    float *o_q = out.quats + 4 * (int64_t)i;
-    float *o_o = out.opacity_logits + i;
-    if (radius[i] <= 0) {
-        if (!accumulate) {
-            for (int k = 0; k < 3; ++k) o_m[k] = 0.f, o_s[k] = 0.f;
-            for (int k = 0; k < 4; ++k) o_q[k] = 0.f;
-            *o_o = 0.f;
-        }
-        return;
-    }
     const AccT *g = acc + (int64_t)i * GSR_ACC_STRIDE;
     const float mx = means[3 * i], my = means[3 * i + 1], mz = means[3 * i + 2];
     const float tz = depth_of(cam, mx, my, mz);
@@ -432,22 +369,118 @@ __device__ __forceinline__ void preprocess_bwd_one(int i, const float *__restric
                    y * dR[7]);
     const float qd = dq[0] * w + dq[1] * x + dq[2] * y + dq[3] * z;
     const float op = 1.0f / (1.0f + expf(-opacity_logits[i]));
-    const float dop = go * op * (1.0f - op);
-    if (accumulate) {
-        for (int k = 0; k < 3; ++k) o_m[k] += dm[k], o_s[k] += dls[k];
-        o_q[0] += (dq[0] - qd * w) * p.qinv;
-        o_q[1] += (dq[1] - qd * x) * p.qinv;
-        o_q[2] += (dq[2] - qd * y) * p.qinv;
-        o_q[3] += (dq[3] - qd * z) * p.qinv;
-        *o_o += dop;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) o[k] = dm[k], o[3 + k] = dls[k];
+    o[6] = (dq[0] - qd * w) * p.qinv;
+    o[7] = (dq[1] - qd * x) * p.qinv;
+    o[8] = (dq[2] - qd * y) * p.qinv;
+    o[9] = (dq[3] - qd * z) * p.qinv;
+    o[10] = go * op * (1.0f - op);
+}
+
+// a7 over blocks of 256 consecutive Gaussians. The block first lists its visible Gaussians
+// (radius > 0) in LDS, so that their chain rule runs on dense lanes (a view from inside the
+// cloud keeps about a quarter of them); each computed Gaussian leaves 11 gradients, its K basis
+// values and its 3 clamped colour gradients in an LDS row. Then the block writes its whole
+// segment of every output array, zeros for culled Gaussians included, as consecutive 16-byte
+// non-temporal stores (when the arrays are 16-byte aligned and the block is full; else one float
+// per lane and store). accumulate = 1 adds to the outputs instead.
+constexpr int kA7Block = 256;
+
+template <int DEG>
+struct A7Layout {
+    static constexpr int K = (DEG + 1) * (DEG + 1);
+    static constexpr int ROW = 11 + K + 3;     // gradients, basis values, colour gradients
+    static constexpr int PITCH = ROW | 1;       // odd: rows written by consecutive lanes hit distinct banks
+};
+
+template <int W, typename F>
+__device__ __forceinline__ void a7_write(float *__restrict__ dst, int count, bool vec, int accumulate, F &&val) {
+    // dst: this block's segment of one [n, W] array; count: Gaussians in the block
+    if (vec) {
+        typedef float v4f __attribute__((ext_vector_type(4)));
+        v4f *d4 = reinterpret_cast<v4f *>(dst);
+        constexpr int N4 = kA7Block * W / 4;
+        for (int c = threadIdx.x; c < N4; c += kA7Block) {
+            v4f v = {val(4 * c), val(4 * c + 1), val(4 * c + 2), val(4 * c + 3)};
+            if (accumulate) v += d4[c];
+            __builtin_nontemporal_store(v, d4 + c);
+        }
     } else {
-        for (int k = 0; k < 3; ++k) o_m[k] = dm[k], o_s[k] = dls[k];
-        o_q[0] = (dq[0] - qd * w) * p.qinv;
-        o_q[1] = (dq[1] - qd * x) * p.qinv;
-        o_q[2] = (dq[2] - qd * y) * p.qinv;
-        o_q[3] = (dq[3] - qd * z) * p.qinv;
-        *o_o = dop;
+        for (int e = threadIdx.x; e < count * W; e += kA7Block) {
+            const float v = val(e);
+            dst[e] = accumulate ? dst[e] + v : v;
+        }
     }
+}
+
+template <int DEG, typename AccT>
+__global__ __launch_bounds__(kA7Block) void preprocess_bwd_kernel(int n, const float *__restrict__ means,
+                                                                  const float *__restrict__ log_scales,
+                                                                  const float *__restrict__ quats,
+                                                                  const float *__restrict__ opacity_logits,
+                                                                  const float *__restrict__ sh, DevCamera cam,
+                                                                  const int32_t *__restrict__ radius,
+                                                                  const AccT *__restrict__ acc, gsr_grads out,
+                                                                  int accumulate, int aligned) {
+    using L = A7Layout<DEG>;
+    constexpr int K = L::K, NS = 3 * K, PITCH = L::PITCH;
+    __shared__ float s_row[kA7Block * PITCH];
+    __shared__ int16_t s_slot[kA7Block];   // LDS row of each Gaussian of the block, -1 = culled
+    __shared__ int16_t s_list[kA7Block];   // block-local indices of the visible Gaussians
+    __shared__ int s_wave_count[kA7Block / 64];
+    const int64_t g0 = (int64_t)blockIdx.x * kA7Block;
+    const int count = (int)min<int64_t>(kA7Block, (int64_t)n - g0);
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+
+    // ---- list the visible Gaussians in index order (ballot ranks within each wave) ----
+    const bool vis = t < count && radius[g0 + t] > 0;
+    const uint64_t mask = __ballot(vis);
+    if (lane == 0) s_wave_count[wave] = __popcll(mask);
+    __syncthreads();
+    int before = 0, nv = 0;
+#pragma unroll
+    for (int w = 0; w < kA7Block / 64; ++w) {
+        before += w < wave ? s_wave_count[w] : 0;
+        nv += s_wave_count[w];
+    }
+    const int rank = before + __popcll(mask & ((1ull << lane) - 1ull));
+    s_slot[t] = vis ? (int16_t)rank : (int16_t)-1;
+    if (vis) s_list[rank] = (int16_t)t;
+    __syncthreads();
+
+    // ---- chain rule of the visible ones on the first nv lanes ----
+    if (t < nv) {
+        const int64_t i = g0 + s_list[t];
+        float o[11], Y[K], g[3];
+        gaussian_grads<DEG, AccT>(i, means, log_scales, quats, opacity_logits, sh, cam, acc, o, Y, g);
+        float *row = s_row + t * PITCH;
+#pragma unroll
+        for (int k = 0; k < 11; ++k) row[k] = o[k];
+#pragma unroll
+        for (int k = 0; k < K; ++k) row[11 + k] = Y[k];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) row[11 + K + c] = g[c];
+    }
+    __syncthreads();
+
+    // ---- the block's segment of each output array, culled rows as zeros ----
+    const bool vec = aligned && count == kA7Block;
+    const auto field = [&](int W, int off) {
+        return [=](int e) {
+            const int s = s_slot[e / W];
+            return s >= 0 ? s_row[s * PITCH + off + e % W] : 0.0f;
+        };
+    };
+    a7_write<3>(out.means3d + 3 * g0, count, vec, accumulate, field(3, 0));
+    a7_write<3>(out.log_scales + 3 * g0, count, vec, accumulate, field(3, 3));
+    a7_write<4>(out.quats + 4 * g0, count, vec, accumulate, field(4, 6));
+    a7_write<1>(out.opacity_logits + g0, count, vec, accumulate, field(1, 10));
+    a7_write<NS>(out.sh + NS * g0, count, vec, accumulate, [=](int e) {
+        const int s = s_slot[e / NS];
+        const int r = e % NS;
+        return s >= 0 ? s_row[s * PITCH + 11 + r / 3] * s_row[s * PITCH + 11 + K + r % 3] : 0.0f;
+    });
 }
 
 } // namespace
@@ -473,11 +506,14 @@ hipError_t launch_preprocess_fwd(const gsr_scene &s, const DevCamera &cam, float
 hipError_t launch_preprocess_bwd(const gsr_scene &s, const DevCamera &cam, const int32_t *radius, const void *acc,
                                  bool acc_f64, const gsr_grads &out, int accumulate, hipStream_t st) {
     if (s.n <= 0) return hipSuccess;
-    const unsigned blocks = (unsigned)((s.n + 255) / 256);
+    const unsigned blocks = (unsigned)((s.n + kA7Block - 1) / kA7Block);
+    const auto a16 = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+    const int aligned = a16(out.means3d) && a16(out.log_scales) && a16(out.quats) && a16(out.opacity_logits) &&
+                        a16(out.sh);
 #define GSR_PB(D, A)                                                                                               \
-    preprocess_bwd_kernel<D, A><<<blocks, 256, 0, st>>>(s.n, s.means3d, s.log_scales, s.quats, s.opacity_logits,  \
-                                                         s.sh, cam, radius, static_cast<const A *>(acc), out,     \
-                                                         accumulate)
+    preprocess_bwd_kernel<D, A><<<blocks, kA7Block, 0, st>>>(s.n, s.means3d, s.log_scales, s.quats,                \
+                                                              s.opacity_logits, s.sh, cam, radius,                 \
+                                                              static_cast<const A *>(acc), out, accumulate, aligned)
     if (acc_f64) {
         switch (s.sh_degree) {
         case 0: GSR_PB(0, double); break;

@@ -1188,7 +1188,7 @@ gsr_status gsr_microbench(gsr_ctx *ctx, int32_t kind, int64_t bytes, int32_t rep
                           double *ops_per_launch) {
     if (!ctx) return GSR_EINVAL;
     ctx->err.clear();
-    if (kind < GSR_MB_COPY || kind > GSR_MB_ATOMIC_F64_NINE_LANES) return fail(ctx, GSR_EINVAL, "bad kind");
+    if (kind < GSR_MB_COPY || kind > GSR_MB_GATHER48) return fail(ctx, GSR_EINVAL, "bad kind");
     if (bytes < (1 << 20) || bytes > (int64_t(1) << 32) || (bytes & (bytes - 1)))
         return fail(ctx, GSR_EINVAL, "bytes must be a power of two in [1 MiB, 4 GiB]");
     if (reps < 1 || reps > 100 || !ms_per_launch || !ops_per_launch) return fail(ctx, GSR_EINVAL, "bad arguments");

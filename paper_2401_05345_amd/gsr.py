@@ -28,7 +28,8 @@ GSR_MAX_BATCH = 16
 GSR_EBUDGET = -5
 GSR_ACC_STRIDE = 16
 (GSR_MB_COPY, GSR_MB_ATOMIC_F32_DISTINCT, GSR_MB_ATOMIC_F64_DISTINCT, GSR_MB_ATOMIC_F32_SAME_ADDRESS,
- GSR_MB_ATOMIC_F32_ONE_LANE, GSR_MB_ATOMIC_F64_NINE_LANES) = range(6)
+ GSR_MB_ATOMIC_F32_ONE_LANE, GSR_MB_ATOMIC_F64_NINE_LANES, GSR_MB_WRITE, GSR_MB_READ, GSR_MB_COPY_NT,
+ GSR_MB_GATHER48) = range(10)
 
 c_void_p = ctypes.c_void_p
 c_int32 = ctypes.c_int32

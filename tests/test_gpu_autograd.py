@@ -114,14 +114,18 @@ def test_autograd_full_large_view_equals_direct_backward(renderer):
         d32b, _, _ = run_backward(renderer, gs, st, dl, cfg32)
     finally:
         gsr.gsr_fwd_release(renderer.ctx, st)
-    # fp64 accumulators (the default): autograd and two direct runs give the same sums. The fp32
-    # runs differ from each other and from them by the atomic-order noise, which reaches the
-    # 1e-3 gradient tolerance on the quaternions of this view (the reason fp64 is the default);
-    # it is reported, and only bounded loosely here.
+    # fp64 accumulators (the default): autograd and two direct runs give the same sums (their
+    # parity with the oracle over the whole frame is test_gpu_large.py's).
+    # fp32 accumulators (the paper's setting) are NOT within the 1e-3 gradient tolerance on this
+    # view: the screen-filling splats collect ~1e4 wave sums with heavy cancellation, and the
+    # order in which fp32 atomics add them moves the quaternion and scale gradients by ~1e-3
+    # from run to run. The bound below is no parity claim; it only checks that the fp32 sums are
+    # the same sums up to that ordering noise (a wrong term would be far above it).
     for name, p, g, h, a32, b32 in zip(NAMES, params, grads, again, d32a, d32b):
         e, floor64 = rel_l2(p.grad.cpu().numpy(), g), rel_l2(h, g)
         floor32, e32 = rel_l2(b32, a32), rel_l2(a32, g)
         say(f"[gpu] full 3M {name}: autograd vs direct {e:.2e}, direct runs {floor64:.2e} (fp64 acc); "
-            f"fp32 acc runs {floor32:.2e}, fp32 vs fp64 {e32:.2e}")
+            f"fp32 acc runs {floor32:.2e}, fp32 vs fp64 {e32:.2e} (fp32 accumulators: outside parity here)")
         assert e <= 1e-5 and floor64 <= 1e-5, (name, e, floor64)
-        assert e32 <= 1e-2, (name, e32, floor32)
+        ordering_noise_bound = 1e-2
+        assert e32 <= ordering_noise_bound, (name, e32, floor32)

@@ -204,3 +204,50 @@ def test_backward_counters_match_the_atomic_count_model(renderer):
                 f"WR={c.reduced} A<={c.plain_lanes} lane_atomics={c.lane_atomics}")
         finally:
             gsr.gsr_fwd_release(renderer.ctx, st)
+
+
+@pytest.mark.parametrize("degree", [0, 3])
+def test_gradient_outputs_unaligned_and_accumulated(renderer, degree):
+    # The per-Gaussian gradients leave as 16-byte stores when every output is 16-byte aligned
+    # and a block of 256 Gaussians is full, else one float at a time: both paths, and
+    # accumulate = 1 on both, must write the same values bit for bit.
+    import torch
+    say(f"[gpu] unaligned / accumulated gradient outputs, SH degree {degree}")
+    wl = sg.tiny_scene(9, 777, 48, 40, sh_degree=degree, log_scale=(-2.4, 0.4), half=0.8)
+    sc = wl.scene
+    m = sc.means3d.copy()
+    m[::5, 2] = -6.0                # every fifth Gaussian behind the camera: culled rows among visible ones
+    wl.scene = sg.Scene(m, sc.log_scales, sc.quats, sc.opacity_logits, sc.sh, degree)
+    cam = wl.camera.with_bg((0.1, 0.2, 0.3))
+    gs = GpuScene(wl.scene, cam)
+    cfg = gsr.make_config(16, 256, gsr.GSR_BWD_WAVE_REDUCE, 1)
+    st, out = run_render(renderer, gs, cfg)
+    try:
+        rr = oracle.render(wl.scene, cam)
+        dl = torch.from_numpy(oracle_dl_dimage(rr, wl.target, "l1")).cuda()
+        gsr.gsr_backward_composite(renderer.ctx, st, dl, cfg)
+        shapes = [v.shape for v in gs.t.values()]
+        aligned = [torch.full(s, float("nan"), device="cuda:0") for s in shapes]
+        gsr.gsr_backward_params(renderer.ctx, st, gsr.make_grads(*aligned), 0)
+        bufs = [torch.full((int(np.prod(s)) + 1,), float("nan"), device="cuda:0") for s in shapes]
+        shifted = [b[1:].view(s) for b, s in zip(bufs, shapes)]
+        gsr.gsr_backward_params(renderer.ctx, st, gsr.make_grads(*shifted), 0)
+        base = [torch.randn(s, device="cuda:0") for s in shapes]
+        acc_a = [b.clone() for b in base]
+        acc_u_bufs = [torch.zeros(int(np.prod(s)) + 1, device="cuda:0") for s in shapes]
+        acc_u = [b[1:].view(s) for b, s in zip(acc_u_bufs, shapes)]
+        for a, b in zip(acc_u, base):
+            a.copy_(b)
+        gsr.gsr_backward_params(renderer.ctx, st, gsr.make_grads(*acc_a), 1)
+        gsr.gsr_backward_params(renderer.ctx, st, gsr.make_grads(*acc_u), 1)
+        torch.cuda.synchronize()
+        vis = torch.from_numpy(out["radius"] > 0).cuda()
+        assert 0 < int(vis.sum()) < gs.n
+        for a, u, b, ca, cu in zip(aligned, shifted, base, acc_a, acc_u):
+            assert torch.isfinite(a).all()
+            assert torch.equal(a.view(torch.int32), u.view(torch.int32))
+            assert (a[~vis] == 0).all()
+            assert torch.equal(ca, b + a) and torch.equal(cu, b + a)
+        assert all(torch.isnan(b[0]) for b in bufs)   # nothing written before the shifted arrays
+    finally:
+        gsr.gsr_fwd_release(renderer.ctx, st)

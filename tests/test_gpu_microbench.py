@@ -27,6 +27,10 @@ def renderer(gsr):
     (gsr.GSR_MB_ATOMIC_F32_SAME_ADDRESS, THREADS * ITERS),
     (gsr.GSR_MB_ATOMIC_F32_ONE_LANE, THREADS // 64 * ITERS),
     (gsr.GSR_MB_ATOMIC_F64_NINE_LANES, THREADS // 64 * ITERS * 9),
+    (gsr.GSR_MB_WRITE, 8 * MIB),
+    (gsr.GSR_MB_READ, 8 * MIB - 16),
+    (gsr.GSR_MB_COPY_NT, 8 * MIB),
+    (gsr.GSR_MB_GATHER48, 131072 * 48),
 ])
 def test_microbench_runs_and_counts(renderer, kind, ops):
     say(f"[gpu] microbench kind {kind}")
@@ -36,7 +40,7 @@ def test_microbench_runs_and_counts(renderer, kind, ops):
 
 
 def test_microbench_rejects_bad_arguments(renderer):
-    for kind, nbytes, reps in [(6, 8 * MIB, 3), (-1, 8 * MIB, 3), (0, 3 * MIB, 3), (0, MIB // 2, 3),
+    for kind, nbytes, reps in [(10, 8 * MIB, 3), (-1, 8 * MIB, 3), (0, 3 * MIB, 3), (0, MIB // 2, 3),
                                (0, 8 << 30, 3), (0, 8 * MIB, 0), (0, 8 * MIB, 101)]:
         with pytest.raises(gsr.GsrError) as e:
             gsr.gsr_microbench(renderer.ctx, kind, nbytes, reps)
