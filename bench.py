@@ -9,8 +9,8 @@ workload's loss gradient (L1 for the 3M-Gaussian 1080p view, L1 + 0.2 D-SSIM
 for the object scene), and the backward (backward composite + per-Gaussian
 chain rule), inputs already resident in HBM. The default view is the large
 one: 3M Gaussians at 1920x1080 with the camera inside the cloud. `value` is
-the backward's milliseconds per iteration (backward composite + preprocess
-backward) in wave-reduce mode at the balancing threshold picked by a
+the backward's milliseconds per iteration (the whole backward call: clearing
+the accumulator rows, backward composite, preprocess backward) in wave-reduce mode at the balancing threshold picked by a
 one-iteration-per-candidate sweep (the paper's tuning rule); the
 plain-atomic backward on the same forward state is reported beside it, as
 are the atomic counts, both backward kernels against their roofs and the
@@ -46,7 +46,7 @@ FLOPS_PER_EVAL = 14
 FLOPS_PER_CONTRIB = 40
 BYTES_PER_RECORD = 40             # id + mean2d + conic + opacity + rgb, read once per tile-list entry walked
 BYTES_PER_PIXEL = 20              # dL/dI (12) + T_final (4) + n_contrib (4)
-BYTES_PER_VISIBLE = 2 * 72        # nine fp64 sums written back once (zero-fill excluded) and read by a7
+BYTES_PER_VISIBLE = 72            # nine fp64 sums written back once (their clearing excluded; a7 reads them)
 
 
 MODES = {"reduce": 1, "plain": 0, "serial": 2, "block": 3}   # gsr_bwd_mode values
@@ -71,6 +71,9 @@ def parse():
                    help="reduced sums issued by one lane (default: nine lanes, one instruction)")
     p.add_argument("--no-batch", action="store_true", help="skip the 16-view batched leg")
     p.add_argument("--no-serve", action="store_true", help="skip the served request stream")
+    p.add_argument("--profile-batch", default=None, metavar="TILE,LDS,THR",
+                   help="only the 16-view batched render + backward at this fixed configuration, --steps "
+                        "times (for rocprofv3 runs: no autotuning, no graph capture)")
     p.add_argument("--serve-seconds", type=float, default=1.5, help="seconds of arrivals per rate")
     p.add_argument("--xcd-remap", action="store_true", help="map neighbouring tiles to one XCD")
     p.add_argument("--no-tile-order", action="store_true", help="launch tiles in index order (no longest-first)")
@@ -146,14 +149,17 @@ class Bench:
         self.r.release(fr)
         return st, stats
 
-    def backward_only(self, fr, cfg, iters):
-        """Backward repeated on one forward state; returns per-iteration (a6, a7) ms lists."""
+    def backward_only(self, fr, cfg, iters, clear=None):
+        """Backward repeated on one forward state; returns per-iteration (a6, a7) ms lists (and the
+        accumulator clearing's ms in `clear` when given)."""
         a6, a7 = [], []
         for _ in range(iters):
             self.gsr.gsr_backward(self.r.ctx, fr.state, self.dl, self.gstruct, 0, cfg)
             st = self.gsr.gsr_ctx_stage_times(self.r.ctx)
             a6.append(st.composite_bwd)
             a7.append(st.preprocess_bwd)
+            if clear is not None:
+                clear.append(st.zero_acc)
         return a6, a7
 
     def loss_grad(self, image):
@@ -280,6 +286,46 @@ def bench_multi_view(flags, reps=5):
     })
     log(f"[bench] multi-view: {json.dumps({k: v for k, v in res.items() if k != 'autotune'})}")
     return res
+
+
+def profile_multi_view(flags, spec, steps, warmup):
+    """The 16-view batch's kernels alone: batched render, L1 gradient and batched backward at a
+    fixed (tile, LDS batch, threshold), with no autotuner and no graph capture."""
+    import torch
+    from paper_2401_05345_amd import gsr
+    from paper_2401_05345_amd import scenegen as sg
+    tile, lds, thr = (int(x) for x in spec.split(","))
+    mv = sg.multi_view()
+    dev = torch.device("cuda:0")
+    st_t = [[torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in s.arrays()] for s in mv.scenes]
+    structs = [gsr.make_scene(*t, s.sh_degree) for t, s in zip(st_t, mv.scenes)]
+    gstructs = [gsr.make_grads(*[torch.zeros_like(x) for x in t]) for t in st_t]
+    scenes, cams, targets, imgs, dls, outs = [], [], [], [], [], []
+    for si, c, tgt in mv.views:
+        scenes.append(structs[si])
+        cams.append(gsr.make_camera(c.width, c.height, c.fx, c.fy, c.cx, c.cy, c.world_to_cam, c.znear, c.bg))
+        targets.append(torch.from_numpy(tgt).to(dev))
+        imgs.append(torch.empty((3, c.height, c.width), device=dev))
+        dls.append(torch.empty((3, c.height, c.width), device=dev))
+        outs.append(gstructs[si])
+    r = gsr.Renderer(0)
+    cfg = gsr.make_config(tile, lds, gsr.GSR_BWD_WAVE_REDUCE, thr, flags)
+    torch.cuda.synchronize()
+    t0 = None
+    for k in range(warmup + steps):
+        if k == warmup:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        states = gsr.gsr_render_batch(r.ctx, scenes, cams, cfg, imgs)
+        for im, tg, d in zip(imgs, targets, dls):
+            gsr.gsr_l1_grad(r.ctx, im, tg, d)
+        gsr.gsr_backward_batch(r.ctx, states, dls, outs, 0, cfg)
+        for s in states:
+            gsr.gsr_fwd_release(r.ctx, s)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / max(steps, 1)
+    r.close()
+    return {"profile_batch": spec, "views": len(mv.views), "ms_per_step": round(ms, 4)}
 
 
 SERVE_RATES = (50, 100, 200, 400)       # the served stream's rates (both servers)
@@ -443,8 +489,9 @@ def ab_legs(b, thr, iters, full=True):
         legs += [("serial_f64", gsr.GSR_BWD_SERIAL_REDUCE, thr, 0, iters),
                  ("block_f64", gsr.GSR_BWD_BLOCK_REDUCE, thr, 0, iters)]
     for name, mode, t, flags, n in legs:
-        a6, a7 = b.backward_only(fr, b.cfg(mode, t, flags), n)
-        res[name] = (float(np.median(a6)), float(np.median(a7)))
+        z = []
+        a6, a7 = b.backward_only(fr, b.cfg(mode, t, flags), n, z)
+        res[name] = (float(np.median(a6)), float(np.median(a7)), float(np.median(z)))
     cnt = {"plain": b.counters(fr, gsr.GSR_BWD_PLAIN_ATOMIC, 0), "reduce": b.counters(fr, gsr.GSR_BWD_WAVE_REDUCE, thr)}
     if full:
         cnt["block"] = b.counters(fr, gsr.GSR_BWD_BLOCK_REDUCE, thr)
@@ -454,17 +501,18 @@ def ab_legs(b, thr, iters, full=True):
 
 
 def ab_summary(res, cnt, stats, thr, sweep):
-    r6, r7 = res["reduce_f64"]
-    p6, p7 = res["plain_f32"]
-    q6, q7 = res["plain_f64"]
-    w6, w7 = res["reduce_f32"]
+    r6, r7, rz = res["reduce_f64"]
+    p6, p7, pz = res["plain_f32"]
+    q6, q7, qz = res["plain_f64"]
+    w6, w7, wz = res["reduce_f32"]
     cp, cr = cnt["plain"], cnt["reduce"]
     out = {
         "n_pairs": int(stats.n_pairs), "n_visible": int(stats.n_visible), "threshold": thr,
-        "wave_reduce_ms": round(r6 + r7, 4),
-        "plain_atomic_ms": round(p6 + p7, 4),
-        "plain_atomic_f64_ms": round(q6 + q7, 4),
-        "wave_reduce_acc_f32_ms": round(w6 + w7, 4),
+        "wave_reduce_ms": round(rz + r6 + r7, 4),
+        "plain_atomic_ms": round(pz + p6 + p7, 4),
+        "plain_atomic_f64_ms": round(qz + q6 + q7, 4),
+        "wave_reduce_acc_f32_ms": round(wz + w6 + w7, 4),
+        "clear_accumulators_ms": round(rz, 4),
         "composite_bwd_wave_reduce_ms": round(r6, 4),
         "preprocess_bwd_ms": round(r7, 4),
         "composite_bwd_plain_ms": round(p6, 4),
@@ -500,6 +548,7 @@ def rooflines(wl, stats, cr, a6_ms, a7_ms):
     K3 = 3 * (wl.scene.sh_degree + 1) ** 2
     flops = FLOPS_PER_EVAL * cr.evaluated + FLOPS_PER_CONTRIB * cr.active
     a6_tflops = flops / (a6_ms * 1e-3) / 1e12
+    pbytes = 4 * (11 + K3)
     a6_bytes = BYTES_PER_PIXEL * hw + BYTES_PER_VISIBLE * n_vis + BYTES_PER_RECORD * int(stats.n_pairs)
     a6 = {"bound": "alu", "achieved": round(a6_tflops, 3), "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
           "frac": round(a6_tflops / PEAK_FP32_VALU_TFLOPS, 4), "kernel": "composite_bwd_kernel<16,256,wave_reduce>",
@@ -512,7 +561,6 @@ def rooflines(wl, stats, cr, a6_ms, a7_ms):
         a6["valu_issue_frac"] = m6["valu_issue_frac"]
     # a7: reads radius (4 B) of every Gaussian and, for the visible ones, the parameters and the nine
     # fp64 accumulator sums; writes every Gaussian's gradient row (zeros for culled ones).
-    pbytes = 4 * (11 + K3)
     a7_bytes = n * (4 + pbytes) + n_vis * (pbytes + 72)
     a7_gbs = a7_bytes / (a7_ms * 1e-3) / 1e9
     a7 = {"bound": "hbm", "achieved": round(a7_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -557,6 +605,11 @@ def main():
                           "GBs": round(ops / ms / 1e6, 1), "launches": 6}))
         return
 
+    if args.profile_batch:
+        flags = 0 if args.no_lane_split else gsr.GSR_FLAG_LANE_SPLIT_ATOMICS
+        print(json.dumps(profile_multi_view(flags, args.profile_batch, args.steps, args.warmup)))
+        return
+
     wl = sg.WORKLOADS[args.workload]()
     log(f"[bench] workload {wl.name}: {wl.scene.n} Gaussians, {wl.camera.width}x{wl.camera.height}")
     Bench.extra_flags = ((0 if args.no_lane_split else gsr.GSR_FLAG_LANE_SPLIT_ATOMICS) |
@@ -589,10 +642,13 @@ def main():
         per.append(st)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) * 1000.0 / args.steps
-    bwd = np.array([s.composite_bwd + s.preprocess_bwd for s in per])
+    # The whole backward call: accumulator rows cleared, backward composite, per-Gaussian chain rule.
+    bwd = np.array([s.zero_acc + s.composite_bwd + s.preprocess_bwd for s in per])
     a6 = np.array([s.composite_bwd for s in per])
     fwd = np.array([s.preprocess + s.depth_sort + s.scan_emit + s.tile_sort + s.ranges + s.composite_fwd for s in per])
-    log(f"[bench] {args.steps} steps: {wall:.3f} ms/step, backward {bwd.mean():.3f} ms (a6 {a6.mean():.3f})")
+    a7 = np.array([s.preprocess_bwd for s in per])
+    log(f"[bench] {args.steps} steps: {wall:.3f} ms/step, backward {bwd.mean():.3f} ms (a6 {a6.mean():.3f}, "
+        f"a7 {a7.mean():.3f})")
     if args.profile_only:
         print(json.dumps({"profile_only": True, "ms_per_step": wall, "bwd_ms": float(bwd.mean())}))
         return

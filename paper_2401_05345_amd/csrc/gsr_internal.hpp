@@ -61,7 +61,8 @@ hipError_t launch_preprocess_fwd(const gsr_scene &s, const DevCamera &cam, float
                                  uint32_t *tiles_touched, uint32_t *depth_key, uint32_t *ids, uint8_t *clamp_mask,
                                  hipStream_t st);
 
-// a7: raw-parameter gradients from the accumulators (float or, acc_f64, double rows).
+// a7: raw-parameter gradients from the accumulators (float or, acc_f64, double rows). Writes
+// every row (zeros for culled Gaussians), or with accumulate = 1 adds to the visible rows only.
 hipError_t launch_preprocess_bwd(const gsr_scene &s, const DevCamera &cam, const int32_t *radius, const void *acc,
                                  bool acc_f64, const gsr_grads &out, int accumulate, hipStream_t st);
 

@@ -7,48 +7,98 @@
 // These are the first and last steps of the paper's rasterisation pipeline
 // figure (projection of the primitives; "gradients for all the parameters");
 // the math is the published 3D Gaussian Splatting method.
+#include <algorithm>
+
 #include "device_common.hpp"
 
 namespace gsr {
 namespace {
 
-struct Proj {
-    float tx, ty, tz;
-    float R[9];      // rotation of the normalised quaternion, row-major
-    float s[3];      // exp(log-scales)
-    float M[9];      // R diag(s)
-    float Sig[6];    // Sigma: 00 01 02 11 12 22
-    float T2[6];     // J * Rc, rows 0 and 1
-    float V0[3], V1[3];
-    float a, b, c, det;
-    float xc, yc;    // guard-band-clamped x, y used by J
+// Projection quantities of one Gaussian. The forward (a1) takes them in fp32; the chain rule
+// (a7) recomputes them in fp64 from the same fp32 parameters: for near-isotropic splats the
+// rotation and scale gradients are small differences of large conic terms, and fp32 rounding of
+// those terms would move them by ~1e-3.
+template <typename T>
+struct ProjT {
+    T tx, ty, tz;
+    T R[9];      // rotation of the normalised quaternion, row-major
+    T s[3];      // exp(log-scales)
+    T M[9];      // R diag(s)
+    T Sig[6];    // Sigma: 00 01 02 11 12 22
+    T T2[6];     // J * Rc, rows 0 and 1
+    T V0[3], V1[3];
+    T a, b, c, det;
+    T xc, yc;    // guard-band-clamped x, y used by J
     bool clx, cly;
-    float qn[4];     // normalised quaternion
-    float qinv;      // 1 / |q|
+    T qn[4];     // normalised quaternion
+    T qinv;      // 1 / |q|
 };
+using Proj = ProjT<float>;
 
-__device__ __forceinline__ void project_splat(const DevCamera &cam, float mx, float my, float mz, float tz,
-                                              const float *ls, const float *q, Proj &p) {
+// fp64 reciprocal: the hardware estimate refined by one Newton step (relative error ~1e-16).
+__device__ __forceinline__ double recip64(double x) {
+    const double r = __builtin_amdgcn_rcp(x);
+    return r * fma(-x, r, 2.0);
+}
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ float div_t(float a, float b) { return a / b; }
+__device__ __forceinline__ double div_t(double a, double b) { return a * recip64(b); }
+// exp of a parameter: in fp64 the fp32 value upcast (a relative change of ~1e-7 of a free
+// parameter, which moves the derivatives by as little; only the chain's sums need fp64).
+__device__ __forceinline__ float exp_t(float x) { return expf(x); }
+__device__ __forceinline__ double exp_t(double x) { return (double)expf((float)x); }
+// 1/sqrt: in fp64 refined by a Newton step, so the normalised quaternion has unit length to
+// ~1e-16 and its rotation matrix is orthogonal to that level.
+__device__ __forceinline__ float rsqrt_t(float x) { return 1.0f / sqrtf(x); }
+__device__ __forceinline__ double rsqrt_t(double x) {
+    const double r = (double)(1.0f / sqrtf((float)x));
+    return r * fma(-0.5 * x * r, r, 1.5);
+}
+__device__ __forceinline__ float fmin_t(float a, float b) { return fminf(a, b); }
+__device__ __forceinline__ double fmin_t(double a, double b) { return fmin(a, b); }
+__device__ __forceinline__ float fmax_t(float a, float b) { return fmaxf(a, b); }
+__device__ __forceinline__ double fmax_t(double a, double b) { return fmax(a, b); }
+
+// Guard band of x/z and y/z: the camera's fp32 bounds, or in fp64 the same formula (the image
+// extended by 15 % of its size on each side) evaluated in fp64.
+__device__ __forceinline__ void guard_band(const DevCamera &cam, float &lox, float &hix, float &loy, float &hiy) {
+    lox = cam.lox, hix = cam.hix, loy = cam.loy, hiy = cam.hiy;
+}
+__device__ __forceinline__ void guard_band(const DevCamera &cam, double &lox, double &hix, double &loy,
+                                           double &hiy) {
+    const double w = cam.width, h = cam.height, cx = cam.cx, cy = cam.cy;
+    const double ifx = recip64((double)cam.fx), ify = recip64((double)cam.fy);
+    lox = (-cx - 0.15 * w) * ifx;
+    hix = (w - cx + 0.15 * w) * ifx;
+    loy = (-cy - 0.15 * h) * ify;
+    hiy = (h - cy + 0.15 * h) * ify;
+}
+
+template <typename T>
+__device__ __forceinline__ void project_splat(const DevCamera &cam, T mx, T my, T mz, T tz, const float *ls,
+                                              const float *q, ProjT<T> &p) {
     p.tz = tz;
-    p.tx = fmaf(cam.R[0], mx, fmaf(cam.R[1], my, fmaf(cam.R[2], mz, cam.t[0])));
-    p.ty = fmaf(cam.R[3], mx, fmaf(cam.R[4], my, fmaf(cam.R[5], mz, cam.t[1])));
+    p.tx = fma_t((T)cam.R[0], mx, fma_t((T)cam.R[1], my, fma_t((T)cam.R[2], mz, (T)cam.t[0])));
+    p.ty = fma_t((T)cam.R[3], mx, fma_t((T)cam.R[4], my, fma_t((T)cam.R[5], mz, (T)cam.t[1])));
 
-    p.s[0] = expf(ls[0]);
-    p.s[1] = expf(ls[1]);
-    p.s[2] = expf(ls[2]);
-    const float qq = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
-    p.qinv = 1.0f / sqrtf(qq);
-    const float w = q[0] * p.qinv, x = q[1] * p.qinv, y = q[2] * p.qinv, z = q[3] * p.qinv;
+    p.s[0] = exp_t((T)ls[0]);
+    p.s[1] = exp_t((T)ls[1]);
+    p.s[2] = exp_t((T)ls[2]);
+    const T q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3];
+    const T qq = q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3;
+    p.qinv = rsqrt_t(qq);
+    const T w = q0 * p.qinv, x = q1 * p.qinv, y = q2 * p.qinv, z = q3 * p.qinv;
     p.qn[0] = w; p.qn[1] = x; p.qn[2] = y; p.qn[3] = z;
-    p.R[0] = 1.f - 2.f * (y * y + z * z); p.R[1] = 2.f * (x * y - w * z);       p.R[2] = 2.f * (x * z + w * y);
-    p.R[3] = 2.f * (x * y + w * z);       p.R[4] = 1.f - 2.f * (x * x + z * z); p.R[5] = 2.f * (y * z - w * x);
-    p.R[6] = 2.f * (x * z - w * y);       p.R[7] = 2.f * (y * z + w * x);       p.R[8] = 1.f - 2.f * (x * x + y * y);
+    p.R[0] = T(1) - T(2) * (y * y + z * z); p.R[1] = T(2) * (x * y - w * z);       p.R[2] = T(2) * (x * z + w * y);
+    p.R[3] = T(2) * (x * y + w * z);       p.R[4] = T(1) - T(2) * (x * x + z * z); p.R[5] = T(2) * (y * z - w * x);
+    p.R[6] = T(2) * (x * z - w * y);       p.R[7] = T(2) * (y * z + w * x);       p.R[8] = T(1) - T(2) * (x * x + y * y);
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
         for (int k = 0; k < 3; ++k) p.M[3 * r + k] = p.R[3 * r + k] * p.s[k];
     // Sigma = M M^T
-    const float *M = p.M;
+    const T *M = p.M;
     p.Sig[0] = M[0] * M[0] + M[1] * M[1] + M[2] * M[2];
     p.Sig[1] = M[0] * M[3] + M[1] * M[4] + M[2] * M[5];
     p.Sig[2] = M[0] * M[6] + M[1] * M[7] + M[2] * M[8];
@@ -57,32 +107,35 @@ __device__ __forceinline__ void project_splat(const DevCamera &cam, float mx, fl
     p.Sig[5] = M[6] * M[6] + M[7] * M[7] + M[8] * M[8];
 
     // Jacobian of the pinhole map, x/z and y/z held inside the guard band.
-    const float txtz = p.tx / tz, tytz = p.ty / tz;
-    p.clx = txtz < cam.lox || txtz > cam.hix;
-    p.cly = tytz < cam.loy || tytz > cam.hiy;
-    p.xc = fminf(cam.hix, fmaxf(cam.lox, txtz)) * tz;
-    p.yc = fminf(cam.hiy, fmaxf(cam.loy, tytz)) * tz;
-    const float itz = 1.0f / tz;
-    const float J00 = cam.fx * itz, J02 = -cam.fx * p.xc * itz * itz;
-    const float J11 = cam.fy * itz, J12 = -cam.fy * p.yc * itz * itz;
+    T lox, hix, loy, hiy;
+    guard_band(cam, lox, hix, loy, hiy);
+    const T txtz = div_t(p.tx, tz), tytz = div_t(p.ty, tz);
+    p.clx = txtz < lox || txtz > hix;
+    p.cly = tytz < loy || tytz > hiy;
+    p.xc = fmin_t(hix, fmax_t(lox, txtz)) * tz;
+    p.yc = fmin_t(hiy, fmax_t(loy, tytz)) * tz;
+    const T itz = div_t(T(1), tz);
+    const T fx = cam.fx, fy = cam.fy;
+    const T J00 = fx * itz, J02 = -fx * p.xc * itz * itz;
+    const T J11 = fy * itz, J12 = -fy * p.yc * itz * itz;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        p.T2[k] = J00 * cam.R[k] + J02 * cam.R[6 + k];
-        p.T2[3 + k] = J11 * cam.R[3 + k] + J12 * cam.R[6 + k];
+        p.T2[k] = J00 * (T)cam.R[k] + J02 * (T)cam.R[6 + k];
+        p.T2[3 + k] = J11 * (T)cam.R[3 + k] + J12 * (T)cam.R[6 + k];
     }
     // V = Sigma T2^T (Sigma symmetric), a = T2_0 . V0, b = T2_0 . V1, c = T2_1 . V1
-    const float *S = p.Sig;
-    const float *T = p.T2;
-    p.V0[0] = S[0] * T[0] + S[1] * T[1] + S[2] * T[2];
-    p.V0[1] = S[1] * T[0] + S[3] * T[1] + S[4] * T[2];
-    p.V0[2] = S[2] * T[0] + S[4] * T[1] + S[5] * T[2];
-    p.V1[0] = S[0] * T[3] + S[1] * T[4] + S[2] * T[5];
-    p.V1[1] = S[1] * T[3] + S[3] * T[4] + S[4] * T[5];
-    p.V1[2] = S[2] * T[3] + S[4] * T[4] + S[5] * T[5];
-    p.a = T[0] * p.V0[0] + T[1] * p.V0[1] + T[2] * p.V0[2] + 0.3f;
-    p.b = T[0] * p.V1[0] + T[1] * p.V1[1] + T[2] * p.V1[2];
-    p.c = T[3] * p.V1[0] + T[4] * p.V1[1] + T[5] * p.V1[2] + 0.3f;
-    p.det = fmaf(p.a, p.c, -p.b * p.b);
+    const T *S = p.Sig;
+    const T *Tm = p.T2;
+    p.V0[0] = S[0] * Tm[0] + S[1] * Tm[1] + S[2] * Tm[2];
+    p.V0[1] = S[1] * Tm[0] + S[3] * Tm[1] + S[4] * Tm[2];
+    p.V0[2] = S[2] * Tm[0] + S[4] * Tm[1] + S[5] * Tm[2];
+    p.V1[0] = S[0] * Tm[3] + S[1] * Tm[4] + S[2] * Tm[5];
+    p.V1[1] = S[1] * Tm[3] + S[3] * Tm[4] + S[4] * Tm[5];
+    p.V1[2] = S[2] * Tm[3] + S[4] * Tm[4] + S[5] * Tm[5];
+    p.a = Tm[0] * p.V0[0] + Tm[1] * p.V0[1] + Tm[2] * p.V0[2] + T(0.3);
+    p.b = Tm[0] * p.V1[0] + Tm[1] * p.V1[1] + Tm[2] * p.V1[2];
+    p.c = Tm[3] * p.V1[0] + Tm[4] * p.V1[1] + Tm[5] * p.V1[2] + T(0.3);
+    p.det = fma_t(p.a, p.c, -p.b * p.b);
 }
 
 // Depth key: ((R20*mx + R21*my) + R22*mz) + t2, one correctly rounded fp32
@@ -248,17 +301,7 @@ __device__ __forceinline__ void gaussian_grads(int64_t i, const float *__restric
     constexpr int K = (DEG + 1) * (DEG + 1);
     const AccT *g = acc + (int64_t)i * GSR_ACC_STRIDE;
     const float mx = means[3 * i], my = means[3 * i + 1], mz = means[3 * i + 2];
-    const float tz = depth_of(cam, mx, my, mz);
-    Proj p;
-    project_splat(cam, mx, my, mz, tz, log_scales + 3 * i, quats + 4 * i, p);
-    float g5[5];
-    {
-        // the opacity and the conic as the forward computed them
-        const float o = 1.0f / (1.0f + expf(-opacity_logits[i]));
-        const float idet = 1.0f / p.det;
-        moments_to_grads(g, o, p.c * idet, -p.b * idet, p.a * idet, g5);
-    }
-    const float gu = g5[0], gv = g5[1], gA = g5[2], gB = g5[3], gC = g5[4], go = (float)g[5];
+    const float go = (float)g[5];
     const float grgb[3] = {(float)g[6], (float)g[7], (float)g[8]};
 
     // ---- colour: rgb = max(sum_k Y_k f_k + 0.5, 0) along d = (m - centre)/|m - centre| ----
@@ -300,81 +343,104 @@ __device__ __forceinline__ void gaussian_grads(int64_t i, const float *__restric
     gsh[1] = graw[1];
     gsh[2] = graw[2];
 
+    // fp64 geometry (see ProjT): camera-space position, covariance, Jacobian and conic
+    using D = double;
+    const D tz = fma((D)cam.R[6], (D)mx, fma((D)cam.R[7], (D)my, fma((D)cam.R[8], (D)mz, (D)cam.t[2])));
+    ProjT<D> p;
+    project_splat<D>(cam, (D)mx, (D)my, (D)mz, tz, log_scales + 3 * i, quats + 4 * i, p);
+    D g5[5];
+    {
+        // dL/d(mean2d, conic) from the moments, with the opacity and the conic in fp64
+        const D o = (D)(1.0f / (1.0f + expf(-opacity_logits[i])));
+        const D idet = recip64(p.det);
+        const D A = p.c * idet, B = -p.b * idet, C = p.a * idet;
+        const D m0 = (D)g[0], m1 = (D)g[1];
+        g5[0] = o * (A * m0 + B * m1);
+        g5[1] = o * (B * m0 + C * m1);
+        g5[2] = -0.5 * o * (D)g[2];
+        g5[3] = -o * (D)g[3];
+        g5[4] = -0.5 * o * (D)g[4];
+    }
+    const D gu = g5[0], gv = g5[1], gA = g5[2], gB = g5[3], gC = g5[4];
+
     // ---- conic (A,B,C) = (c, -b, a) / det  ->  2D covariance (a, b, c) ----
-    const float a = p.a, b = p.b, c = p.c;
-    const float id2 = 1.0f / (p.det * p.det);
-    const float ga = (-gA * c * c + gB * b * c - gC * b * b) * id2;
-    const float gb = (2.0f * gA * b * c - gB * (a * c + b * b) + 2.0f * gC * a * b) * id2;
-    const float gc = (-gA * b * b + gB * a * b - gC * a * a) * id2;
+    const D a = p.a, b = p.b, c = p.c;
+    const D idt = recip64(p.det), id2 = idt * idt;
+    const D ga = (-gA * c * c + gB * b * c - gC * b * b) * id2;
+    const D gb = (2.0 * gA * b * c - gB * (a * c + b * b) + 2.0 * gC * a * b) * id2;
+    const D gc = (-gA * b * b + gB * a * b - gC * a * a) * id2;
 
     // ---- Sigma2 = T2 Sigma T2^T: dSigma = T2^T G2 T2, dT2 = 2 G2 T2 Sigma, G2 = [[ga, gb/2],[gb/2, gc]] ----
-    const float *T = p.T2;
-    float dS[6];
+    const D *T = p.T2;
+    D dS[6];
     {
         const int rr[6] = {0, 0, 0, 1, 1, 2}, cc[6] = {0, 1, 2, 1, 2, 2};
 #pragma unroll
         for (int e = 0; e < 6; ++e) {
             const int r = rr[e], q = cc[e];
-            dS[e] = ga * T[r] * T[q] + 0.5f * gb * (T[r] * T[3 + q] + T[3 + r] * T[q]) + gc * T[3 + r] * T[3 + q];
+            dS[e] = ga * T[r] * T[q] + 0.5 * gb * (T[r] * T[3 + q] + T[3 + r] * T[q]) + gc * T[3 + r] * T[3 + q];
         }
     }
-    float dT0[3], dT1[3];
+    D dT0[3], dT1[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        dT0[k] = 2.0f * ga * p.V0[k] + gb * p.V1[k];
-        dT1[k] = gb * p.V0[k] + 2.0f * gc * p.V1[k];
+        dT0[k] = 2.0 * ga * p.V0[k] + gb * p.V1[k];
+        dT1[k] = gb * p.V0[k] + 2.0 * gc * p.V1[k];
     }
     // ---- T2 = J Rc ----
-    const float dJ00 = dT0[0] * cam.R[0] + dT0[1] * cam.R[1] + dT0[2] * cam.R[2];
-    const float dJ02 = dT0[0] * cam.R[6] + dT0[1] * cam.R[7] + dT0[2] * cam.R[8];
-    const float dJ11 = dT1[0] * cam.R[3] + dT1[1] * cam.R[4] + dT1[2] * cam.R[5];
-    const float dJ12 = dT1[0] * cam.R[6] + dT1[1] * cam.R[7] + dT1[2] * cam.R[8];
+    const D R0 = cam.R[0], R1 = cam.R[1], R2 = cam.R[2], R3 = cam.R[3], R4 = cam.R[4], R5 = cam.R[5];
+    const D R6 = cam.R[6], R7 = cam.R[7], R8 = cam.R[8];
+    const D dJ00 = dT0[0] * R0 + dT0[1] * R1 + dT0[2] * R2;
+    const D dJ02 = dT0[0] * R6 + dT0[1] * R7 + dT0[2] * R8;
+    const D dJ11 = dT1[0] * R3 + dT1[1] * R4 + dT1[2] * R5;
+    const D dJ12 = dT1[0] * R6 + dT1[1] * R7 + dT1[2] * R8;
     // ---- J(t) and (u,v)(t); a clamped coordinate passes no gradient through x/z ----
-    const float itz = 1.0f / tz, itz2 = itz * itz, itz3 = itz2 * itz;
-    const float fx = cam.fx, fy = cam.fy;
-    const float dtx = gu * fx * itz + (p.clx ? 0.0f : -fx * itz2 * dJ02);
-    const float dty = gv * fy * itz + (p.cly ? 0.0f : -fy * itz2 * dJ12);
-    const float dtz = -(gu * fx * p.tx + gv * fy * p.ty) * itz2 - fx * itz2 * dJ00 - fy * itz2 * dJ11 +
-                      dJ02 * fx * p.xc * itz3 * (p.clx ? 1.0f : 2.0f) +
-                      dJ12 * fy * p.yc * itz3 * (p.cly ? 1.0f : 2.0f);
+    const D itz = recip64(tz), itz2 = itz * itz, itz3 = itz2 * itz;
+    const D fx = cam.fx, fy = cam.fy;
+    const D dtx = gu * fx * itz + (p.clx ? 0.0 : -fx * itz2 * dJ02);
+    const D dty = gv * fy * itz + (p.cly ? 0.0 : -fy * itz2 * dJ12);
+    const D dtz = -(gu * fx * p.tx + gv * fy * p.ty) * itz2 - fx * itz2 * dJ00 - fy * itz2 * dJ11 +
+                  dJ02 * fx * p.xc * itz3 * (p.clx ? 1.0 : 2.0) +
+                  dJ12 * fy * p.yc * itz3 * (p.cly ? 1.0 : 2.0);
     // t = Rc m + tc
+    const D Rk[9] = {R0, R1, R2, R3, R4, R5, R6, R7, R8};
 #pragma unroll
-    for (int k = 0; k < 3; ++k) dm[k] += cam.R[k] * dtx + cam.R[3 + k] * dty + cam.R[6 + k] * dtz;
+    for (int k = 0; k < 3; ++k) dm[k] = (float)((D)dm[k] + Rk[k] * dtx + Rk[3 + k] * dty + Rk[6 + k] * dtz);
 
     // ---- Sigma = M M^T: dM = 2 dSigma M;  M = R diag(s) ----
-    const float dSf[9] = {dS[0], dS[1], dS[2], dS[1], dS[3], dS[4], dS[2], dS[4], dS[5]};
-    float dM[9];
+    const D dSf[9] = {dS[0], dS[1], dS[2], dS[1], dS[3], dS[4], dS[2], dS[4], dS[5]};
+    D dM[9];
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
         for (int q = 0; q < 3; ++q)
-            dM[3 * r + q] = 2.0f * (dSf[3 * r] * p.M[q] + dSf[3 * r + 1] * p.M[3 + q] + dSf[3 * r + 2] * p.M[6 + q]);
-    float dR[9], dls[3];
+            dM[3 * r + q] = 2.0 * (dSf[3 * r] * p.M[q] + dSf[3 * r + 1] * p.M[3 + q] + dSf[3 * r + 2] * p.M[6 + q]);
+    D dR[9], dls[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-        const float ds = dM[q] * p.R[q] + dM[3 + q] * p.R[3 + q] + dM[6 + q] * p.R[6 + q];
+        const D ds = dM[q] * p.R[q] + dM[3 + q] * p.R[3 + q] + dM[6 + q] * p.R[6 + q];
         dls[q] = ds * p.s[q];
 #pragma unroll
         for (int r = 0; r < 3; ++r) dR[3 * r + q] = dM[3 * r + q] * p.s[q];
     }
     // ---- R(qn) -> qn -> q (through the normalisation) ----
-    const float w = p.qn[0], x = p.qn[1], y = p.qn[2], z = p.qn[3];
-    float dq[4];
-    dq[0] = 2.f * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
-    dq[1] = 2.f * (y * dR[1] + z * dR[2] + y * dR[3] - 2.f * x * dR[4] - w * dR[5] + z * dR[6] + w * dR[7] -
-                   2.f * x * dR[8]);
-    dq[2] = 2.f * (-2.f * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] + z * dR[7] -
-                   2.f * y * dR[8]);
-    dq[3] = 2.f * (-2.f * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.f * z * dR[4] + y * dR[5] + x * dR[6] +
+    const D w = p.qn[0], x = p.qn[1], y = p.qn[2], z = p.qn[3];
+    D dq[4];
+    dq[0] = 2.0 * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+    dq[1] = 2.0 * (y * dR[1] + z * dR[2] + y * dR[3] - 2.0 * x * dR[4] - w * dR[5] + z * dR[6] + w * dR[7] -
+                   2.0 * x * dR[8]);
+    dq[2] = 2.0 * (-2.0 * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] + z * dR[7] -
+                   2.0 * y * dR[8]);
+    dq[3] = 2.0 * (-2.0 * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.0 * z * dR[4] + y * dR[5] + x * dR[6] +
                    y * dR[7]);
-    const float qd = dq[0] * w + dq[1] * x + dq[2] * y + dq[3] * z;
+    const D qd = dq[0] * w + dq[1] * x + dq[2] * y + dq[3] * z;
     const float op = 1.0f / (1.0f + expf(-opacity_logits[i]));
 #pragma unroll
-    for (int k = 0; k < 3; ++k) o[k] = dm[k], o[3 + k] = dls[k];
-    o[6] = (dq[0] - qd * w) * p.qinv;
-    o[7] = (dq[1] - qd * x) * p.qinv;
-    o[8] = (dq[2] - qd * y) * p.qinv;
-    o[9] = (dq[3] - qd * z) * p.qinv;
+    for (int k = 0; k < 3; ++k) o[k] = dm[k], o[3 + k] = (float)dls[k];
+    o[6] = (float)((dq[0] - qd * w) * p.qinv);
+    o[7] = (float)((dq[1] - qd * x) * p.qinv);
+    o[8] = (float)((dq[2] - qd * y) * p.qinv);
+    o[9] = (float)((dq[3] - qd * z) * p.qinv);
     o[10] = go * op * (1.0f - op);
 }
 
@@ -383,8 +449,8 @@ __device__ __forceinline__ void gaussian_grads(int64_t i, const float *__restric
 // cloud keeps about a quarter of them); each computed Gaussian leaves 11 gradients, its K basis
 // values and its 3 clamped colour gradients in an LDS row. Then the block writes its whole
 // segment of every output array, zeros for culled Gaussians included, as consecutive 16-byte
-// non-temporal stores (when the arrays are 16-byte aligned and the block is full; else one float
-// per lane and store). accumulate = 1 adds to the outputs instead.
+// non-temporal stores (one float per lane and store when unaligned); with accumulate = 1 it adds
+// to the visible rows only.
 constexpr int kA7Block = 256;
 
 template <int DEG>
@@ -394,24 +460,36 @@ struct A7Layout {
     static constexpr int PITCH = ROW | 1;       // odd: rows written by consecutive lanes hit distinct banks
 };
 
+enum { A7_ALL = 0, A7_ADD = 1 };
+
+// The block's segment of one [n, W] output (count rows; val(e) is float e of the segment, 0 for
+// culled rows). A7_ALL: every float, as consecutive 16-byte non-temporal stores when the output
+// is 16-byte aligned (one float per lane and store otherwise). A7_ADD: the visible rows only,
+// added to (the culled rows keep their values).
 template <int W, typename F>
-__device__ __forceinline__ void a7_write(float *__restrict__ dst, int count, bool vec, int accumulate, F &&val) {
-    // dst: this block's segment of one [n, W] array; count: Gaussians in the block
+__device__ __forceinline__ void a7_write(float *__restrict__ dst, int count, bool vec, int mode, const int16_t *slot,
+                                         F &&val) {
+    // No contraction: a value added to an output is rounded as written before the add, so the
+    // accumulating and the overwriting calls agree bit for bit (out + value).
+#pragma clang fp contract(off)
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    const int m = count * W;
+    if (mode == A7_ADD) {
+        for (int e = threadIdx.x; e < m; e += kA7Block)
+            if (slot[e / W] >= 0) dst[e] += val(e);
+        return;
+    }
+    int e0 = 0;
     if (vec) {
-        typedef float v4f __attribute__((ext_vector_type(4)));
         v4f *d4 = reinterpret_cast<v4f *>(dst);
-        constexpr int N4 = kA7Block * W / 4;
-        for (int c = threadIdx.x; c < N4; c += kA7Block) {
-            v4f v = {val(4 * c), val(4 * c + 1), val(4 * c + 2), val(4 * c + 3)};
-            if (accumulate) v += d4[c];
+        const int m4 = m / 4;
+        for (int c = threadIdx.x; c < m4; c += kA7Block) {
+            const v4f v = {val(4 * c), val(4 * c + 1), val(4 * c + 2), val(4 * c + 3)};
             __builtin_nontemporal_store(v, d4 + c);
         }
-    } else {
-        for (int e = threadIdx.x; e < count * W; e += kA7Block) {
-            const float v = val(e);
-            dst[e] = accumulate ? dst[e] + v : v;
-        }
+        e0 = m4 * 4;
     }
+    for (int e = e0 + threadIdx.x; e < m; e += kA7Block) dst[e] = val(e);
 }
 
 template <int DEG, typename AccT>
@@ -422,7 +500,7 @@ __global__ __launch_bounds__(kA7Block) void preprocess_bwd_kernel(int n, const f
                                                                   const float *__restrict__ sh, DevCamera cam,
                                                                   const int32_t *__restrict__ radius,
                                                                   const AccT *__restrict__ acc, gsr_grads out,
-                                                                  int accumulate, int aligned) {
+                                                                  int mode, int aligned) {
     using L = A7Layout<DEG>;
     constexpr int K = L::K, NS = 3 * K, PITCH = L::PITCH;
     __shared__ float s_row[kA7Block * PITCH];
@@ -448,9 +526,10 @@ __global__ __launch_bounds__(kA7Block) void preprocess_bwd_kernel(int n, const f
     s_slot[t] = vis ? (int16_t)rank : (int16_t)-1;
     if (vis) s_list[rank] = (int16_t)t;
     __syncthreads();
+    if (mode == A7_ADD && nv == 0) return;
 
-    // ---- chain rule of the visible ones on the first nv lanes ----
     if (t < nv) {
+        // ---- chain rule of the visible ones on the first nv lanes ----
         const int64_t i = g0 + s_list[t];
         float o[11], Y[K], g[3];
         gaussian_grads<DEG, AccT>(i, means, log_scales, quats, opacity_logits, sh, cam, acc, o, Y, g);
@@ -465,18 +544,18 @@ __global__ __launch_bounds__(kA7Block) void preprocess_bwd_kernel(int n, const f
     __syncthreads();
 
     // ---- the block's segment of each output array, culled rows as zeros ----
-    const bool vec = aligned && count == kA7Block;
+    const bool vec = aligned != 0;
     const auto field = [&](int W, int off) {
         return [=](int e) {
             const int s = s_slot[e / W];
             return s >= 0 ? s_row[s * PITCH + off + e % W] : 0.0f;
         };
     };
-    a7_write<3>(out.means3d + 3 * g0, count, vec, accumulate, field(3, 0));
-    a7_write<3>(out.log_scales + 3 * g0, count, vec, accumulate, field(3, 3));
-    a7_write<4>(out.quats + 4 * g0, count, vec, accumulate, field(4, 6));
-    a7_write<1>(out.opacity_logits + g0, count, vec, accumulate, field(1, 10));
-    a7_write<NS>(out.sh + NS * g0, count, vec, accumulate, [=](int e) {
+    a7_write<3>(out.means3d + 3 * g0, count, vec, mode, s_slot, field(3, 0));
+    a7_write<3>(out.log_scales + 3 * g0, count, vec, mode, s_slot, field(3, 3));
+    a7_write<4>(out.quats + 4 * g0, count, vec, mode, s_slot, field(4, 6));
+    a7_write<1>(out.opacity_logits + g0, count, vec, mode, s_slot, field(1, 10));
+    a7_write<NS>(out.sh + NS * g0, count, vec, mode, s_slot, [=](int e) {
         const int s = s_slot[e / NS];
         const int r = e % NS;
         return s >= 0 ? s_row[s * PITCH + 11 + r / 3] * s_row[s * PITCH + 11 + K + r % 3] : 0.0f;
@@ -510,10 +589,11 @@ hipError_t launch_preprocess_bwd(const gsr_scene &s, const DevCamera &cam, const
     const auto a16 = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
     const int aligned = a16(out.means3d) && a16(out.log_scales) && a16(out.quats) && a16(out.opacity_logits) &&
                         a16(out.sh);
+    const int mode = accumulate ? A7_ADD : A7_ALL;
 #define GSR_PB(D, A)                                                                                               \
     preprocess_bwd_kernel<D, A><<<blocks, kA7Block, 0, st>>>(s.n, s.means3d, s.log_scales, s.quats,                \
                                                               s.opacity_logits, s.sh, cam, radius,                 \
-                                                              static_cast<const A *>(acc), out, accumulate, aligned)
+                                                              static_cast<const A *>(acc), out, mode, aligned)
     if (acc_f64) {
         switch (s.sh_degree) {
         case 0: GSR_PB(0, double); break;

@@ -634,7 +634,7 @@ gsr_status bwd_enqueue(gsr_ctx *ctx, int nv, gsr_fwd *const *sts, const gsr_conf
         // Gaussians; a capacity-mode re-render leaves the count on the device.
         const gsr_fwd *sv = sts[v];
         GSR_HIP(ctx, launch_zero_visible_rows(sv->radius, sv->n, sv->p_known ? sv->sorted_ids_by_depth : nullptr,
-                                              sv->n_visible, sv->acc, f64, s));
+                                              sv->n_visible, plan.vb.v[v].acc, f64, s));
         sts[v]->acc_f64 = f64;
     }
     if (count) GSR_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t *>(sts[0]->counters), 0u, 160, s));
@@ -773,7 +773,8 @@ gsr_status check_batch_bwd(gsr_ctx *ctx, int32_t n_views, gsr_fwd *const *states
 gsr_status enqueue_params(gsr_ctx *ctx, int nv, gsr_fwd *const *states, const gsr_grads *outs, const int *adds) {
     for (int v = 0; v < nv; ++v) {
         gsr_fwd *st = states[v];
-        GSR_HIP(ctx, launch_preprocess_bwd(st->scene, st->dcam, st->radius, st->acc, st->acc_f64, outs[v], adds[v], ctx->stream));
+        GSR_HIP(ctx, launch_preprocess_bwd(st->scene, st->dcam, st->radius, st->acc, st->acc_f64, outs[v], adds[v],
+                                           ctx->stream));
     }
     return GSR_OK;
 }

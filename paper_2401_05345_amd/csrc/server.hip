@@ -45,6 +45,7 @@ struct Pending {
 struct Batch {
     std::vector<Pending> reqs;
     std::vector<int32_t> steps;
+    std::vector<Scene *> sc;          // each request's scene (the deque keeps them in place)
     std::vector<gsr_status> status;
     double t_start = 0.0;
 };
@@ -57,9 +58,9 @@ struct Lane {
     float *loss_host = nullptr;   // pinned, GSR_MAX_BATCH sums
     float *loss_dev = nullptr;
     bool busy = false;
-    bool has_batch = false;       // a launched batch waits for its completion thread
+    bool has_batch = false;       // a batch handed over by the scheduler waits for this lane's thread
     Batch batch;
-    std::thread waiter;
+    std::thread waiter;           // runs the lane's batches and stamps their completion
 };
 
 template <typename T>
@@ -126,7 +127,8 @@ int64_t request_bytes(const Scene &sc, const gsr_camera &cam) {
 }
 
 // Runs one batch on a lane: everything is enqueued on the lane's stream; the render
-// synchronises once on it (pair counts). Called by the scheduler thread without the lock.
+// synchronises once on it (pair counts). Called by the lane's own thread without the lock, so
+// the scheduler goes on admitting work for the other lanes meanwhile.
 void run_batch(gsr_server *S, Lane &L, Batch &b, std::vector<Scene *> &sc) {
     const int k = (int)b.reqs.size();
     gsr_ctx *c = L.ctx;
@@ -201,7 +203,6 @@ void scheduler_main(gsr_server *S) {
     while (true) {
         Lane *lane = nullptr;
         Batch b;
-        std::vector<Scene *> sc;
         // A request fits if its footprint fits beside the resident scenes and the requests in
         // flight; one that fits nowhere still runs when nothing else is in flight.
         const auto fits = [&](int64_t est, int64_t batch_bytes) {
@@ -244,7 +245,7 @@ void scheduler_main(gsr_server *S) {
             s.step += 1;
             b.reqs.push_back(*it);
             b.steps.push_back(s.step);
-            sc.push_back(&s);
+            b.sc.push_back(&s);
             it = S->queue.erase(it);
         }
         if (b.reqs.empty()) continue;
@@ -252,9 +253,6 @@ void scheduler_main(gsr_server *S) {
         lane->busy = true;
         b.status.assign(b.reqs.size(), GSR_OK);
         b.t_start = S->now();
-        lk.unlock();
-        run_batch(S, *lane, b, sc);
-        lk.lock();
         lane->batch = std::move(b);
         lane->has_batch = true;
         S->cv.notify_all();
@@ -270,6 +268,7 @@ void lane_main(gsr_server *S, Lane *L) {
         Batch &b = L->batch;
         const hipEvent_t ev = L->done;
         lk.unlock();
+        run_batch(S, *L, b, b.sc);
         (void)hipEventSynchronize(ev);
         const double t_done = S->now();
         lk.lock();

@@ -1,16 +1,16 @@
-"""Parity at full size: 3M Gaussians, 1920x1080, SH degree 3, in the launch
-configuration bench.py times (tile 16, LDS batch 256, wave reduce with
-nine-lane atomics). The oracle computes sampled outputs one by one: a set of
-tiles (random ones plus the longest lists) rendered pixel by pixel, and the
-gradients of sampled Gaussians whose every tile is in that set. Properties that
-hold at any size are checked on the whole frame."""
+"""Parity at full size: 3M Gaussians, 1920x1080, SH degree 3, camera inside the cloud, in the
+launch configuration bench.py times (tile 16, LDS batch 256, wave reduce with nine-lane atomics).
+The oracle renders and differentiates the whole frame in independent mode (every decision its
+own, in fp64): every pixel whose decisions agree is compared, and all five gradient tensors are
+compared whole, with the L1 loss gradient against the view's U(0,1) target."""
 import numpy as np
 import pytest
 
 import oracle
 from paper_2401_05345_amd import gsr
 from paper_2401_05345_amd import scenegen as sg
-from gpu_util import GpuScene, run_render, run_backward, rel_l2, say, geometric_ties, TIE_PIXEL
+from gpu_util import (GpuScene, run_render, run_backward, rel_l2, say, check_forward, check_grads,
+                      oracle_dl_dimage, NAMES)
 
 pytestmark = pytest.mark.gpu
 
@@ -24,13 +24,8 @@ def renderer(gsr):
     r.close()
 
 
-class _Vis:
-    def __init__(self, n):
-        self.visible = np.ones(n, bool)
-
-
-def test_large_3m_1080p_sampled_parity(renderer):
-    say("[gpu] large_3m sampled parity: generating")
+def test_large_3m_1080p_full_frame_parity(renderer):
+    say("[gpu] large_3m full-frame parity: generating")
     wl = sg.large_3m()
     cam = wl.camera
     gs = GpuScene(wl.scene, cam)
@@ -38,75 +33,47 @@ def test_large_3m_1080p_sampled_parity(renderer):
     say("[gpu] large_3m render")
     st, out = run_render(renderer, gs, cfg)
     try:
-        H, W = cam.height, cam.width
         P = int(out["stats"].n_pairs)
-        # ---- properties of the whole frame ----
+        # ---- properties of the whole list ----
         assert int(out["tiles_touched"].astype(np.int64).sum()) == P
         rgs = out["ranges"].astype(np.int64)
         nonempty = rgs[:, 1] > rgs[:, 0]
         order = np.argsort(rgs[nonempty, 0])
         starts, ends = rgs[nonempty][order, 0], rgs[nonempty][order, 1]
         assert starts[0] == 0 and ends[-1] == P and np.array_equal(starts[1:], ends[:-1])
-        ids = out["sorted_ids"].astype(np.int64)
-        tile_of = np.repeat(np.nonzero(nonempty)[0][order], ends - starts)
-        key = out["depth"].view(np.uint32)[ids].astype(np.int64)
-        # lexicographic (tile, depth bits, id) strictly increasing along the list
-        step = np.stack([np.diff(tile_of), np.diff(key), np.diff(ids)], 1)
-        first_nz = np.where(step[:, 0] != 0, step[:, 0], np.where(step[:, 1] != 0, step[:, 1], step[:, 2]))
-        assert (first_nz > 0).all()
         assert out["T_final"].min() >= 1e-4 and np.isfinite(out["image"]).all()
 
-        # ---- sampled outputs against the oracle ----
-        say("[gpu] large_3m oracle projection")
-        pr = oracle.project(wl.scene, cam, 16)
-        gx, gy = pr.grid
-        rng = np.random.default_rng(17)
-        lengths = (rgs[:, 1] - rgs[:, 0])
-        cand = np.nonzero(lengths > 0)[0]
-        tiles = set(rng.choice(cand, 16, replace=False).tolist()) | set(np.argsort(lengths)[-3:].tolist())
-        small = np.nonzero(pr.visible & (pr.tiles_touched <= 4) & (out["radius"] == pr.radius)
-                           & (out["tiles_touched"] == pr.tiles_touched))[0]
-        picked = np.sort(rng.choice(small, 40, replace=False))
-        for g in picked:
-            x0, x1, y0, y1 = pr.rect[g]
-            tiles |= {ty * gx + tx for ty in range(y0, y1) for tx in range(x0, x1)}
-        sel = np.zeros(gx * gy, np.uint8)
-        sel[list(tiles)] = 1
-        # The depth sort key is the same fp32 formula on both sides: bit-exact for all listed Gaussians.
-        both = pr.visible & (out["radius"] > 0)
-        assert np.array_equal(out["depth"][both].view(np.uint32), pr.depth_key[both].view(np.uint32))
-        say(f"[gpu] large_3m oracle render of {len(tiles)} tiles")
-        rr = oracle.render(wl.scene, cam, 16, tile_select=sel)
-        _, tie_tiles = geometric_ties(rr, out)
-        pix_sel = np.repeat(np.repeat(sel.reshape(gy, gx), 16, 0), 16, 1)[:H, :W].astype(bool)
-        ties = rr.margin < TIE_PIXEL
-        for tx, ty in tie_tiles:
-            ties[ty * 16:(ty + 1) * 16, tx * 16:(tx + 1) * 16] = True
-        keep = pix_sel & ~ties
-        assert keep.sum() >= 0.98 * pix_sel.sum()
-        for t in tiles:
-            if (t % gx, t // gx) in tie_tiles:
-                continue
-            a, b = out["ranges"][t]
-            assert np.array_equal(out["sorted_ids"][a:b], rr.lists.ids[rr.lists.tile_start[t]:rr.lists.tile_start[t + 1]])
-        assert np.array_equal(out["n_contrib"][keep], rr.n_contrib[keep])
-        err = rel_l2(out["image"][:, keep], rr.image[:, keep])
-        say(f"[gpu] large_3m image rel-L2 on {keep.sum()} sampled pixels: {err:.3e}")
-        assert err <= 1e-5
+        # ---- the whole frame against the oracle ----
+        say("[gpu] large_3m oracle render (all tiles)")
+        rr = oracle.render(wl.scene, cam, 16)
+        img_err, ties = check_forward(out, rr, 16)
+        say(f"[gpu] large_3m image rel-L2 {img_err:.3e} on {int((~ties).sum())} pixels, "
+            f"{int(ties.sum())} left out (flipped near-ties and tie tiles)")
 
+        # Gradients of the same function on both sides: dL/dI is zeroed at the pixels where several
+        # forward results are valid (flipped near-ties, tie tiles), so no flipped decision enters
+        # either side's sums; every Gaussian is compared. The errors with the unmasked dL/dI (which
+        # also carry the flipped decisions' genuine differences) are reported beside them.
+        dl_all = oracle_dl_dimage(rr, wl.target, "l1")
+        dl = np.where(ties[None], np.float32(0.0), dl_all).astype(np.float32)
+        say("[gpu] large_3m oracle backward")
+        acc_ref, grads_ref = oracle.backward(wl.scene, rr, dl.astype(np.float64))
         say("[gpu] large_3m backward")
-        dl = (np.random.default_rng(18).standard_normal((3, H, W)) * 1e-6).astype(np.float32)
         grads, acc, _ = run_backward(renderer, gs, st, dl, cfg)
-        acc_ref = oracle.composite_backward(rr, dl.astype(np.float64))
-        e_acc = rel_l2(acc[picked], acc_ref[picked, :9])
-        sub = wl.scene.subset(picked)
-        g_ref = oracle.params_backward(sub, cam, _Vis(len(picked)), acc_ref[picked])
-        errs = {n: rel_l2(g[picked], r) for n, g, r in
-                zip(("means3d", "log_scales", "quats", "opacity_logits", "sh"), grads, g_ref)}
-        say(f"[gpu] large_3m sampled-Gaussian acc rel-L2 {e_acc:.3e}, grads {errs}")
-        assert e_acc <= 1e-3
-        for n, e in errs.items():
-            assert e <= 1e-3, (n, e)
+        errs = check_grads(grads, acc, acc_ref[:, :9], grads_ref)
+        say(f"[gpu] large_3m full-tensor gradients rel-L2 (tie pixels masked) {errs}")
+        acc_u, grads_u = oracle.backward(wl.scene, rr, dl_all.astype(np.float64))
+        gu, accu, _ = run_backward(renderer, gs, st, dl_all, cfg)
+        say("[gpu] large_3m unmasked dL/dI, rel-L2 " +
+            str({n: round(rel_l2(a, b), 7) for n, a, b in zip(NAMES, gu, grads_u)}))
+        # The screen-filling splats: every one sums ~1e4 wave partials with heavy cancellation.
+        big = np.argsort(np.where(rr.proj.visible, rr.proj.tiles_touched, -1))[-100:]
+        per = np.array([rel_l2(acc[g], acc_ref[g, :9]) for g in big])
+        pg = np.array([rel_l2(np.concatenate([x[g].ravel() for x in grads]),
+                              np.concatenate([x[g].ravel() for x in grads_ref])) for g in big])
+        say(f"[gpu] large_3m 100 largest splats ({int(rr.proj.tiles_touched[big].min())}-"
+            f"{int(rr.proj.tiles_touched[big].max())} tiles): accumulator rel err max {per.max():.2e} "
+            f"median {np.median(per):.2e}; parameter-gradient rel err max {pg.max():.2e} median {np.median(pg):.2e}")
 
         # The plain-atomic kernel gives the same sums on the whole frame: with the default fp64
         # accumulators up to the fp32 rounding of each wave's sum, with fp32 accumulators (the
@@ -119,5 +86,9 @@ def test_large_3m_1080p_sampled_parity(renderer):
         e64, e32 = rel_l2(acc_plain, acc), rel_l2(acc32p, acc32)
         say(f"[gpu] large_3m acc plain vs reduce: fp64 accumulators {e64:.2e}, fp32 accumulators {e32:.2e}")
         assert e64 <= 1e-5 and e32 <= 1e-5
+        # Each large splat's nine sums within 1e-3 of the oracle's (its parameter gradients are
+        # reported: for near-isotropic splats the rotation gradient is a small difference of large
+        # terms, so its own relative error is no measure of the accumulation).
+        assert per.max() <= 1e-3
     finally:
         gsr.gsr_fwd_release(renderer.ctx, st)

@@ -14,13 +14,10 @@ import pytest
 import oracle
 from paper_2401_05345_amd import gsr
 from paper_2401_05345_amd import scenegen as sg
-from gpu_util import (GpuScene, run_render, run_backward, tie_pixels, geometric_ties, oracle_dl_dimage,
-                      rel_l2, say)
+from gpu_util import (GpuScene, run_render, run_backward, oracle_dl_dimage, rel_l2, say,
+                      check_forward as _check_forward, check_grads as _check_grads, NAMES)
 
 pytestmark = pytest.mark.gpu
-
-NAMES = ["means3d", "log_scales", "quats", "opacity_logits", "sh"]
-
 
 @pytest.fixture(scope="module")
 def renderer(gsr):
@@ -29,60 +26,6 @@ def renderer(gsr):
     yield r
     torch.cuda.synchronize()
     r.close()
-
-
-def _check_forward(out, rr, tile):
-    pr = rr.proj
-    # radius / tile counts: exact, except Gaussians sitting on a geometric tie (checked inside).
-    differ, _ = geometric_ties(rr, out)
-    assert differ.size <= max(3, 0.002 * pr.n), differ.size
-    same = np.ones(pr.n, bool)
-    same[differ] = False
-    # depth key: the same fp32 formula on both sides, so bit-exact for every listed Gaussian.
-    vis = pr.visible & same
-    assert np.array_equal(out["depth"][vis].view(np.uint32), pr.depth_key[vis].view(np.uint32))
-    assert np.array_equal(out["radius"] > 0, pr.visible | ~same) or differ.size > 0
-    # projected values (fp32 vs fp64)
-    v = np.nonzero(pr.visible & (out["radius"] > 0))[0]
-    assert rel_l2(out["mean2d"][v], pr.mean2d[v]) < 1e-6
-    assert rel_l2(out["conic_opacity"][v, :3], pr.conic[v]) < 2e-6
-    assert rel_l2(out["conic_opacity"][v, 3], pr.opacity[v]) < 1e-6
-    assert rel_l2(out["rgb"][v], pr.rgb[v]) < 1e-6
-    assert np.array_equal(out["clamp_mask"][v], pr.clamp_mask[v])
-    # lists: exact per tile unless a geometric tie changes the tile's membership
-    _, tie_tiles = geometric_ties(rr, out)
-    ties = tie_pixels(rr, out)
-    gx, gy = pr.grid
-    bad_tiles = 0
-    for t in range(gx * gy):
-        a, b = out["ranges"][t]
-        o0, o1 = rr.lists.tile_start[t], rr.lists.tile_start[t + 1]
-        if (t % gx, t // gx) in tie_tiles:
-            continue
-        if not np.array_equal(out["sorted_ids"][a:b], rr.lists.ids[o0:o1]):
-            bad_tiles += 1
-    assert bad_tiles == 0
-    assert len(tie_tiles) <= max(2, 0.01 * gx * gy)
-    # per-pixel decisions and the image
-    keep = ~ties
-    assert ties.mean() < 0.01, ties.mean()
-    assert np.array_equal(out["n_contrib"][keep], rr.n_contrib[keep])
-    assert rel_l2(out["T_final"][keep], rr.T_final[keep]) < 1e-5
-    img_err = rel_l2(out["image"][:, keep], rr.image[:, keep])
-    assert img_err <= 1e-5, img_err
-    assert np.isfinite(out["image"]).all()
-    return img_err, ties
-
-
-def _check_grads(grads_gpu, acc_gpu, acc_ref, grads_ref, tol=1e-3):
-    errs = {}
-    for name, g, ref in zip(NAMES, grads_gpu, grads_ref):
-        assert np.isfinite(g).all(), name
-        errs[name] = rel_l2(g, ref)
-        assert errs[name] <= tol, (name, errs[name])
-    errs["acc9"] = rel_l2(acc_gpu, acc_ref)
-    assert errs["acc9"] <= tol
-    return errs
 
 
 def _workload_tiny():
