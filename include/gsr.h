@@ -255,6 +255,30 @@ gsr_status gsr_backward_composite(gsr_ctx *ctx, gsr_fwd *state, const float *dl_
  * written with wider stores). */
 gsr_status gsr_backward_params(gsr_ctx *ctx, gsr_fwd *state, const gsr_grads *out, int accumulate);
 
+/* Largest state gsr_backward_noalloc takes: Gaussians, and tiles of the view. */
+#define GSR_NOALLOC_MAX_GAUSSIANS 524288
+#define GSR_NOALLOC_MAX_TILES 65536
+
+/* gsr_backward without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc). Same arguments, kernels and results as gsr_backward;
+ * the per-Gaussian accumulator rows (and, when the state has none cached, the
+ * backward's tile order) live in a fixed scratch area that the library holds
+ * on each GPU it runs on until the process ends: 64 MiB of rows
+ * (GSR_NOALLOC_MAX_GAUSSIANS x GSR_ACC_STRIDE doubles) plus 512 KiB of tile
+ * order. The rows the kernels add into are cleared at the start of every
+ * call; the area keeps the last call's sums afterwards.
+ * Errors: GSR_EINVAL (before anything is enqueued) when the state has more
+ * than GSR_NOALLOC_MAX_GAUSSIANS Gaussians or GSR_NOALLOC_MAX_TILES tiles, or
+ * when config asks for GSR_FLAG_DEBUG_COUNTERS (their buffer is allocated);
+ * GSR_EHIP when the scratch area's address could not be obtained at context
+ * creation. Every call on one GPU shares that GPU's area: calls that overlap
+ * on one GPU (two streams or two host threads) race and must be serialised by
+ * the caller. The sums stay in the shared area, so gsr_backward_params and
+ * the `acc` export of this state do not see them. */
+gsr_status gsr_backward_noalloc(gsr_ctx *ctx, gsr_fwd *state, const float *dl_dimage_chw,
+                                const gsr_grads *out, int accumulate, const gsr_config *config);
+
 /* Most views one batched call takes. */
 #define GSR_MAX_BATCH 16
 

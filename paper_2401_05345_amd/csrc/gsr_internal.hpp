@@ -199,6 +199,8 @@ struct gsr_ctx {
     hipEvent_t ev[12] = {};
     hipEvent_t ev_counts = nullptr;  // counts of a render read back (no timing)
     bool timing_render = false, timing_bwd = false;
+    void *scratch = nullptr;         // this device's fixed scratch area (gsr_backward_noalloc)
+    hipError_t scratch_err = hipSuccess;
 };
 
 struct gsr_fwd {

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -145,6 +146,41 @@ void mark(gsr_ctx *ctx, bool on, int ev) {
 
 } // namespace
 
+// Fixed scratch of the allocation-free backward: the accumulator rows, then the tile order.
+// Every GPU holds its own copy at its own address; host code uses only that address (the
+// array's name is a host-side stand-in), taken once per device at context creation.
+constexpr size_t kNoallocRowBytes = size_t(GSR_NOALLOC_MAX_GAUSSIANS) * GSR_ACC_STRIDE * sizeof(double);
+constexpr size_t kNoallocOrderBytes = size_t(GSR_NOALLOC_MAX_TILES) * sizeof(uint2);
+static __device__ __align__(256) unsigned char scratch[kNoallocRowBytes + kNoallocOrderBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// With ctx->device current: this device's scratch address, looked up on its first context.
+void scratch_init(gsr_ctx *ctx) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (ctx->device >= kMaxDevices) {
+        ctx->scratch_err = hipErrorInvalidDevice;
+        return;
+    }
+    if (!g_scratch_ptr[ctx->device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            ctx->scratch_err = e != hipSuccess ? e : hipErrorInvalidSymbol;
+            (void)hipGetLastError();
+            return;
+        }
+        g_scratch_ptr[ctx->device] = p;
+    }
+    ctx->scratch = g_scratch_ptr[ctx->device];
+}
+
+} // namespace
+
 extern "C" {
 
 const char *gsr_version(void) { return "gsr 0.1 gfx950"; }
@@ -216,6 +252,7 @@ gsr_status gsr_ctx_create(gsr_ctx **out, int device, void *hip_stream) {
         return GSR_ENOMEM;
     }
     ctx->host_pinned = static_cast<uint32_t *>(hp);
+    scratch_init(ctx);
     for (auto &e : ctx->ev) {
         if (hipEventCreate(&e) != hipSuccess) {
             gsr_ctx_destroy(ctx);
@@ -573,6 +610,7 @@ struct BwdPlan {
     uint2 *work = nullptr;   // table the composite reads (nullptr: identity / XCD remap, one view)
     bool build_work = false; // recompute `work` before the composite
     int remap = 0;
+    bool own_acc = true;     // accumulators are the states' own rows (not the fixed scratch)
 };
 
 gsr_status bwd_prepare(gsr_ctx *ctx, int nv, gsr_fwd *const *sts, const float *const *dls, const gsr_config *cfg,
@@ -635,7 +673,7 @@ gsr_status bwd_enqueue(gsr_ctx *ctx, int nv, gsr_fwd *const *sts, const gsr_conf
         const gsr_fwd *sv = sts[v];
         GSR_HIP(ctx, launch_zero_visible_rows(sv->radius, sv->n, sv->p_known ? sv->sorted_ids_by_depth : nullptr,
                                               sv->n_visible, plan.vb.v[v].acc, f64, s));
-        sts[v]->acc_f64 = f64;
+        if (plan.own_acc) sts[v]->acc_f64 = f64;
     }
     if (count) GSR_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t *>(sts[0]->counters), 0u, 160, s));
     mark(ctx, tm, EV_B1);
@@ -655,6 +693,31 @@ gsr_status bwd_views(gsr_ctx *ctx, int nv, gsr_fwd *const *sts, const float *con
     BwdPlan plan;
     GSR_TRY(bwd_prepare(ctx, nv, sts, dls, cfg, plan));
     return bwd_enqueue(ctx, nv, sts, cfg, plan, tm);
+}
+
+// The plan of a single-view backward whose accumulators and (when the state caches none) tile
+// order are in the fixed scratch: makes no buffer.
+void bwd_plan_scratch(gsr_ctx *ctx, gsr_fwd *st, const float *dl, const gsr_config *cfg, BwdPlan &plan) {
+    ViewBatch &vb = plan.vb;
+    vb = ViewBatch{};
+    vb.n = 1;
+    vb.v[0] = desc_of(st, nullptr, dl);
+    vb.v[0].acc = ctx->scratch;
+    vb.base[1] = (uint32_t)st->n_tiles;
+    const bool ordered = !(cfg->flags & (GSR_FLAG_XCD_REMAP | GSR_FLAG_NO_TILE_ORDER));
+    plan.order_mode = ordered ? (st->tile_walk ? ORDER_BY_WALK : ORDER_BY_LENGTH) : ORDER_IDENTITY;
+    plan.remap = (cfg->flags & GSR_FLAG_XCD_REMAP) ? 1 : 0;
+    plan.work = nullptr;
+    plan.build_work = false;
+    plan.own_acc = false;
+    if (ordered) {
+        if (st->order_bwd) {
+            plan.work = st->order_bwd;
+        } else {
+            plan.work = reinterpret_cast<uint2 *>(static_cast<unsigned char *>(ctx->scratch) + kNoallocRowBytes);
+            plan.build_work = true;
+        }
+    }
 }
 
 gsr_status check_bwd_args(gsr_ctx *ctx, gsr_fwd *st, const float *dl, const gsr_config **cfg) {
@@ -737,6 +800,36 @@ gsr_status gsr_backward(gsr_ctx *ctx, gsr_fwd *st, const float *dl_dimage_chw, c
     const bool tm = (config->flags & GSR_FLAG_STAGE_TIMING) != 0;
     GSR_TRY(bwd_views(ctx, 1, &st, &dl_dimage_chw, config, tm));
     GSR_HIP(ctx, launch_preprocess_bwd(st->scene, st->dcam, st->radius, st->acc, st->acc_f64, *out, accumulate ? 1 : 0,
+                                       ctx->stream));
+    mark(ctx, tm, EV_B3);
+    ctx->timing_bwd = tm;
+    return GSR_OK;
+}
+
+gsr_status gsr_backward_noalloc(gsr_ctx *ctx, gsr_fwd *st, const float *dl_dimage_chw, const gsr_grads *out,
+                                int accumulate, const gsr_config *config) {
+    if (!ctx) return GSR_EINVAL;
+    ctx->err.clear();
+    GSR_TRY(check_bwd_args(ctx, st, dl_dimage_chw, &config));
+    GSR_TRY(check_grads(ctx, st, out));
+    if (config->flags & GSR_FLAG_DEBUG_COUNTERS)
+        return fail(ctx, GSR_EINVAL, "debug counters need an allocated buffer (use gsr_backward)");
+    if (st->n > GSR_NOALLOC_MAX_GAUSSIANS)
+        return fail(ctx, GSR_EINVAL, "%lld Gaussians exceed the allocation-free backward's %d",
+                    (long long)st->n, GSR_NOALLOC_MAX_GAUSSIANS);
+    if (st->n_tiles > GSR_NOALLOC_MAX_TILES)
+        return fail(ctx, GSR_EINVAL, "%lld tiles exceed the allocation-free backward's %d", (long long)st->n_tiles,
+                    GSR_NOALLOC_MAX_TILES);
+    if (!ctx->scratch)
+        return fail(ctx, GSR_EHIP, "scratch address of device %d unavailable: %s", ctx->device,
+                    hipGetErrorString(ctx->scratch_err));
+    GSR_HIP(ctx, hipSetDevice(ctx->device));
+    const bool tm = (config->flags & GSR_FLAG_STAGE_TIMING) != 0;
+    BwdPlan plan;
+    bwd_plan_scratch(ctx, st, dl_dimage_chw, config, plan);
+    GSR_TRY(bwd_enqueue(ctx, 1, &st, config, plan, tm));
+    const bool f64 = (config->flags & GSR_FLAG_ACC_F32) == 0;
+    GSR_HIP(ctx, launch_preprocess_bwd(st->scene, st->dcam, st->radius, ctx->scratch, f64, *out, accumulate ? 1 : 0,
                                        ctx->stream));
     mark(ctx, tm, EV_B3);
     ctx->timing_bwd = tm;

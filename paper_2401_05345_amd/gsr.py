@@ -27,6 +27,8 @@ GSR_FLAG_ACC_F32 = 32
 GSR_MAX_BATCH = 16
 GSR_EBUDGET = -5
 GSR_ACC_STRIDE = 16
+GSR_NOALLOC_MAX_GAUSSIANS = 524288
+GSR_NOALLOC_MAX_TILES = 65536
 (GSR_MB_COPY, GSR_MB_ATOMIC_F32_DISTINCT, GSR_MB_ATOMIC_F64_DISTINCT, GSR_MB_ATOMIC_F32_SAME_ADDRESS,
  GSR_MB_ATOMIC_F32_ONE_LANE, GSR_MB_ATOMIC_F64_NINE_LANES, GSR_MB_WRITE, GSR_MB_READ, GSR_MB_COPY_NT,
  GSR_MB_GATHER48) = range(10)
@@ -124,6 +126,8 @@ _PROTOS = {
                              ctypes.POINTER(gsr_config), c_void_p, ctypes.POINTER(c_void_p)]),
     "gsr_backward": (c_int32, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(gsr_grads), c_int32,
                                ctypes.POINTER(gsr_config)]),
+    "gsr_backward_noalloc": (c_int32, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(gsr_grads), c_int32,
+                                       ctypes.POINTER(gsr_config)]),
     "gsr_render_batch": (c_int32, [c_void_p, c_int32, ctypes.POINTER(gsr_scene), ctypes.POINTER(gsr_camera),
                                    ctypes.POINTER(gsr_config), ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p)]),
     "gsr_backward_batch": (c_int32, [c_void_p, c_int32, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p),
@@ -286,6 +290,12 @@ def gsr_render(ctx, scene: gsr_scene, cam: gsr_camera, cfg: gsr_config, image):
 def gsr_backward(ctx, state, dl_dimage, grads: gsr_grads, accumulate: int = 0, cfg: gsr_config | None = None):
     _check(ctx, load().gsr_backward(ctx, state, _ptr(dl_dimage), ctypes.byref(grads), int(accumulate),
                                     ctypes.byref(cfg) if cfg is not None else None))
+
+
+def gsr_backward_noalloc(ctx, state, dl_dimage, grads: gsr_grads, accumulate: int = 0,
+                         cfg: gsr_config | None = None):
+    _check(ctx, load().gsr_backward_noalloc(ctx, state, _ptr(dl_dimage), ctypes.byref(grads), int(accumulate),
+                                            ctypes.byref(cfg) if cfg is not None else None))
 
 
 def gsr_render_batch(ctx, scenes, cams, cfg: gsr_config, images):
