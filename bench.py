@@ -299,7 +299,8 @@ def profile_multi_view(flags, spec, steps, warmup):
     dev = torch.device("cuda:0")
     st_t = [[torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in s.arrays()] for s in mv.scenes]
     structs = [gsr.make_scene(*t, s.sh_degree) for t, s in zip(st_t, mv.scenes)]
-    gstructs = [gsr.make_grads(*[torch.zeros_like(x) for x in t]) for t in st_t]
+    grads_t = [[torch.zeros_like(x) for x in t] for t in st_t]   # held: the structs keep bare pointers
+    gstructs = [gsr.make_grads(*g) for g in grads_t]
     scenes, cams, targets, imgs, dls, outs = [], [], [], [], [], []
     for si, c, tgt in mv.views:
         scenes.append(structs[si])
