@@ -49,7 +49,7 @@ BYTES_PER_PIXEL = 20              # dL/dI (12) + T_final (4) + n_contrib (4)
 BYTES_PER_VISIBLE = 72            # nine fp64 sums written back once (their clearing excluded; a7 reads them)
 
 
-MODES = {"reduce": 1, "plain": 0, "serial": 2, "block": 3}   # gsr_bwd_mode values
+MODES = {"reduce": 1, "plain": 0, "serial": 2, "block": 3, "compiler": 4}   # gsr_bwd_mode values
 
 
 def log(*a):
@@ -477,7 +477,8 @@ def source_hash(files=("k_composite.hip", "device_common.hpp")):
 def ab_legs(b, thr, iters, full=True):
     """Backward A/B on one forward state: the plain-atomic kernel with fp32 accumulators (the
     paper's baseline), the same with fp64 accumulators, and the wave-reduced kernel with both;
-    with `full`, the serial-leader and block-level reductions too. Medians in ms."""
+    with `full`, the serial-leader and block-level reductions and the plain source built with the
+    compiler's own atomic reduction too. Medians in ms."""
     gsr = b.gsr
     F32 = gsr.GSR_FLAG_ACC_F32
     fr = b.forward_state(b.cfg(gsr.GSR_BWD_WAVE_REDUCE, thr))
@@ -488,7 +489,9 @@ def ab_legs(b, thr, iters, full=True):
             ("plain_f64", gsr.GSR_BWD_PLAIN_ATOMIC, 0, 0, max(3, iters // 4))]
     if full:
         legs += [("serial_f64", gsr.GSR_BWD_SERIAL_REDUCE, thr, 0, iters),
-                 ("block_f64", gsr.GSR_BWD_BLOCK_REDUCE, thr, 0, iters)]
+                 ("block_f64", gsr.GSR_BWD_BLOCK_REDUCE, thr, 0, iters),
+                 ("compiler_f64", gsr.GSR_BWD_PLAIN_COMPILER_REDUCE, 0, 0, max(3, iters // 4)),
+                 ("compiler_f32", gsr.GSR_BWD_PLAIN_COMPILER_REDUCE, 0, F32, max(3, iters // 4))]
     for name, mode, t, flags, n in legs:
         z = []
         a6, a7 = b.backward_only(fr, b.cfg(mode, t, flags), n, z)
@@ -534,8 +537,11 @@ def ab_summary(res, cnt, stats, thr, sweep):
     if "serial_f64" in res:
         out["composite_bwd_by_mode_ms"] = {
             "f64_accumulators": {"wave_reduce": round(r6, 4), "serial_leader": round(res["serial_f64"][0], 4),
-                                 "block_lds": round(res["block_f64"][0], 4), "plain_atomic": round(q6, 4)},
-            "f32_accumulators": {"wave_reduce": round(w6, 4), "plain_atomic": round(p6, 4)}}
+                                 "block_lds": round(res["block_f64"][0], 4), "plain_atomic": round(q6, 4),
+                                 "plain_compiler_reduced": round(res["compiler_f64"][0], 4)},
+            "f32_accumulators": {"wave_reduce": round(w6, 4), "plain_atomic": round(p6, 4),
+                                 "plain_compiler_reduced": round(res["compiler_f32"][0], 4)}}
+        out["speedup_composite_bwd_vs_compiler_reduced"] = round(res["compiler_f64"][0] / r6, 3)
         out["lane_atomics_block_lds"] = int(cnt["block"].lane_atomics)
         out["atomic_instrs_block_lds"] = int(cnt["block"].atomic_instrs)
     return out

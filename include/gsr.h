@@ -49,8 +49,13 @@ typedef enum {
     GSR_BWD_WAVE_REDUCE = 1,  /* wave reduction + one lane's atomics when active lanes >= threshold */
     GSR_BWD_SERIAL_REDUCE = 2, /* ablation: the sums built one active lane at a time (readlane loop, the
                                   paper's serialised SW-S form) when active lanes >= threshold; lanes 0..8 issue */
-    GSR_BWD_BLOCK_REDUCE = 3  /* extension: waves at or above the threshold reduce into LDS; the
+    GSR_BWD_BLOCK_REDUCE = 3, /* extension: waves at or above the threshold reduce into LDS; the
                                  block issues one atomic per (tile, Gaussian, value) after each LDS batch */
+    GSR_BWD_PLAIN_COMPILER_REDUCE = 4 /* ablation: the plain-atomic kernel's source compiled with the
+                                 compiler's own rewrite of atomics to one address (LLVM's atomic
+                                 optimizer, DPP strategy): each of the nine adds becomes a reduction over
+                                 the active lanes and one lane's atomic. The threshold is ignored and
+                                 GSR_FLAG_DEBUG_COUNTERS is rejected (GSR_EINVAL) for this mode */
 } gsr_bwd_mode;
 
 enum {

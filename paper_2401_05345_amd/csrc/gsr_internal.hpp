@@ -163,6 +163,9 @@ struct BwdParams {
 hipError_t launch_composite_bwd(const ViewBatch &vb, int tile, int lds_batch, int remap, int mode, bool count,
                                 bool lane_split, bool acc_f64, const BwdParams &p, const uint2 *work,
                                 hipStream_t st);
+// The plain-atomic a6 built with the compiler's atomic optimizer (k_composite_compiler_reduce.hip).
+hipError_t launch_composite_bwd_compiler_reduce(const ViewBatch &vb, int tile, int lds_batch, int remap,
+                                                bool acc_f64, const BwdParams &p, const uint2 *work, hipStream_t st);
 
 hipError_t launch_l1_grad(const float *image, const float *target, int64_t count, float *out, hipStream_t st);
 

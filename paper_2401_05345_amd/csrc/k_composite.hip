@@ -672,6 +672,7 @@ hipError_t bwd_t(const ViewBatch &vb, int remap, int mode, bool count, bool spli
 
 } // namespace
 
+#ifndef GSR_COMPOSITE_COMPILER_REDUCE
 hipError_t launch_order_tiles(const ViewBatch &vb, int mode, uint2 *work, hipStream_t st) {
     if (vb.n <= 0 || vb.base[vb.n] == 0) return hipSuccess;
     order_tiles_kernel<<<1, 1024, 0, st>>>(vb, mode, work);
@@ -735,5 +736,42 @@ hipError_t launch_wave_reduce_selftest(const float *vals, const uint8_t *active,
                                                                                         sums, lane_atomics);
     return hipGetLastError();
 }
+
+#else
+// This file compiled a second time with the compiler's atomic optimizer on: only the plain-atomic
+// backward is instantiated, so that build differs from the default one in the atomic rewrite alone.
+namespace {
+template <int TILE, int BATCH>
+hipError_t bwd_compiler_reduce_t(const ViewBatch &vb, int remap, bool f64, const BwdParams &p, const uint2 *work,
+                                 hipStream_t st) {
+    const int n_tiles = vb.v[0].cam.grid_x * vb.v[0].cam.grid_y;
+    const dim3 grid(work ? vb.base[vb.n] : (unsigned)grid_for_tiles(n_tiles, remap));
+    if (grid.x == 0) return hipSuccess;
+    if (f64)
+        composite_bwd_kernel<TILE, BATCH, GSR_BWD_PLAIN_ATOMIC, false, false, double>
+            <<<grid, TILE * TILE, 0, st>>>(vb, remap, work, p);
+    else
+        composite_bwd_kernel<TILE, BATCH, GSR_BWD_PLAIN_ATOMIC, false, false, float>
+            <<<grid, TILE * TILE, 0, st>>>(vb, remap, work, p);
+    return hipGetLastError();
+}
+} // namespace
+
+hipError_t launch_composite_bwd_compiler_reduce(const ViewBatch &vb, int t, int lds_batch, int remap, bool acc_f64,
+                                                const BwdParams &p, const uint2 *work, hipStream_t st) {
+    if (vb.n <= 0 || (vb.n > 1 && !work)) return hipErrorInvalidValue;
+#define GSR_B(T, B) return bwd_compiler_reduce_t<T, B>(vb, remap, acc_f64, p, work, st)
+    if (t == 8) GSR_B(8, 64);
+    if (t == 16) {
+        if (lds_batch == 64) GSR_B(16, 64);
+        if (lds_batch == 128) GSR_B(16, 128);
+        GSR_B(16, 256);
+    }
+    if (lds_batch == 64) GSR_B(32, 64);
+    if (lds_batch == 128) GSR_B(32, 128);
+    GSR_B(32, 256);
+#undef GSR_B
+}
+#endif
 
 } // namespace gsr

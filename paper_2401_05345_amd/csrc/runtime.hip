@@ -217,7 +217,9 @@ gsr_status gsr_validate_config(const gsr_config *cf, const gsr_camera *c) {
     if (cf->tile != 8 && cf->tile != 16 && cf->tile != 32) return GSR_EINVAL;
     if (cf->lds_batch != 64 && cf->lds_batch != 128 && cf->lds_batch != 256) return GSR_EINVAL;
     if (cf->lds_batch > cf->tile * cf->tile) return GSR_EINVAL;
-    if (cf->bwd_mode < GSR_BWD_PLAIN_ATOMIC || cf->bwd_mode > GSR_BWD_BLOCK_REDUCE) return GSR_EINVAL;
+    if (cf->bwd_mode < GSR_BWD_PLAIN_ATOMIC || cf->bwd_mode > GSR_BWD_PLAIN_COMPILER_REDUCE) return GSR_EINVAL;
+    // The compiler-reduced kernel is built without the counting instrumentation.
+    if (cf->bwd_mode == GSR_BWD_PLAIN_COMPILER_REDUCE && (cf->flags & GSR_FLAG_DEBUG_COUNTERS)) return GSR_EINVAL;
     if (cf->reduce_threshold < 0 || cf->reduce_threshold > 65) return GSR_EINVAL;
     if (cf->flags & ~(GSR_FLAG_DEBUG_COUNTERS | GSR_FLAG_XCD_REMAP | GSR_FLAG_STAGE_TIMING |
                       GSR_FLAG_LANE_SPLIT_ATOMICS | GSR_FLAG_NO_TILE_ORDER | GSR_FLAG_ACC_F32))
@@ -681,8 +683,12 @@ gsr_status bwd_enqueue(gsr_ctx *ctx, int nv, gsr_fwd *const *sts, const gsr_conf
     BwdParams p{};
     p.counters = count ? sts[0]->counters : nullptr;
     p.threshold = cfg->reduce_threshold < 1 ? 1 : cfg->reduce_threshold;
-    GSR_HIP(ctx, launch_composite_bwd(plan.vb, cfg->tile, cfg->lds_batch, plan.remap, cfg->bwd_mode, count,
-                                      (cfg->flags & GSR_FLAG_LANE_SPLIT_ATOMICS) != 0, f64, p, plan.work, s));
+    if (cfg->bwd_mode == GSR_BWD_PLAIN_COMPILER_REDUCE)
+        GSR_HIP(ctx, launch_composite_bwd_compiler_reduce(plan.vb, cfg->tile, cfg->lds_batch, plan.remap, f64, p,
+                                                          plan.work, s));
+    else
+        GSR_HIP(ctx, launch_composite_bwd(plan.vb, cfg->tile, cfg->lds_batch, plan.remap, cfg->bwd_mode, count,
+                                          (cfg->flags & GSR_FLAG_LANE_SPLIT_ATOMICS) != 0, f64, p, plan.work, s));
     mark(ctx, tm, EV_B2);
     sts[0]->counters_valid = count;
     return GSR_OK;

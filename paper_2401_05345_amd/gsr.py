@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "_lib", "libgsr.so")
 
 GSR_OK, GSR_EINVAL, GSR_ENOMEM, GSR_EHIP, GSR_ESTATE = 0, -1, -2, -3, -4
 GSR_BWD_PLAIN_ATOMIC, GSR_BWD_WAVE_REDUCE, GSR_BWD_SERIAL_REDUCE, GSR_BWD_BLOCK_REDUCE = 0, 1, 2, 3
+GSR_BWD_PLAIN_COMPILER_REDUCE = 4
 GSR_FLAG_DEBUG_COUNTERS = 1
 GSR_FLAG_XCD_REMAP = 2
 GSR_FLAG_STAGE_TIMING = 4

@@ -89,13 +89,18 @@ def test_validate_config_modes_and_thresholds(lib):
         assert gsr.gsr_validate_config(gsr.make_config(reduce_threshold=thr)) == gsr.GSR_OK
     for thr in (-1, 66):
         assert gsr.gsr_validate_config(gsr.make_config(reduce_threshold=thr)) == gsr.GSR_EINVAL
-    for mode in (0, 1, 2, 3):
+    for mode in (0, 1, 2, 3, 4):
         assert gsr.gsr_validate_config(gsr.make_config(bwd_mode=mode)) == gsr.GSR_OK
-    for mode in (-1, 4):
+    for mode in (-1, 5):
         assert gsr.gsr_validate_config(gsr.make_config(bwd_mode=mode)) == gsr.GSR_EINVAL
     assert gsr.gsr_validate_config(gsr.make_config(flags=1 << 10)) == gsr.GSR_EINVAL
-    for mode in (0, 1, 2, 3):   # both accumulator precisions exist for every mode
+    for mode in (0, 1, 2, 3, 4):   # both accumulator precisions exist for every mode
         assert gsr.gsr_validate_config(gsr.make_config(bwd_mode=mode, flags=gsr.GSR_FLAG_ACC_F32)) == gsr.GSR_OK
+    # the compiler-reduced ablation has no counting build
+    assert gsr.gsr_validate_config(gsr.make_config(bwd_mode=gsr.GSR_BWD_PLAIN_COMPILER_REDUCE,
+                                                   flags=gsr.GSR_FLAG_DEBUG_COUNTERS)) == gsr.GSR_EINVAL
+    assert gsr.gsr_validate_config(gsr.make_config(bwd_mode=gsr.GSR_BWD_PLAIN_ATOMIC,
+                                                   flags=gsr.GSR_FLAG_DEBUG_COUNTERS)) == gsr.GSR_OK
 
 
 def test_ctx_create_without_gpu_reports_error(lib):

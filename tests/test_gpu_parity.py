@@ -48,6 +48,8 @@ def _workload_tiny():
     (gsr.GSR_BWD_PLAIN_ATOMIC, 0, gsr.GSR_FLAG_ACC_F32),
     (gsr.GSR_BWD_WAVE_REDUCE, 4, gsr.GSR_FLAG_ACC_F32 | gsr.GSR_FLAG_LANE_SPLIT_ATOMICS),
     (gsr.GSR_BWD_BLOCK_REDUCE, 1, gsr.GSR_FLAG_ACC_F32),
+    (gsr.GSR_BWD_PLAIN_COMPILER_REDUCE, 0, 0),
+    (gsr.GSR_BWD_PLAIN_COMPILER_REDUCE, 0, gsr.GSR_FLAG_ACC_F32),
 ])
 def test_tiny_parity(renderer, mode, thr, flags):
     say(f"[gpu] tiny_1k parity mode={mode} thr={thr} flags={flags}")
@@ -77,7 +79,7 @@ def test_tiles_and_batches_ragged_image(renderer, tile, batch):
     acc_ref, grads_ref = oracle.backward(wl.scene, rr, dl.astype(np.float64))
     gs = GpuScene(wl.scene, cam)
     for mode in (gsr.GSR_BWD_PLAIN_ATOMIC, gsr.GSR_BWD_WAVE_REDUCE, gsr.GSR_BWD_SERIAL_REDUCE,
-                 gsr.GSR_BWD_BLOCK_REDUCE):
+                 gsr.GSR_BWD_BLOCK_REDUCE, gsr.GSR_BWD_PLAIN_COMPILER_REDUCE):
         cfg = gsr.make_config(tile, batch, mode, 24, 0)
         st, out = run_render(renderer, gs, cfg)
         try:
@@ -129,7 +131,8 @@ def test_object_100k_parity_and_modes(renderer):
                                  (gsr.GSR_BWD_WAVE_REDUCE, 1, gsr.GSR_FLAG_LANE_SPLIT_ATOMICS),
                                  (gsr.GSR_BWD_SERIAL_REDUCE, 1, 0), (gsr.GSR_BWD_BLOCK_REDUCE, 1, 0),
                                  (gsr.GSR_BWD_WAVE_REDUCE, 1, gsr.GSR_FLAG_LANE_SPLIT_ATOMICS | gsr.GSR_FLAG_ACC_F32),
-                                 (gsr.GSR_BWD_PLAIN_ATOMIC, 0, gsr.GSR_FLAG_ACC_F32)]:
+                                 (gsr.GSR_BWD_PLAIN_ATOMIC, 0, gsr.GSR_FLAG_ACC_F32),
+                                 (gsr.GSR_BWD_PLAIN_COMPILER_REDUCE, 0, 0)]:
             grads, acc, _ = run_backward(renderer, gs, st, dl, gsr.make_config(16, 256, mode, thr, flags))
             errs = _check_grads(grads, acc, acc_ref, grads_ref)
             say(f"[gpu] object_100k mode={mode} thr={thr} grad rel-L2 {errs}")
