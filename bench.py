@@ -656,8 +656,12 @@ def main():
     a7 = np.array([s.preprocess_bwd for s in per])
     log(f"[bench] {args.steps} steps: {wall:.3f} ms/step, backward {bwd.mean():.3f} ms (a6 {a6.mean():.3f}, "
         f"a7 {a7.mean():.3f})")
+    stages = {k: round(float(np.mean([getattr(s, k) for s in per])), 4)
+              for k in ("preprocess", "depth_sort", "scan_emit", "tile_sort", "ranges", "composite_fwd")}
+    log(f"[bench] render {fwd.mean():.4f} ms, stages {stages}")
     if args.profile_only:
-        print(json.dumps({"profile_only": True, "ms_per_step": wall, "bwd_ms": float(bwd.mean())}))
+        print(json.dumps({"profile_only": True, "ms_per_step": wall, "bwd_ms": float(bwd.mean()),
+                          "render_ms": float(fwd.mean()), "forward_stages_ms": stages}))
         return
 
     # A/B on one forward state: plain atomics vs wave reduce, same inputs.
@@ -688,9 +692,7 @@ def main():
         "roofline": roofline,
         "backward": backward,
         "forward_ms": round(float(fwd.mean()), 4),
-        "forward_stages_ms": {k: round(float(np.mean([getattr(s, k) for s in per])), 4)
-                              for k in ("preprocess", "depth_sort", "scan_emit", "tile_sort", "ranges",
-                                        "composite_fwd")},
+        "forward_stages_ms": stages,
         "p99_step_ms": None,
     }
 

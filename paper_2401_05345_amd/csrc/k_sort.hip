@@ -342,16 +342,19 @@ __device__ __forceinline__ bool dev_skip(int shift, const uint32_t *range_dev) {
 }
 
 // Digit histogram of each block of ITEMS * 256 items, written digit-major (mask + 1
-// rows of `blocks` entries) so one exclusive scan of the whole table yields every
-// block's output offsets.
+// rows of `stride` entries, one column per block) so one exclusive scan of the whole
+// table yields every block's output offsets. Columns from gridDim.x to stride - 1 (the
+// padding of a table the scatter reads with 16-byte loads) are written as zeros.
 template <int ITEMS>
 __global__ __launch_bounds__(kThreads) void radix_hist_kernel(const uint32_t *keys, int64_t n, int shift,
-                                                              uint32_t mask, uint32_t *hist, int64_t blocks,
+                                                              uint32_t mask, uint32_t *hist, int64_t stride,
                                                               const uint32_t *n_dev, const uint32_t *range_dev) {
     n = dev_items(n, n_dev);
     if (n <= 0 || dev_skip(shift, range_dev)) return; // the scatter then ignores the table
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x <= mask)
+        for (int64_t c = gridDim.x; c < stride; ++c) hist[(int64_t)threadIdx.x * stride + c] = 0u;
     if ((int64_t)blockIdx.x * (kThreads * ITEMS) >= n) { // past the device-side count: an empty column
-        if (threadIdx.x <= mask) hist[(int64_t)threadIdx.x * blocks + blockIdx.x] = 0u;
+        if (threadIdx.x <= mask) hist[(int64_t)threadIdx.x * stride + blockIdx.x] = 0u;
         return;
     }
     __shared__ uint32_t s_count[kBins];
@@ -365,23 +368,25 @@ __global__ __launch_bounds__(kThreads) void radix_hist_kernel(const uint32_t *ke
     for (int r = 0; r < ITEMS; ++r)
         if (pos(r) < n) atomicAdd(&s_count[(k[r] >> shift) & mask], 1u);
     __syncthreads();
-    if (threadIdx.x <= mask) hist[(int64_t)threadIdx.x * blocks + blockIdx.x] = s_count[threadIdx.x];
+    if (threadIdx.x <= mask) hist[(int64_t)threadIdx.x * stride + blockIdx.x] = s_count[threadIdx.x];
 }
 
 // Stable scatter of one block of ITEMS * 256 items. Wave w ranks items
 // [w*64*ITEMS, (w+1)*64*ITEMS) of the block in ITEMS rounds of 64; lanes
 // with equal digits find each other with one ballot per digit bit. Items are
 // staged in LDS in digit order and written out with consecutive threads on
-// consecutive addresses. offsets: the scanned digit-major table, or with
-// fused != 0 the unscanned histogram table, from which each block derives its
-// own offsets (thread d sums row d: its total and the part before this block;
-// a scan over the digit totals adds the rows before it) - for tables of few
-// blocks, where a separate scan launch costs more than these reads.
+// consecutive addresses. offsets: the scanned digit-major table (rows of
+// `stride` = gridDim.x entries), or with fused != 0 the unscanned histogram
+// table (rows padded with zeros to `stride`, a multiple of 4), from which each
+// block derives its own offsets (thread d sums row d with 16-byte loads: its
+// total and the part before this block; a scan over the digit totals adds the
+// rows before it) - for tables of few blocks, where a separate scan launch
+// costs more than these reads.
 template <int ITEMS>
 __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(const uint32_t *keys_in, const uint32_t *vals_in,
                                                                  uint32_t *keys_out, uint32_t *vals_out, int64_t n,
                                                                  int shift, int nbits, const uint32_t *offsets,
-                                                                 int64_t blocks, int fused, const uint32_t *n_dev,
+                                                                 int64_t stride, int fused, const uint32_t *n_dev,
                                                                  const uint32_t *range_dev) {
     constexpr int TILE_ITEMS = kThreads * ITEMS;
     n = dev_items(n, n_dev);
@@ -410,12 +415,16 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(const uint32_t 
         const uint32_t d = threadIdx.x; // kThreads == kBins
         uint32_t before = 0, all = 0;
         if (d <= mask) {
-            const uint32_t *row = offsets + (int64_t)d * blocks;
+            // Eight 16-byte loads in flight per round (a row of at most 128 columns takes four).
+            const uint4 *row = reinterpret_cast<const uint4 *>(offsets + (int64_t)d * stride);
+            const int64_t me = blockIdx.x;
 #pragma unroll 8
-            for (int64_t b2 = 0; b2 < blocks; ++b2) {
-                const uint32_t h = row[b2];
-                all += h;
-                before += b2 < (int64_t)blockIdx.x ? h : 0u;
+            for (int64_t q = 0; q < (stride >> 2); ++q) {
+                const uint4 h = row[q];
+                const int64_t c = 4 * q;
+                all += h.x + h.y + h.z + h.w;
+                before += (c < me ? h.x : 0u) + (c + 1 < me ? h.y : 0u) + (c + 2 < me ? h.z : 0u) +
+                          (c + 3 < me ? h.w : 0u);
             }
         }
         uint32_t unused;
@@ -474,7 +483,7 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(const uint32_t 
     for (uint32_t i = threadIdx.x; i < block_total; i += kThreads) {
         const uint32_t k = s_key[i];
         const uint32_t d = (k >> shift) & mask;
-        const int64_t dst = (int64_t)(fused ? s_goff[d] : offsets[(int64_t)d * blocks + blockIdx.x]) + (i - s_dstart[d]);
+        const int64_t dst = (int64_t)(fused ? s_goff[d] : offsets[(int64_t)d * stride + blockIdx.x]) + (i - s_dstart[d]);
         keys_out[dst] = k;
         vals_out[dst] = s_val[i];
     }
@@ -484,18 +493,20 @@ template <int ITEMS>
 hipError_t radix_pass(const uint32_t *k_in, const uint32_t *v_in, uint32_t *k_out, uint32_t *v_out, int64_t n,
                       int shift, int nb, int64_t blocks, uint32_t *hist, uint32_t *partials, const uint32_t *n_dev,
                       const uint32_t *range_dev, hipStream_t st) {
-    radix_hist_kernel<ITEMS><<<(unsigned)blocks, kThreads, 0, st>>>(k_in, n, shift, (1u << nb) - 1u, hist, blocks,
+    // Few blocks: each scatter block reads the histogram rows itself instead of a scan launch,
+    // over rows padded to whole 16-byte groups.
+    const int fused = blocks <= kFusedScanBlocks ? 1 : 0;
+    const int64_t stride = fused ? (blocks + 3) & ~int64_t(3) : blocks;
+    radix_hist_kernel<ITEMS><<<(unsigned)blocks, kThreads, 0, st>>>(k_in, n, shift, (1u << nb) - 1u, hist, stride,
                                                                      n_dev, range_dev);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // Few blocks: each scatter block reads the histogram rows itself instead of a scan launch.
-    const int fused = blocks <= kFusedScanBlocks ? 1 : 0;
     if (!fused) {
         e = device_exclusive_scan(hist, nullptr, hist, blocks << nb, nullptr, partials, st); // (1 << nb) rows
         if (e != hipSuccess) return e;
     }
     radix_scatter_kernel<ITEMS><<<(unsigned)blocks, kThreads, 0, st>>>(k_in, v_in, k_out, v_out, n, shift, nb, hist,
-                                                                        blocks, fused, n_dev, range_dev);
+                                                                        stride, fused, n_dev, range_dev);
     return hipGetLastError();
 }
 
@@ -506,7 +517,7 @@ size_t radix_hist_count(int64_t n) {
     // shorter sort can need more blocks than a longer one.
     int64_t b = sort_blocks(n);
     if (n >= kSmallSort) b = b > sort_blocks(kSmallSort - 1) ? b : sort_blocks(kSmallSort - 1);
-    return (size_t)b * kBins + 8;
+    return (size_t)(b + 4) * kBins + 8; // + 4 columns: a fused table's rows are padded to a multiple of 4
 }
 
 hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n, int bits,
@@ -613,14 +624,22 @@ __global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t *p, uint32_t val
     if (i < count) p[i] = value;
 }
 
+// Every tile's [start, end) in the tile-sorted list, written once per tile with no
+// clearing pass: thread i (0 <= i <= P) looks at the boundary before position i,
+// between tile a = tile[i - 1] (-1 before the list) and b = tile[i] (n_tiles past it,
+// and for capacity-mode sentinels, which sort last). Where a < b it ends a, starts b
+// and gives each tile strictly between them the empty range [i, i).
 __global__ __launch_bounds__(256) void tile_ranges_kernel(int64_t P, const uint32_t *tile, uint2 *ranges,
                                                            uint32_t n_tiles) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= P) return;
-    const uint32_t t = tile[i];
-    if (t >= n_tiles) return; // capacity-mode sentinel
-    if (i == 0 || tile[i - 1] != t) ranges[t].x = (uint32_t)i;
-    if (i == P - 1 || tile[i + 1] != t) ranges[t].y = (uint32_t)(i + 1);
+    if (i > P) return;
+    const int64_t a = i == 0 ? -1 : (int64_t)min(tile[i - 1], n_tiles);
+    const int64_t b = i == P ? (int64_t)n_tiles : (int64_t)min(tile[i], n_tiles);
+    if (a >= b) return;
+    const uint32_t at = (uint32_t)i;
+    if (a >= 0) ranges[a].y = at;
+    if (b < (int64_t)n_tiles) ranges[b].x = at;
+    for (int64_t t = a + 1; t < b; ++t) ranges[t] = make_uint2(at, at);
 }
 
 } // namespace
@@ -650,9 +669,9 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream
 
 hipError_t launch_tile_ranges(int64_t P, const uint32_t *sorted_tile, uint2 *ranges, int64_t n_tiles,
                               hipStream_t st) {
-    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), 0u, 2 * n_tiles, st);
-    if (e != hipSuccess || P <= 0) return e;
-    tile_ranges_kernel<<<(unsigned)((P + 255) / 256), 256, 0, st>>>(P, sorted_tile, ranges, (uint32_t)n_tiles);
+    if (n_tiles <= 0) return hipSuccess;
+    if (P < 0) P = 0;
+    tile_ranges_kernel<<<(unsigned)((P + 1 + 255) / 256), 256, 0, st>>>(P, sorted_tile, ranges, (uint32_t)n_tiles);
     return hipGetLastError();
 }
 

@@ -63,6 +63,8 @@ def _check_lists(renderer, scene, camera, n):
         ids = out["sorted_ids"].astype(np.int64)
         assert np.array_equal(np.bincount(ids, minlength=n), touched)
         rgs = out["ranges"].astype(np.int64)
+        # every tile's range lies in [0, P) and is empty or ordered
+        assert (rgs[:, 0] <= rgs[:, 1]).all() and rgs.min() >= 0 and rgs.max() <= P
         nonempty = rgs[:, 1] > rgs[:, 0]
         order = np.argsort(rgs[nonempty, 0])
         starts, ends = rgs[nonempty][order, 0], rgs[nonempty][order, 1]
