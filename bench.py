@@ -340,15 +340,18 @@ def _latency_stats(res):
             "p99_ms": round(float(np.percentile(lat, 99)), 3), "mean_ms": round(float(lat.mean()), 3),
             "steps_per_s": round(len(res) / span, 2),
             "mean_batch": round(float(np.mean([r.batch_size for r in res])), 2),
-            "failed": int(sum(r.status != 0 for r in res))}
+            "failed": int(sum(r.status != 0 for r in res)),
+            "capacity_mode_frac": round(float(np.mean([r.render_mode == 1 for r in res])), 3),
+            "reruns": int(sum(r.render_mode == 2 for r in res))}
 
 
 def bench_serving(flags, seconds):
     """The served stream: ten resident scenes (100k-2M Gaussians, SH3) with Adam state on the
     device; Poisson arrivals of render + L1 + backward + Adam requests at several rates, each at
     a random eye and resolution with a device-drawn U(0,1) target. The continuous-batching server
-    (wave-reduce backward, up to 16 requests per batch, two lanes) against a sequential
-    plain-atomic server (one request at a time, one lane) on the same arrival streams."""
+    (wave-reduce backward, up to 16 requests per batch, two lanes), the same in capacity mode (no
+    host synchronisation inside a batch), and a sequential plain-atomic server (one request at a
+    time, one lane) on the same arrival streams."""
     import torch
     from paper_2401_05345_amd import gsr
     from paper_2401_05345_amd import scenegen as sg
@@ -375,6 +378,7 @@ def bench_serving(flags, seconds):
     reduce_cfg = gsr.make_config(16, 256, gsr.GSR_BWD_WAVE_REDUCE, 4, flags)
     plain_cfg = gsr.make_config(16, 256, gsr.GSR_BWD_PLAIN_ATOMIC, 0, flags | gsr.GSR_FLAG_ACC_F32)
     servers = {"batched_reduce": dict(max_batch=16, lanes=2, config=reduce_cfg),
+               "batched_reduce_capacity": dict(max_batch=16, lanes=2, config=reduce_cfg, capacity_render=True),
                "sequential_plain": dict(max_batch=1, lanes=1, config=plain_cfg)}
     for name, kw in servers.items():
         with Server(out["budget_bytes"], lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-15, **kw) as srv:
@@ -383,7 +387,7 @@ def bench_serving(flags, seconds):
             srv.replay([srv.request(ids[si], cam, seed) for _, si, cam, seed in warm], [0.0] * len(warm))
             srv.drain()
             srv.results()
-            for rate in SERVE_RATES + (SERVE_RATES_HIGH if name == "batched_reduce" else ()):
+            for rate in SERVE_RATES + (SERVE_RATES_HIGH if name.startswith("batched") else ()):
                 stream = sg.serving_requests(1000 + rate, len(ids), max(8, int(rate * seconds)), float(rate))
                 reqs = [srv.request(ids[si], cam, seed) for _, si, cam, seed in stream]
                 t0 = time.perf_counter()
@@ -399,6 +403,15 @@ def bench_serving(flags, seconds):
             continue
         d["p99_speedup"] = round(d["sequential_plain"]["p99_ms"] / d["batched_reduce"]["p99_ms"], 2)
         d["throughput_ratio"] = round(d["batched_reduce"]["steps_per_s"] / d["sequential_plain"]["steps_per_s"], 2)
+    # The lowest measured rate at which requests start to share batches (mean batch >= 1.2).
+    out["batches_first_form"] = {}
+    for name in ("batched_reduce", "batched_reduce_capacity"):
+        for rate in sorted(int(r) for r in out["rates"]):
+            st = out["rates"][str(rate)].get(name)
+            if st and st["mean_batch"] >= 1.2:
+                out["batches_first_form"][name] = {"rate": rate, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+                                                   "mean_batch": st["mean_batch"]}
+                break
     return out
 
 

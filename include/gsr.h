@@ -405,6 +405,13 @@ typedef struct {
     int32_t lanes;            /* 1..4 streams batches rotate over */
     gsr_config config;        /* render/backward configuration of every batch */
     float lr, beta1, beta2, eps;
+    int32_t capacity_render;  /* 1: a batch whose scenes have been rendered before renders with pair
+                                 buffers sized from each scene's last pairs per pixel (x 1.25 + 4096)
+                                 and runs render, loss, backward and Adam without any host
+                                 synchronisation; a request whose pairs overflow skips its Adam
+                                 update on the device and is run again with the counts read back
+                                 (gsr_result.render_mode). 0: every batch's render reads its counts
+                                 back */
 } gsr_server_opts;
 
 /* One request: a step of scene `scene` seen by `camera` against a target
@@ -424,6 +431,9 @@ typedef struct {
     int32_t step;                /* the scene's optimiser step count after this request */
     float loss;                  /* mean |image - target| of the render before the step */
     double t_arrival, t_start, t_done; /* seconds on the server clock (gsr_server_now) */
+    int32_t render_mode;         /* 0: the render read its pair counts back; 1: capacity mode (no host
+                                    synchronisation); 2: its capacity-mode render overflowed and the
+                                    step ran again with the counts read back */
 } gsr_result;
 
 /* Resident bytes of a scene of n Gaussians at sh_degree (four flat blocks). */

@@ -67,9 +67,10 @@ hipError_t launch_preprocess_bwd(const gsr_scene &s, const DevCamera &cam, const
                                  bool acc_f64, const gsr_grads &out, int accumulate, hipStream_t st);
 
 // Zero the accumulator rows of Gaussians with radius > 0 (the only rows the composite writes):
-// those listed in visible_ids[0, n_visible) when the list is given, else found from radius.
+// those listed in visible_ids[0, n_visible) when the list is given (the first *n_visible_dev of
+// them when that device-side count is given), else found from radius.
 hipError_t launch_zero_visible_rows(const int32_t *radius, int64_t n, const uint32_t *visible_ids, int64_t n_visible,
-                                    void *acc, bool acc_f64, hipStream_t st);
+                                    const uint32_t *n_visible_dev, void *acc, bool acc_f64, hipStream_t st);
 // Accumulator rows as fp32 gradients [n][GSR_ACC_STRIDE] (dL/du, dL/dv, dL/dA, dL/dB, dL/dC,
 // dL/do, dL/drgb: the moments converted with the record's opacity and conic), culled rows as
 // zeros.
@@ -169,10 +170,10 @@ hipError_t launch_composite_bwd_compiler_reduce(const ViewBatch &vb, int tile, i
 
 hipError_t launch_l1_grad(const float *image, const float *target, int64_t count, float *out, hipStream_t st);
 
-// Training-step kernels (k_train.hip): Adam on a flat block (step >= 1), a
-// SplitMix64 U[0,1) fill, and sum |a-b| added into *out.
+// Training-step kernels (k_train.hip): Adam on a flat block (step >= 1; no update when `skip` is
+// given and *skip != 0 on the device), a SplitMix64 U[0,1) fill, and sum |a-b| added into *out.
 hipError_t launch_adam(float *p, const float *g, float *m, float *v, int64_t count, float lr, float b1, float b2,
-                       float eps, int step, hipStream_t st);
+                       float eps, int step, hipStream_t st, const uint32_t *skip = nullptr);
 hipError_t launch_uniform(float *out, int64_t count, uint64_t seed, hipStream_t st);
 hipError_t launch_l1_sum(const float *a, const float *b, int64_t count, float *out, hipStream_t st);
 
@@ -188,6 +189,12 @@ hipError_t launch_microbench(int kind, void *buf, int64_t bytes, int64_t *ops, h
 hipError_t launch_wave_reduce_selftest(const float *vals, const uint8_t *active, int n_waves, int mode,
                                        int threshold, int lane_split, float *sums, unsigned long long *lane_atomics,
                                        hipStream_t st);
+
+// Batched render into new states in capacity mode (pair buffers of caps[v] pairs, no host
+// synchronisation; a view whose pairs exceed its capacity raises its overflow word, totals[2]).
+gsr_status render_batch_capacity(gsr_ctx *ctx, int nv, const gsr_scene *scenes, const gsr_camera *cameras,
+                                 const gsr_config *config, float *const *images, const int64_t *caps,
+                                 gsr_fwd **states_out);
 
 } // namespace gsr
 

@@ -627,10 +627,11 @@ __global__ __launch_bounds__(256) void zero_visible_rows_kernel(const int32_t *r
 // The same for a list of the visible Gaussians (the depth-sorted ids of a render): one thread per
 // 16-byte chunk of a listed row, so consecutive threads fill whole 128-byte lines, and no thread
 // is spent on culled Gaussians.
-__global__ __launch_bounds__(256) void zero_listed_rows_kernel(const uint32_t *ids, int64_t m, uint4 *acc,
-                                                                int chunks_per_row) {
+__global__ __launch_bounds__(256) void zero_listed_rows_kernel(const uint32_t *ids, int64_t m, const uint32_t *m_dev,
+                                                                uint4 *acc, int chunks_per_row) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t v = t / chunks_per_row;
+    if (m_dev && (int64_t)*m_dev < m) m = *m_dev; // a count that lives on the device (capacity mode)
     if (v >= m) return;
     acc[(int64_t)ids[v] * chunks_per_row + (t - v * chunks_per_row)] = make_uint4(0u, 0u, 0u, 0u);
 }
@@ -663,13 +664,13 @@ __global__ __launch_bounds__(256) void export_acc_kernel(const int32_t *radius, 
 } // namespace
 
 hipError_t launch_zero_visible_rows(const int32_t *radius, int64_t n, const uint32_t *visible_ids, int64_t n_visible,
-                                    void *acc, bool acc_f64, hipStream_t st) {
+                                    const uint32_t *n_visible_dev, void *acc, bool acc_f64, hipStream_t st) {
     const int chunks = GSR_ACC_STRIDE * (acc_f64 ? 8 : 4) / 16;
     if (visible_ids) {
         if (n_visible <= 0) return hipSuccess;
         const int64_t threads = n_visible * chunks;
         zero_listed_rows_kernel<<<(unsigned)((threads + 255) / 256), 256, 0, st>>>(
-            visible_ids, n_visible, static_cast<uint4 *>(acc), chunks);
+            visible_ids, n_visible, n_visible_dev, static_cast<uint4 *>(acc), chunks);
         return hipGetLastError();
     }
     if (n <= 0) return hipSuccess;

@@ -8,10 +8,14 @@ namespace gsr {
 namespace {
 
 // Adam (Kingma and Ba, 2015) with bias correction; one thread per float4 of
-// the flat parameter block, plain tail handled by the first threads.
+// the flat parameter block, plain tail handled by the first threads. With
+// `skip` given, nothing is updated when *skip is non-zero (a step whose
+// gradient came from an overflowed capacity-mode render).
 __global__ __launch_bounds__(256) void adam_kernel(float *__restrict__ p, const float *__restrict__ g,
                                                    float *__restrict__ m, float *__restrict__ v, int64_t count,
-                                                   float lr, float b1, float b2, float eps, float c1, float c2) {
+                                                   float lr, float b1, float b2, float eps, float c1, float c2,
+                                                   const uint32_t *skip) {
+    if (skip && *skip) return;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const auto one = [&](int64_t k) {
         const float gk = g[k];
@@ -74,11 +78,11 @@ __global__ __launch_bounds__(256) void l1_sum_kernel(const float *a, const float
 } // namespace
 
 hipError_t launch_adam(float *p, const float *g, float *m, float *v, int64_t count, float lr, float b1, float b2,
-                       float eps, int step, hipStream_t st) {
+                       float eps, int step, hipStream_t st, const uint32_t *skip) {
     if (count <= 0) return hipSuccess;
     const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
     const int64_t threads = count / 4 > 3 ? count / 4 : 3;
-    adam_kernel<<<(unsigned)((threads + 255) / 256), 256, 0, st>>>(p, g, m, v, count, lr, b1, b2, eps, c1, c2);
+    adam_kernel<<<(unsigned)((threads + 255) / 256), 256, 0, st>>>(p, g, m, v, count, lr, b1, b2, eps, c1, c2, skip);
     return hipGetLastError();
 }
 

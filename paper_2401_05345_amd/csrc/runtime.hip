@@ -601,6 +601,45 @@ gsr_status rerender_views(gsr_ctx *ctx, int nv, gsr_fwd *const *sts, float *cons
     return enqueue_composite_fwd(ctx, nv, sts, images, config, work_buf, tm);
 }
 
+// Renders nv validated views into new states whose pair buffers hold caps[v] pairs, in capacity
+// mode: no host synchronisation; a view whose pairs exceed its capacity raises its overflow word
+// (totals[2]) and its lists hold only the first caps[v] pairs.
+gsr_status render_views_capacity(gsr_ctx *ctx, int nv, const gsr_scene *scenes, const gsr_camera *cameras,
+                                 const gsr_config *config, float *const *images, const int64_t *caps,
+                                 gsr_fwd **states_out) {
+    GSR_HIP(ctx, hipSetDevice(ctx->device));
+    const bool tm = (config->flags & GSR_FLAG_STAGE_TIMING) != 0;
+    ctx->timing_render = tm;
+    gsr_fwd *sts[kMaxViews] = {};
+    gsr_status status = GSR_OK;
+    for (int v = 0; v < nv && status == GSR_OK; ++v) {
+        status = check_view(ctx, v, &scenes[v], &cameras[v], config, images[v]);
+        if (status != GSR_OK) break;
+        gsr_fwd *st = new (std::nothrow) gsr_fwd();
+        if (!st) {
+            status = fail(ctx, GSR_ENOMEM, "host allocation failed");
+            break;
+        }
+        sts[v] = st;
+        st->scene = scenes[v];
+        st->camera = cameras[v];
+        st->config = *config;
+        st->dcam = make_dev_camera(cameras[v], config->tile);
+        st->n = scenes[v].n;
+        st->n_tiles = (int64_t)st->dcam.grid_x * st->dcam.grid_y;
+        status = alloc_view(ctx, st);
+        if (status == GSR_OK) status = alloc_pairs(ctx, st, caps[v] > 0 ? caps[v] : 1);
+    }
+    if (status == GSR_OK) status = rerender_views(ctx, nv, sts, images, config, nullptr, tm);
+    if (status != GSR_OK) {
+        for (int v = 0; v < nv; ++v)
+            if (sts[v]) gsr_fwd_release(ctx, sts[v]);
+        return status;
+    }
+    for (int v = 0; v < nv; ++v) states_out[v] = sts[v];
+    return GSR_OK;
+}
+
 // Backward composite over nv checked states, in two parts so that the second
 // can be captured in a graph: bwd_prepare makes every buffer exist (and
 // computes a single view's cached tile order once), bwd_enqueue only launches
@@ -670,11 +709,13 @@ gsr_status bwd_enqueue(gsr_ctx *ctx, int nv, gsr_fwd *const *sts, const gsr_conf
     for (int v = 0; v < nv; ++v) sts[v]->counters_valid = false;
     mark(ctx, tm, EV_B0);
     for (int v = 0; v < nv; ++v) {
-        // After a render that read its counts back, the depth-sorted ids are exactly the visible
-        // Gaussians; a capacity-mode re-render leaves the count on the device.
+        // The depth-sorted ids start with the visible Gaussians (culled ones carry the largest
+        // key): after a render that read its counts back they are exactly those; after a
+        // capacity-mode render their count is on the device.
         const gsr_fwd *sv = sts[v];
-        GSR_HIP(ctx, launch_zero_visible_rows(sv->radius, sv->n, sv->p_known ? sv->sorted_ids_by_depth : nullptr,
-                                              sv->n_visible, plan.vb.v[v].acc, f64, s));
+        GSR_HIP(ctx, launch_zero_visible_rows(sv->radius, sv->n, sv->sorted_ids_by_depth,
+                                              sv->p_known ? sv->n_visible : sv->n,
+                                              sv->p_known ? nullptr : sv->totals + 1, plan.vb.v[v].acc, f64, s));
         if (plan.own_acc) sts[v]->acc_f64 = f64;
     }
     if (count) GSR_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t *>(sts[0]->counters), 0u, 160, s));
@@ -750,6 +791,20 @@ int grads_alias(const gsr_grads &a, const gsr_grads &b) {
 }
 
 } // namespace
+
+namespace gsr {
+gsr_status render_batch_capacity(gsr_ctx *ctx, int nv, const gsr_scene *scenes, const gsr_camera *cameras,
+                                 const gsr_config *config, float *const *images, const int64_t *caps,
+                                 gsr_fwd **states_out) {
+    if (!ctx) return GSR_EINVAL;
+    ctx->err.clear();
+    if (nv < 1 || nv > GSR_MAX_BATCH) return fail(ctx, GSR_EINVAL, "n_views %d outside 1..16", nv);
+    if (!scenes || !cameras || !images || !caps || !states_out || !config)
+        return fail(ctx, GSR_EINVAL, "null array argument");
+    for (int v = 0; v < nv; ++v) states_out[v] = nullptr;
+    return render_views_capacity(ctx, nv, scenes, cameras, config, images, caps, states_out);
+}
+} // namespace gsr
 
 extern "C" {
 

@@ -57,6 +57,7 @@ struct Lane {
     hipEvent_t done = nullptr;
     float *loss_host = nullptr;   // pinned, GSR_MAX_BATCH sums
     float *loss_dev = nullptr;
+    uint32_t *counts_host = nullptr; // pinned, 4 words per view: a capacity-mode render's pairs, visible, overflow
     bool busy = false;
     bool has_batch = false;       // a batch handed over by the scheduler waits for this lane's thread
     Batch batch;
@@ -126,10 +127,14 @@ int64_t request_bytes(const Scene &sc, const gsr_camera &cam) {
     return 48 * hw + 160 * sc.n + 16 * (int64_t)(ppp * (double)hw);
 }
 
-// Runs one batch on a lane: everything is enqueued on the lane's stream; the render
-// synchronises once on it (pair counts). Called by the lane's own thread without the lock, so
-// the scheduler goes on admitting work for the other lanes meanwhile.
-void run_batch(gsr_server *S, Lane &L, Batch &b, std::vector<Scene *> &sc) {
+// Runs one batch on a lane: everything is enqueued on the lane's stream. The render either
+// synchronises once on it (pair counts), or - in capacity mode, when every scene of the batch has
+// a pairs-per-pixel estimate - renders into pair buffers sized from that estimate with no host
+// synchronisation at all, gating each scene's Adam update on its render's overflow word and
+// queueing the read-back of its counts (checked after the batch). Returns whether the batch ran
+// in capacity mode. Called by the lane's own thread without the lock, so the scheduler goes on
+// admitting work for the other lanes meanwhile.
+bool run_batch(gsr_server *S, Lane &L, Batch &b, std::vector<Scene *> &sc, bool allow_capacity) {
     const int k = (int)b.reqs.size();
     gsr_ctx *c = L.ctx;
     hipStream_t st = L.stream;
@@ -161,7 +166,18 @@ void run_batch(gsr_server *S, Lane &L, Batch &b, std::vector<Scene *> &sc) {
     }
     if (status == GSR_OK && launch_fill_u32(reinterpret_cast<uint32_t *>(L.loss_dev), 0u, kMaxViews, st) != hipSuccess)
         status = GSR_EHIP;
-    if (status == GSR_OK) status = gsr_render_batch(c, k, scenes, cams, &S->opts.config, imgs, states);
+    bool capacity = allow_capacity && S->opts.capacity_render != 0;
+    int64_t caps[kMaxViews] = {};
+    for (int i = 0; i < k; ++i) {
+        // The scene's pairs per pixel from its last render (written only by the lane that runs
+        // its request, and read by the scheduler only while the scene is idle).
+        const double ppp = sc[i]->pairs_per_px;
+        if (!(ppp > 0.0)) capacity = false;
+        caps[i] = (int64_t)(1.25 * ppp * (double)cams[i].width * (double)cams[i].height) + 4096;
+    }
+    if (status == GSR_OK)
+        status = capacity ? render_batch_capacity(c, k, scenes, cams, &S->opts.config, imgs, caps, states)
+                          : gsr_render_batch(c, k, scenes, cams, &S->opts.config, imgs, states);
     for (int i = 0; i < k && status == GSR_OK; ++i) {
         const int64_t n3 = 3 * (int64_t)cams[i].width * cams[i].height;
         if (launch_l1_sum(imgs[i], tgts[i], n3, L.loss_dev + i, st) != hipSuccess) status = GSR_EHIP;
@@ -171,18 +187,24 @@ void run_batch(gsr_server *S, Lane &L, Batch &b, std::vector<Scene *> &sc) {
         status = gsr_backward_batch(c, k, states, dls, outs, 0, &S->opts.config);
     for (int i = 0; i < k && status == GSR_OK; ++i) {
         Scene &s = *sc[i];
+        // an overflowed capacity-mode render gives no update (the step runs again)
         if (launch_adam(s.p, s.g, s.m, s.v, s.count, S->opts.lr, S->opts.beta1, S->opts.beta2, S->opts.eps,
-                        b.steps[i], st) != hipSuccess)
+                        b.steps[i], st, capacity ? states[i]->totals + 2 : nullptr) != hipSuccess)
             status = GSR_EHIP;
     }
     if (status == GSR_OK &&
         hipMemcpyAsync(L.loss_host, L.loss_dev, k * sizeof(float), hipMemcpyDeviceToHost, st) != hipSuccess)
         status = GSR_EHIP;
+    for (int i = 0; i < k && status == GSR_OK && capacity; ++i)
+        if (hipMemcpyAsync(L.counts_host + 4 * i, states[i]->totals, 3 * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                           st) != hipSuccess)
+            status = GSR_EHIP;
     for (int i = 0; i < k; ++i) {
         if (states[i]) {
             const double hw = (double)cams[i].width * cams[i].height;
             gsr_fwd_stats_t fs{};
-            if (gsr_fwd_stats(states[i], &fs) == GSR_OK && hw > 0) sc[i]->pairs_per_px = (double)fs.n_pairs / hw;
+            if (!capacity && gsr_fwd_stats(states[i], &fs) == GSR_OK && hw > 0)
+                sc[i]->pairs_per_px = (double)fs.n_pairs / hw;
             gsr_fwd_release(c, states[i]);
         }
     }
@@ -195,6 +217,7 @@ void run_batch(gsr_server *S, Lane &L, Batch &b, std::vector<Scene *> &sc) {
     }
     for (auto &x : b.status) x = status;
     (void)hipEventRecord(L.done, st);
+    return capacity && status == GSR_OK;
 }
 
 void scheduler_main(gsr_server *S) {
@@ -268,8 +291,40 @@ void lane_main(gsr_server *S, Lane *L) {
         Batch &b = L->batch;
         const hipEvent_t ev = L->done;
         lk.unlock();
-        run_batch(S, *L, b, b.sc);
+        const bool capacity = run_batch(S, *L, b, b.sc, true);
         (void)hipEventSynchronize(ev);
+        const size_t k = b.reqs.size();
+        std::vector<float> loss(L->loss_host, L->loss_host + k);
+        std::vector<int32_t> mode(k, capacity ? 1 : 0);
+        if (capacity) {
+            // Counts of the capacity-mode renders: pairs-per-pixel estimates for the next ones, and
+            // the requests whose pairs overflowed (their Adam update was skipped) run again, exactly.
+            Batch again;
+            std::vector<size_t> where;
+            for (size_t i = 0; i < k; ++i) {
+                const uint32_t *h = L->counts_host + 4 * i;
+                const gsr_camera &cam = b.reqs[i].req.camera;
+                const double hw = (double)cam.width * cam.height;
+                if (h[2] == 0u) {
+                    if (hw > 0) b.sc[i]->pairs_per_px = (double)h[0] / hw;
+                    continue;
+                }
+                again.reqs.push_back(b.reqs[i]);
+                again.steps.push_back(b.steps[i]);
+                again.sc.push_back(b.sc[i]);
+                where.push_back(i);
+            }
+            if (!where.empty()) {
+                again.status.assign(where.size(), GSR_OK);
+                run_batch(S, *L, again, again.sc, false);
+                (void)hipEventSynchronize(ev);
+                for (size_t j = 0; j < where.size(); ++j) {
+                    b.status[where[j]] = again.status[j];
+                    loss[where[j]] = L->loss_host[j];
+                    mode[where[j]] = 2;
+                }
+            }
+        }
         const double t_done = S->now();
         lk.lock();
         for (size_t i = 0; i < b.reqs.size(); ++i) {
@@ -282,7 +337,8 @@ void lane_main(gsr_server *S, Lane *L) {
             r.batch_size = (int32_t)b.reqs.size();
             r.lane = L->index;
             r.step = b.steps[i];
-            r.loss = b.status[i] == GSR_OK ? L->loss_host[i] / (3.0f * (float)cam.width * (float)cam.height) : -1.0f;
+            r.loss = b.status[i] == GSR_OK ? loss[i] / (3.0f * (float)cam.width * (float)cam.height) : -1.0f;
+            r.render_mode = mode[i];
             r.t_arrival = p.t_arrival;
             r.t_start = b.t_start;
             r.t_done = t_done;
@@ -303,6 +359,7 @@ void destroy_lane(Lane *L) {
     if (L->ctx) gsr_ctx_destroy(L->ctx);
     if (L->loss_dev) (void)hipFree(L->loss_dev);
     if (L->loss_host) (void)hipHostFree(L->loss_host);
+    if (L->counts_host) (void)hipHostFree(L->counts_host);
     if (L->done) (void)hipEventDestroy(L->done);
     if (L->stream) (void)hipStreamDestroy(L->stream);
     delete L;
@@ -312,6 +369,7 @@ bool valid_opts(const gsr_server_opts *o) {
     if (!o) return false;
     if (o->max_batch < 1 || o->max_batch > GSR_MAX_BATCH || o->lanes < 1 || o->lanes > 4) return false;
     if (o->hbm_budget_bytes <= 0) return false;
+    if (o->capacity_render != 0 && o->capacity_render != 1) return false;
     if (gsr_validate_config(&o->config, nullptr) != GSR_OK) return false;
     if (!(o->lr > 0.0f) || !(o->beta1 >= 0.0f && o->beta1 < 1.0f) || !(o->beta2 >= 0.0f && o->beta2 < 1.0f) ||
         !(o->eps >= 0.0f))
@@ -347,12 +405,14 @@ gsr_status gsr_server_create(int device, const gsr_server_opts *opts, gsr_server
         bool ok = L != nullptr;
         if (ok) {
             L->index = i;
-            void *hp = nullptr;
+            void *hp = nullptr, *hc = nullptr;
             ok = hipStreamCreateWithFlags(&L->stream, hipStreamNonBlocking) == hipSuccess &&
                  hipEventCreateWithFlags(&L->done, hipEventDisableTiming) == hipSuccess &&
                  hipHostMalloc(&hp, kMaxViews * sizeof(float), hipHostMallocDefault) == hipSuccess &&
+                 hipHostMalloc(&hc, 4 * kMaxViews * sizeof(uint32_t), hipHostMallocDefault) == hipSuccess &&
                  hipMalloc(reinterpret_cast<void **>(&L->loss_dev), kMaxViews * sizeof(float)) == hipSuccess;
             L->loss_host = static_cast<float *>(hp);
+            L->counts_host = static_cast<uint32_t *>(hc);
             ok = ok && gsr_ctx_create(&L->ctx, device, L->stream) == GSR_OK;
         }
         if (!ok) {

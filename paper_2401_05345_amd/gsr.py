@@ -93,7 +93,8 @@ class gsr_tune_entry(ctypes.Structure):
 
 class gsr_server_opts(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", c_int64), ("max_batch", c_int32), ("lanes", c_int32), ("config", gsr_config),
-                ("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
+                ("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("capacity_render", c_int32)]
 
 
 class gsr_request(ctypes.Structure):
@@ -103,7 +104,7 @@ class gsr_request(ctypes.Structure):
 class gsr_result(ctypes.Structure):
     _fields_ = [("id", c_int64), ("scene", c_int32), ("status", c_int32), ("batch_size", c_int32), ("lane", c_int32),
                 ("step", c_int32), ("loss", ctypes.c_float), ("t_arrival", ctypes.c_double),
-                ("t_start", ctypes.c_double), ("t_done", ctypes.c_double)]
+                ("t_start", ctypes.c_double), ("t_done", ctypes.c_double), ("render_mode", c_int32)]
 
 
 class GsrError(RuntimeError):
@@ -427,9 +428,9 @@ def _scheck(server, status):
 
 
 def make_server_opts(budget_bytes, max_batch=16, lanes=2, config=None, lr=1e-3, beta1=0.9, beta2=0.999,
-                     eps=1e-15) -> gsr_server_opts:
+                     eps=1e-15, capacity_render=0) -> gsr_server_opts:
     return gsr_server_opts(int(budget_bytes), max_batch, lanes, config if config is not None else make_config(),
-                           lr, beta1, beta2, eps)
+                           lr, beta1, beta2, eps, int(capacity_render))
 
 
 def gsr_server_scene_bytes(n: int, sh_degree: int) -> int:

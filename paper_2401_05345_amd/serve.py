@@ -17,8 +17,10 @@ def camera_struct(c) -> gsr.gsr_camera:
 
 class Server:
     def __init__(self, budget_bytes: int, max_batch: int = 16, lanes: int = 2, config: gsr.gsr_config | None = None,
-                 lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-15, device: int = 0):
-        self.opts = gsr.make_server_opts(budget_bytes, max_batch, lanes, config, lr, beta1, beta2, eps)
+                 lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-15, device: int = 0,
+                 capacity_render: bool = False):
+        self.opts = gsr.make_server_opts(budget_bytes, max_batch, lanes, config, lr, beta1, beta2, eps,
+                                         capacity_render)
         self.h = gsr.gsr_server_create(self.opts, device)
         self.meta = {}
 

@@ -11,6 +11,8 @@
 * The HBM budget rejects scenes that do not fit and limits batch size.
 * A checkpoint written to .npy and loaded into a new server continues the same
   optimisation.
+* Capacity-mode batches (no host synchronisation, overflowed steps run again)
+  give the same results as batches that read their pair counts back.
 """
 import numpy as np
 import pytest
@@ -152,6 +154,54 @@ def test_same_result_alone_and_in_a_batched_mix(gsr, scenes):
     d = np.abs(mixed["params"] - alone["params"])
     bad = d > 1e-7 + 1e-6 * np.abs(alone["params"])
     assert np.all(np.abs(g[bad]) <= 1e-6 * np.abs(g).max()), int(bad.sum())
+
+
+def test_capacity_render_same_as_counts_read_back(gsr, scenes):
+    """Capacity mode: a scene's first request reads its pair counts back (there is no estimate
+    yet); later ones render into pair buffers sized from the scene's last pairs per pixel, with no
+    host synchronisation in the batch. A scene seen from far away and then from close up overflows
+    its estimate: that step's Adam update is skipped on the device and the step runs again. Every
+    request's loss, gradient and Adam state equal those of a server that reads every count back."""
+    say("[gpu] server: capacity-mode batches vs counts read back")
+    gss = _gpu(scenes[:3])
+    # scene 0 (3000 Gaussians): 0.07 pairs per pixel from far away on a wide image, then 5947
+    # pairs on a 64x64 close-up, above the 1.25 * 0.07 * 4096 + 4096 = 4454 its estimate gives
+    far = sg.make_camera(320, 240, (0.0, 0.0, -30.0))
+    near = sg.make_camera(64, 64, (0.0, 0.0, -2.0))
+    cams = _cams(4, seed=61)
+    plan = [(0, far, 1), (0, near, 2), (1, cams[0], 3), (1, cams[1], 4), (2, cams[2], 5), (1, cams[3], 6),
+            (2, cams[3], 7), (0, cams[0], 8)]
+
+    def run(capacity):
+        with Server(16 * GiB, max_batch=16, lanes=2, config=cfg(), capacity_render=capacity) as srv:
+            ids = _add_all(srv, gss)
+            for s, cam, seed in plan:   # one at a time: the same batches on both servers
+                srv.submit(srv.request(ids[s], cam, seed))
+                srv.drain()
+            res = sorted(srv.results(), key=lambda r: r.id)
+            blocks = [{b: srv.block(i, b) for b in gsr.SCENE_BLOCKS} for i in ids]
+        assert all(r.status == gsr.GSR_OK for r in res)
+        return res, blocks
+
+    exact, be = run(False)
+    capm, bc = run(True)
+    modes = [r.render_mode for r in capm]
+    say(f"[gpu] render modes {modes}")
+    assert all(r.render_mode == 0 for r in exact)
+    # first sight of scenes 0, 1, 2 reads back; the close-up of scene 0 overflows; the rest run
+    # in capacity mode
+    assert modes[0] == 0 and modes[2] == 0 and modes[4] == 0
+    assert modes[1] == 2
+    assert all(modes[i] == 1 for i in (3, 5, 6, 7)), modes
+    for a, b in zip(exact, capm):
+        assert a.step == b.step and abs(a.loss - b.loss) <= 1e-5 * a.loss, (a.id, a.loss, b.loss)
+    for x, y in zip(be, bc):
+        assert rel_l2(y["grads"], x["grads"]) <= 1e-6
+        assert rel_l2(y["adam_m"], x["adam_m"]) <= 1e-6 and rel_l2(y["adam_v"], x["adam_v"]) <= 1e-6
+        # Adam's step is lr * m / (sqrt(v) + eps): equal except where g is at rounding level
+        g = x["grads"]
+        bad = np.abs(y["params"] - x["params"]) > 1e-7 + 1e-6 * np.abs(x["params"])
+        assert np.all(np.abs(g[bad]) <= 1e-6 * np.abs(g).max()), int(bad.sum())
 
 
 def test_one_scene_runs_in_arrival_order(gsr, scenes):
