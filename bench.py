@@ -75,6 +75,7 @@ def parse():
                    help="only the 16-view batched render + backward at this fixed configuration, --steps "
                         "times (for rocprofv3 runs: no autotuning, no graph capture)")
     p.add_argument("--serve-seconds", type=float, default=1.5, help="seconds of arrivals per rate")
+    p.add_argument("--serve-only", action="store_true", help="only the served request stream (its JSON)")
     p.add_argument("--xcd-remap", action="store_true", help="map neighbouring tiles to one XCD")
     p.add_argument("--no-tile-order", action="store_true", help="launch tiles in index order (no longest-first)")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -623,6 +624,11 @@ def main():
         r.close()
         print(json.dumps({"microbench": kind, "bytes": int(mib) << 20, "bytes_per_launch": ops, "ms": ms,
                           "GBs": round(ops / ms / 1e6, 1), "launches": 6}))
+        return
+
+    if args.serve_only:
+        flags = 0 if args.no_lane_split else gsr.GSR_FLAG_LANE_SPLIT_ATOMICS
+        print(json.dumps({"serving": bench_serving(flags, args.serve_seconds)}))
         return
 
     if args.profile_batch:

@@ -406,8 +406,10 @@ typedef struct {
     gsr_config config;        /* render/backward configuration of every batch */
     float lr, beta1, beta2, eps;
     int32_t capacity_render;  /* 1: a batch whose scenes have been rendered before renders with pair
-                                 buffers sized from each scene's last pairs per pixel (x 1.25 + 4096)
-                                 and runs render, loss, backward and Adam without any host
+                                 buffers of 1.5 x max(largest pairs per pixel seen x pixels, largest
+                                 pair count seen) + 65536 per view (memory only: the sorts are
+                                 bounded by the device-side count) and runs render, loss, backward
+                                 and Adam without any host
                                  synchronisation; a request whose pairs overflow skips its Adam
                                  update on the device and is run again with the counts read back
                                  (gsr_result.render_mode). 0: every batch's render reads its counts
@@ -483,8 +485,8 @@ gsr_status gsr_server_results(gsr_server *server, gsr_result *out, int32_t max, 
  * their sizes not - and its camera) into images_chw[i] without any host
  * synchronisation, reusing the states' buffers. Each state's pair buffers
  * hold pair_capacity = P + P/4 + 4096 entries of the P of the gsr_render
- * that created it; the whole capacity is sorted, entries past the current
- * pair count carrying a sentinel tile that sorts last. A view whose pairs
+ * that created it; the tile sort and the ranges are launched for the whole
+ * capacity and bounded on the device by the current pair count. A view whose pairs
  * exceed the capacity loses the excess and sets an overflow flag
  * (gsr_fwd_sync). config NULL = states[0]'s render config; its tile must
  * equal the render's. Afterwards the state's pair count is unknown on the

@@ -100,14 +100,13 @@ hipError_t launch_emit_pairs(int64_t n, const uint32_t *sorted_ids, const uint32
                              const int32_t *radius, const DevCamera &cam, uint32_t *pair_tile, uint32_t *pair_id,
                              int64_t cap, hipStream_t st);
 
-// Capacity mode: positions [*total, cap) get tile `sentinel` (>= every tile index); overflow[0]
-// = (*total > cap).
-hipError_t launch_pad_pairs(const uint32_t *total, int64_t cap, uint32_t sentinel, uint32_t *pair_tile,
-                            uint32_t *pair_id, uint32_t *overflow, hipStream_t st);
+// Capacity mode: overflow[0] = (*total > cap).
+hipError_t launch_pair_overflow(const uint32_t *total, int64_t cap, uint32_t *overflow, hipStream_t st);
 
-// a4: per-tile [start, end) ranges from tile-sorted pairs (ranges zero-filled first; entries
-// with tile >= n_tiles are ignored).
-hipError_t launch_tile_ranges(int64_t P, const uint32_t *sorted_tile, uint2 *ranges, int64_t n_tiles, hipStream_t st);
+// a4: per-tile [start, end) ranges of the first P tile-sorted pairs, every tile written (empty
+// ones as [i, i)); P_dev (nullable) bounds P with a device-side count.
+hipError_t launch_tile_ranges(int64_t P, const uint32_t *P_dev, const uint32_t *sorted_tile, uint2 *ranges,
+                              int64_t n_tiles, hipStream_t st);
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream_t st);
 

@@ -606,17 +606,9 @@ __global__ __launch_bounds__(256) void emit_pairs_kernel(int64_t n, const uint32
     }
 }
 
-// Capacity mode: entries [total, cap) get the sentinel tile (sorted last, ignored by the
-// range kernel); overflow[0] = 1 when the pairs did not fit.
-__global__ __launch_bounds__(256) void pad_pairs_kernel(const uint32_t *total, uint32_t cap, uint32_t sentinel,
-                                                         uint32_t *pair_tile, uint32_t *pair_id, uint32_t *overflow) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t t = total[0];
-    if (i == 0) overflow[0] = t > cap ? 1u : 0u;
-    if (i < cap && i >= t) {
-        pair_tile[i] = sentinel;
-        pair_id[i] = 0u;
-    }
+// Capacity mode: overflow[0] = 1 when the pairs did not fit (the lists then hold the first cap).
+__global__ __launch_bounds__(64) void pair_overflow_kernel(const uint32_t *total, uint32_t cap, uint32_t *overflow) {
+    if (threadIdx.x == 0) overflow[0] = total[0] > cap ? 1u : 0u;
 }
 
 __global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t *p, uint32_t value, int64_t count) {
@@ -626,12 +618,13 @@ __global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t *p, uint32_t val
 
 // Every tile's [start, end) in the tile-sorted list, written once per tile with no
 // clearing pass: thread i (0 <= i <= P) looks at the boundary before position i,
-// between tile a = tile[i - 1] (-1 before the list) and b = tile[i] (n_tiles past it,
-// and for capacity-mode sentinels, which sort last). Where a < b it ends a, starts b
-// and gives each tile strictly between them the empty range [i, i).
-__global__ __launch_bounds__(256) void tile_ranges_kernel(int64_t P, const uint32_t *tile, uint2 *ranges,
-                                                           uint32_t n_tiles) {
+// between tile a = tile[i - 1] (-1 before the list) and b = tile[i] (n_tiles past it).
+// Where a < b it ends a, starts b and gives each tile strictly between them the empty
+// range [i, i). P_dev (nullable): a device-side count that bounds P (capacity mode).
+__global__ __launch_bounds__(256) void tile_ranges_kernel(int64_t P, const uint32_t *P_dev, const uint32_t *tile,
+                                                           uint2 *ranges, uint32_t n_tiles) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (P_dev && (int64_t)*P_dev < P) P = *P_dev;
     if (i > P) return;
     const int64_t a = i == 0 ? -1 : (int64_t)min(tile[i - 1], n_tiles);
     const int64_t b = i == P ? (int64_t)n_tiles : (int64_t)min(tile[i], n_tiles);
@@ -653,11 +646,8 @@ hipError_t launch_emit_pairs(int64_t n, const uint32_t *sorted_ids, const uint32
     return hipGetLastError();
 }
 
-hipError_t launch_pad_pairs(const uint32_t *total, int64_t cap, uint32_t sentinel, uint32_t *pair_tile,
-                            uint32_t *pair_id, uint32_t *overflow, hipStream_t st) {
-    const int64_t threads = cap > 1 ? cap : 1;
-    pad_pairs_kernel<<<(unsigned)((threads + 255) / 256), 256, 0, st>>>(total, (uint32_t)cap, sentinel, pair_tile,
-                                                                        pair_id, overflow);
+hipError_t launch_pair_overflow(const uint32_t *total, int64_t cap, uint32_t *overflow, hipStream_t st) {
+    pair_overflow_kernel<<<1, 64, 0, st>>>(total, (uint32_t)cap, overflow);
     return hipGetLastError();
 }
 
@@ -667,11 +657,12 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream
     return hipGetLastError();
 }
 
-hipError_t launch_tile_ranges(int64_t P, const uint32_t *sorted_tile, uint2 *ranges, int64_t n_tiles,
-                              hipStream_t st) {
+hipError_t launch_tile_ranges(int64_t P, const uint32_t *P_dev, const uint32_t *sorted_tile, uint2 *ranges,
+                              int64_t n_tiles, hipStream_t st) {
     if (n_tiles <= 0) return hipSuccess;
     if (P < 0) P = 0;
-    tile_ranges_kernel<<<(unsigned)((P + 1 + 255) / 256), 256, 0, st>>>(P, sorted_tile, ranges, (uint32_t)n_tiles);
+    tile_ranges_kernel<<<(unsigned)((P + 1 + 255) / 256), 256, 0, st>>>(P, P_dev, sorted_tile, ranges,
+                                                                      (uint32_t)n_tiles);
     return hipGetLastError();
 }
 

@@ -556,7 +556,8 @@ gsr_status render_views(gsr_ctx *ctx, int nv, const gsr_scene *scenes, const gsr
     }
     mark(ctx, tm, EV_R4);
     // a4: per-tile ranges
-    for (int v = 0; v < nv; ++v) GSR_RH(launch_tile_ranges(sts[v]->P, sorted_tile[v], sts[v]->ranges, sts[v]->n_tiles, s));
+    for (int v = 0; v < nv; ++v)
+        GSR_RH(launch_tile_ranges(sts[v]->P, nullptr, sorted_tile[v], sts[v]->ranges, sts[v]->n_tiles, s));
     mark(ctx, tm, EV_R5);
     GSR_RT(enqueue_composite_fwd(ctx, nv, sts, images, config, nullptr, tm));
 #undef GSR_RT
@@ -566,9 +567,10 @@ gsr_status render_views(gsr_ctx *ctx, int nv, const gsr_scene *scenes, const gsr
 }
 
 // Capacity mode: re-renders existing states (their scenes' current contents, their cameras)
-// into their own buffers without any host synchronisation. Each view sorts its whole pair
-// capacity, the entries past its pair count carrying a sentinel tile that sorts last; a view
-// whose pairs exceed the capacity sets its overflow flag (gsr_fwd_sync reports it).
+// into their own buffers without any host synchronisation. Each view's tile sort and ranges are
+// launched for its whole pair capacity and bounded on the device by its pair count (blocks past
+// it exit at once); a view whose pairs exceed the capacity keeps the first pair_cap pairs and
+// sets its overflow flag (gsr_fwd_sync reports it).
 gsr_status rerender_views(gsr_ctx *ctx, int nv, gsr_fwd *const *sts, float *const *images, const gsr_config *config,
                           uint2 *work_buf, bool tm) {
     hipStream_t s = ctx->stream;
@@ -582,21 +584,22 @@ gsr_status rerender_views(gsr_ctx *ctx, int nv, gsr_fwd *const *sts, float *cons
         gsr_fwd *st = sts[v];
         GSR_HIP(ctx, launch_emit_pairs(st->n, st->sorted_ids_by_depth, st->offsets, st->rec, st->radius, st->dcam,
                                        st->pair_tile, st->pair_id, st->pair_cap, s));
-        GSR_HIP(ctx, launch_pad_pairs(st->totals, st->pair_cap, (uint32_t)st->n_tiles, st->pair_tile, st->pair_id,
-                                      st->totals + 2, s));
+        GSR_HIP(ctx, launch_pair_overflow(st->totals, st->pair_cap, st->totals + 2, s));
     }
     mark(ctx, tm, EV_R3);
     for (int v = 0; v < nv; ++v) {
         gsr_fwd *st = sts[v];
         int which = 0;
         GSR_HIP(ctx, radix_sort_pairs(st->pair_tile, st->pair_id, st->pair_tile_alt, st->pair_id_alt, st->pair_cap,
-                                      bits_for(st->n_tiles + 1), st->tsort_hist, st->tsort_partials, &which, s));
+                                      bits_for(st->n_tiles), st->tsort_hist, st->tsort_partials, &which, s,
+                                      st->totals));
         sorted_tile[v] = which ? st->pair_tile_alt : st->pair_tile;
         st->sorted_pair_id = which ? st->pair_id_alt : st->pair_id;
     }
     mark(ctx, tm, EV_R4);
     for (int v = 0; v < nv; ++v)
-        GSR_HIP(ctx, launch_tile_ranges(sts[v]->pair_cap, sorted_tile[v], sts[v]->ranges, sts[v]->n_tiles, s));
+        GSR_HIP(ctx, launch_tile_ranges(sts[v]->pair_cap, sts[v]->totals, sorted_tile[v], sts[v]->ranges,
+                                        sts[v]->n_tiles, s));
     mark(ctx, tm, EV_R5);
     return enqueue_composite_fwd(ctx, nv, sts, images, config, work_buf, tm);
 }

@@ -33,6 +33,18 @@ struct Scene {
     bool busy = false;      // a request of this scene is in flight
     int32_t queued = 0;     // requests waiting in the queue
     double pairs_per_px = 0.0; // last observed (tile, Gaussian) pairs per pixel
+    double ppp_max = 0.0;      // largest pairs per pixel and largest pair count observed: pairs per pixel
+    int64_t pairs_max = 0;     // hold across resolutions for large splats, the count for small ones
+    void observe(int64_t pairs, double hw) {
+        if (!(hw > 0)) return;
+        pairs_per_px = (double)pairs / hw;
+        ppp_max = std::max(ppp_max, pairs_per_px);
+        pairs_max = std::max(pairs_max, pairs);
+    }
+    // Pair buffers of a capacity-mode render of this scene at hw pixels.
+    int64_t capacity(double hw) const {
+        return (int64_t)(1.5 * std::max(ppp_max * hw, (double)pairs_max)) + 65536;
+    }
 };
 
 struct Pending {
@@ -118,11 +130,13 @@ gsr_status sfail(gsr_server *s, gsr_status st, const char *fmt, ...) {
     return st;
 }
 
-int64_t request_bytes(const Scene &sc, const gsr_camera &cam) {
+int64_t request_bytes(const Scene &sc, const gsr_camera &cam, bool capacity_render) {
     // image, target, dL/dimage, T_final, n_contrib per pixel; projected records, keys, ids,
     // offsets and accumulators per Gaussian; pair keys and ids (with their sort alternates)
-    // per (tile, Gaussian) pair, estimated from the scene's last pairs-per-pixel ratio.
+    // per (tile, Gaussian) pair: the capacity a capacity-mode render will allocate, else the
+    // scene's last pairs-per-pixel ratio.
     const int64_t hw = (int64_t)cam.width * cam.height;
+    if (capacity_render && sc.pairs_per_px > 0.0) return 48 * hw + 160 * sc.n + 16 * sc.capacity((double)hw);
     const double ppp = sc.pairs_per_px > 0.0 ? sc.pairs_per_px : 4.0 * (double)sc.n / (double)(hw > 0 ? hw : 1);
     return 48 * hw + 160 * sc.n + 16 * (int64_t)(ppp * (double)hw);
 }
@@ -171,9 +185,8 @@ bool run_batch(gsr_server *S, Lane &L, Batch &b, std::vector<Scene *> &sc, bool 
     for (int i = 0; i < k; ++i) {
         // The scene's pairs per pixel from its last render (written only by the lane that runs
         // its request, and read by the scheduler only while the scene is idle).
-        const double ppp = sc[i]->pairs_per_px;
-        if (!(ppp > 0.0)) capacity = false;
-        caps[i] = (int64_t)(1.25 * ppp * (double)cams[i].width * (double)cams[i].height) + 4096;
+        if (!(sc[i]->pairs_per_px > 0.0)) capacity = false;
+        caps[i] = sc[i]->capacity((double)cams[i].width * (double)cams[i].height);
     }
     if (status == GSR_OK)
         status = capacity ? render_batch_capacity(c, k, scenes, cams, &S->opts.config, imgs, caps, states)
@@ -203,8 +216,7 @@ bool run_batch(gsr_server *S, Lane &L, Batch &b, std::vector<Scene *> &sc, bool 
         if (states[i]) {
             const double hw = (double)cams[i].width * cams[i].height;
             gsr_fwd_stats_t fs{};
-            if (!capacity && gsr_fwd_stats(states[i], &fs) == GSR_OK && hw > 0)
-                sc[i]->pairs_per_px = (double)fs.n_pairs / hw;
+            if (!capacity && gsr_fwd_stats(states[i], &fs) == GSR_OK) sc[i]->observe(fs.n_pairs, hw);
             gsr_fwd_release(c, states[i]);
         }
     }
@@ -244,7 +256,7 @@ void scheduler_main(gsr_server *S) {
             // The admission scan below starts from the first request whose scene is idle.
             for (const Pending &p : S->queue) {
                 const Scene &s = S->scenes[p.req.scene];
-                if (!s.busy) return fits(request_bytes(s, p.req.camera), 0);
+                if (!s.busy) return fits(request_bytes(s, p.req.camera, S->opts.capacity_render != 0), 0);
             }
             return false;
         });
@@ -259,7 +271,7 @@ void scheduler_main(gsr_server *S) {
                 ++it;
                 continue;
             }
-            const int64_t est = request_bytes(s, it->req.camera);
+            const int64_t est = request_bytes(s, it->req.camera, S->opts.capacity_render != 0);
             if (!fits(est, batch_bytes)) break;
             batch_bytes += est;
             it->est_bytes = est;
@@ -305,10 +317,8 @@ void lane_main(gsr_server *S, Lane *L) {
                 const uint32_t *h = L->counts_host + 4 * i;
                 const gsr_camera &cam = b.reqs[i].req.camera;
                 const double hw = (double)cam.width * cam.height;
-                if (h[2] == 0u) {
-                    if (hw > 0) b.sc[i]->pairs_per_px = (double)h[0] / hw;
-                    continue;
-                }
+                b.sc[i]->observe((int64_t)h[0], hw); // the full count, also when it overflowed
+                if (h[2] == 0u) continue;
                 again.reqs.push_back(b.reqs[i]);
                 again.steps.push_back(b.steps[i]);
                 again.sc.push_back(b.sc[i]);

@@ -164,10 +164,11 @@ def test_capacity_render_same_as_counts_read_back(gsr, scenes):
     request's loss, gradient and Adam state equal those of a server that reads every count back."""
     say("[gpu] server: capacity-mode batches vs counts read back")
     gss = _gpu(scenes[:3])
-    # scene 0 (3000 Gaussians): 0.07 pairs per pixel from far away on a wide image, then 5947
-    # pairs on a 64x64 close-up, above the 1.25 * 0.07 * 4096 + 4096 = 4454 its estimate gives
-    far = sg.make_camera(320, 240, (0.0, 0.0, -30.0))
-    near = sg.make_camera(64, 64, (0.0, 0.0, -2.0))
+    # scene 0 (3000 Gaussians) from far away at 1024x1024: 6520 pairs, so its capacity for the
+    # next 1024x1024 view is 1.5 * max(0.0062 * 1024^2, 6520) + 65536 = 75316 pairs; the close-up
+    # from 1.5 away has 224224
+    far = sg.make_camera(1024, 1024, (0.0, 0.0, -30.0))
+    near = sg.make_camera(1024, 1024, (0.0, 0.0, -1.5))
     cams = _cams(4, seed=61)
     plan = [(0, far, 1), (0, near, 2), (1, cams[0], 3), (1, cams[1], 4), (2, cams[2], 5), (1, cams[3], 6),
             (2, cams[3], 7), (0, cams[0], 8)]
