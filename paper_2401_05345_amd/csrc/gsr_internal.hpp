@@ -76,6 +76,10 @@ hipError_t launch_zero_visible_rows(const int32_t *radius, int64_t n, const uint
 // zeros.
 hipError_t launch_export_acc(const int32_t *radius, const float4 *rec, int64_t n, const void *acc, bool acc_f64,
                              float *dst, hipStream_t st);
+// mean2d [n,2], conic_opacity [n,4] (A, B, C, o), rgb [n,3], depth [n] out of the records, zeros
+// for culled Gaussians (radius 0); any output may be null.
+hipError_t launch_export_rec(const int32_t *radius, const float4 *rec, int64_t n, float *mean2d,
+                             float *conic_opacity, float *rgb, float *depth, hipStream_t st);
 
 // Exclusive scan of n uint32 values (in[gather[i]] when gather != nullptr; out may equal in when
 // gather is nullptr, and must alias neither in nor gather when it is not). total (device, may be

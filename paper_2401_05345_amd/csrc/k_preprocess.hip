@@ -190,7 +190,6 @@ __global__ __launch_bounds__(256) void preprocess_fwd_kernel(int n, const float 
     ids[i] = (uint32_t)i;
     const float mx = means[3 * i], my = means[3 * i + 1], mz = means[3 * i + 2];
     const float tz = depth_of(cam, mx, my, mz);
-    const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
 
     bool vis = tz > cam.znear;
     Proj p;
@@ -216,9 +215,8 @@ __global__ __launch_bounds__(256) void preprocess_fwd_kernel(int n, const float 
         vis = ntiles > 0;
     }
     if (!vis) {
-        rec[3 * (int64_t)i] = zero;
-        rec[3 * (int64_t)i + 1] = zero;
-        rec[3 * (int64_t)i + 2] = zero;
+        // A culled Gaussian's record is never read (lists and rows hold visible ones only; the
+        // export writes zeros for it), so only its counters are written.
         radius[i] = 0;
         tiles_touched[i] = 0;
         depth_key[i] = 0xffffffffu;
@@ -675,6 +673,45 @@ hipError_t launch_zero_visible_rows(const int32_t *radius, int64_t n, const uint
     }
     if (n <= 0) return hipSuccess;
     zero_visible_rows_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(radius, n, static_cast<uint4 *>(acc), chunks);
+    return hipGetLastError();
+}
+
+// The projected quantities of every Gaussian out of the 48-byte records (u, v, A, B)
+// (C, o, r, g) (b, id, reach, depth), zeros for culled ones (whose records are never
+// written). Each output is optional.
+__global__ __launch_bounds__(256) void export_rec_kernel(const int32_t *radius, const float4 *rec, int64_t n,
+                                                         float *mean2d, float *conic_opacity, float *rgb,
+                                                         float *depth) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a, c = a;
+    if (radius[i] > 0) {
+        a = rec[3 * i];
+        b = rec[3 * i + 1];
+        c = rec[3 * i + 2];
+    }
+    if (mean2d) {
+        mean2d[2 * i] = a.x;
+        mean2d[2 * i + 1] = a.y;
+    }
+    if (conic_opacity) {
+        conic_opacity[4 * i] = a.z;
+        conic_opacity[4 * i + 1] = a.w;
+        conic_opacity[4 * i + 2] = b.x;
+        conic_opacity[4 * i + 3] = b.y;
+    }
+    if (rgb) {
+        rgb[3 * i] = b.z;
+        rgb[3 * i + 1] = b.w;
+        rgb[3 * i + 2] = c.x;
+    }
+    if (depth) depth[i] = c.w;
+}
+
+hipError_t launch_export_rec(const int32_t *radius, const float4 *rec, int64_t n, float *mean2d,
+                             float *conic_opacity, float *rgb, float *depth, hipStream_t st) {
+    if (n <= 0 || !(mean2d || conic_opacity || rgb || depth)) return hipSuccess;
+    export_rec_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(radius, rec, n, mean2d, conic_opacity, rgb, depth);
     return hipGetLastError();
 }
 

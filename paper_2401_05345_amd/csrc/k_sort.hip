@@ -364,9 +364,29 @@ __global__ __launch_bounds__(kThreads) void radix_hist_kernel(const uint32_t *ke
     uint32_t k[ITEMS];
     const auto pos = [&](int r) { return base + (int64_t)r * kThreads; };
     load_items<ITEMS, false>(keys, nullptr, n, pos, k);
+    // A narrow digit (the top pass of the tile sort: a few dozen values over long sorted runs)
+    // puts many lanes of a wave on one LDS counter, where their atomics serialise: lanes find
+    // their equal-digit peers with one ballot per bit and one lane adds the group's size. Wide
+    // digits vary from lane to lane and keep one atomic per lane (measured faster there).
+    const int nbits = __popc(mask);
+    const int lane = threadIdx.x & 63;
+    if (nbits <= 5) {
 #pragma unroll
-    for (int r = 0; r < ITEMS; ++r)
-        if (pos(r) < n) atomicAdd(&s_count[(k[r] >> shift) & mask], 1u);
+        for (int r = 0; r < ITEMS; ++r) {
+            const bool valid = pos(r) < n;
+            const uint32_t d = (k[r] >> shift) & mask;
+            uint64_t peers = __ballot(valid);
+            for (int b = 0; b < nbits; ++b) {
+                const uint64_t bal = __ballot((d >> b) & 1u);
+                peers &= ((d >> b) & 1u) ? bal : ~bal;
+            }
+            if (valid && __ffsll((long long)peers) - 1 == lane) atomicAdd(&s_count[d], (uint32_t)__popcll(peers));
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < ITEMS; ++r)
+            if (pos(r) < n) atomicAdd(&s_count[(k[r] >> shift) & mask], 1u);
+    }
     __syncthreads();
     if (threadIdx.x <= mask) hist[(int64_t)threadIdx.x * stride + blockIdx.x] = s_count[threadIdx.x];
 }

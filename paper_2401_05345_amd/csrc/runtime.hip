@@ -1225,25 +1225,8 @@ gsr_status gsr_fwd_export(gsr_ctx *ctx, const gsr_fwd *st, const gsr_fwd_export_
     GSR_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
     const int64_t n = st->n, hw = (int64_t)st->camera.width * st->camera.height;
-    const auto cp = [&](void *dst, const void *src, size_t bytes, size_t spitch, size_t dpitch, size_t width,
-                        size_t rows) -> hipError_t {
-        if (!dst || rows == 0) return hipSuccess;
-        if (spitch == dpitch && spitch == width) return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s);
-        return hipMemcpy2DAsync(dst, dpitch, src, spitch, width, rows, hipMemcpyDeviceToDevice, s);
-    };
     if (n > 0) {
-        // rec rows are 48 bytes: (u, v, A, B) (C, o, r, g) (b, id, reach, depth)
-        const float *rec = reinterpret_cast<const float *>(st->rec);
-        GSR_HIP(ctx, cp(d->mean2d, rec, 0, 48, 8, 8, n));
-        if (d->conic_opacity) {
-            GSR_HIP(ctx, hipMemcpy2DAsync(d->conic_opacity, 16, rec + 2, 48, 8, n, hipMemcpyDeviceToDevice, s));
-            GSR_HIP(ctx, hipMemcpy2DAsync(d->conic_opacity + 2, 16, rec + 4, 48, 8, n, hipMemcpyDeviceToDevice, s));
-        }
-        if (d->rgb) {
-            GSR_HIP(ctx, hipMemcpy2DAsync(d->rgb, 12, rec + 6, 48, 8, n, hipMemcpyDeviceToDevice, s));
-            GSR_HIP(ctx, hipMemcpy2DAsync(d->rgb + 2, 12, rec + 8, 48, 4, n, hipMemcpyDeviceToDevice, s));
-        }
-        GSR_HIP(ctx, cp(d->depth, rec + 11, 0, 48, 4, 4, n));
+        GSR_HIP(ctx, launch_export_rec(st->radius, st->rec, n, d->mean2d, d->conic_opacity, d->rgb, d->depth, s));
         if (d->radius) GSR_HIP(ctx, hipMemcpyAsync(d->radius, st->radius, n * 4, hipMemcpyDeviceToDevice, s));
         if (d->tiles_touched)
             GSR_HIP(ctx, hipMemcpyAsync(d->tiles_touched, st->tiles_touched, n * 4, hipMemcpyDeviceToDevice, s));
