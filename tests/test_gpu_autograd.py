@@ -62,16 +62,19 @@ def test_autograd_on_large_crop_matches_oracle(renderer):
 
 
 def test_autograd_fp32_finite_differences(renderer):
-    # SH enters linearly (away from the colour clamp) and opacity smoothly: fp32 central
-    # differences of the GPU forward agree with the GPU gradient to fp32 precision.
+    # Central differences of the GPU forward (fp32 image, the weighted sum taken in fp64) against
+    # the GPU gradient, for all five tensors. SH enters linearly (away from the colour clamp) and
+    # opacity smoothly; the geometry (means, log-scales, quaternions) is smooth too except where a
+    # step moves a splat across a tile edge or an alpha threshold, which a small step rarely does
+    # (the median over the sampled entries is the bound, the worst entry is reported).
     import torch
     say("[gpu] autograd fp32 FD")
     sub, cam, w, _, _ = large_crop()
-    wt = torch.from_numpy(w.astype(np.float32)).cuda()
+    wt = torch.from_numpy(w.astype(np.float32)).cuda().double()
     params = _params(sub)
-    (rasterize(*params, renderer=renderer, camera=_cam(cam)) * wt).sum().backward()
+    (rasterize(*params, renderer=renderer, camera=_cam(cam)) * wt.float()).sum().backward()
     rng = np.random.default_rng(9)
-    for ti, h in ((4, 1e-2), (3, 1e-2)):
+    for ti, h in ((4, 1e-2), (3, 1e-2), (0, 1e-3), (1, 1e-3), (2, 1e-3)):
         grad = params[ti].grad.cpu().numpy().reshape(-1)
         fd, an = [], []
         for j in rng.choice(grad.size, 24, replace=False):
@@ -80,13 +83,14 @@ def test_autograd_fp32_finite_differences(renderer):
                 q = [p.detach().clone() for p in params]
                 q[ti].view(-1)[j] += s
                 with torch.no_grad():
-                    vals.append(float((rasterize(*q, renderer=renderer, camera=_cam(cam)) * wt).sum()))
+                    img = rasterize(*q, renderer=renderer, camera=_cam(cam))
+                    vals.append(float((img.double() * wt).sum()))
             fd.append((vals[0] - vals[1]) / (2 * h))
             an.append(grad[j])
         fd, an = np.array(fd), np.array(an)
         err = np.abs(fd - an) / (np.abs(an).max() + 1e-12)
         say(f"[gpu] fp32 FD tensor {NAMES[ti]}: median rel {np.median(err):.2e}, max {err.max():.2e}")
-        assert np.median(err) <= 1e-2
+        assert np.median(err) <= 1e-2, (NAMES[ti], np.median(err))
 
 
 def test_autograd_full_large_view_equals_direct_backward(renderer):
