@@ -373,6 +373,12 @@ __global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(ViewBatch vb,
             const bool active = walked && e.pass;
             // the ballot as the AND of the three compares' own lane masks
             const uint64_t am = __ballot(walked) & __ballot(!(e.lp > 0.0f)) & __ballot(e.alpha >= kAlphaMin);
+            // No lane takes the entry (an eighth of the visits): T, S and the sums stay exactly as
+            // they are, so the wave skips the rest.
+            if (am == 0) {
+                if (COUNT) c_visit += 1;
+                return;
+            }
             // Lanes that skip this entry run the same arithmetic with alpha and G set to zero:
             // their nine values come out as zeros and T, S stay as they are (the hardware
             // reciprocal of 1 is exactly 1).
