@@ -328,6 +328,11 @@ __global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(ViewBatch vb,
     // Q <- Q + alpha (c - Q) of the three channels carried as one number S = Q . dL/dpixel.
     float S = cam.bg[0] * G0 + cam.bg[1] * G1 + cam.bg[2] * G2;
     const uint2 rg = a.ranges[tile];
+    // The view's pointers in registers: read through the descriptor, they would be loaded again
+    // after every atomic (the compiler cannot tell that the adds leave the descriptor alone).
+    AccT *const acc = static_cast<AccT *>(a.acc);
+    const float4 *const rec = a.rec;
+    const uint32_t *const ids = a.ids + rg.x;
 
     if (tid == 0) s_walk = 0;
     if (COUNT)
@@ -354,7 +359,7 @@ __global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(ViewBatch vb,
         const int start = end > BATCH ? end - BATCH : 0;
         const int cnt = end - start;
         __syncthreads();
-        if (tid < cnt) stage_record(a.rec, a.ids[rg.x + start + tid], s0[tid], s1[tid], s2[tid]);
+        if (tid < cnt) stage_record(rec, ids[start + tid], s0[tid], s1[tid], s2[tid]);
         if (BLOCK) {
             for (int i = tid; i < cnt * 9; i += TILE * TILE) s_acc[i] = 0.0f;
             if (tid < cnt) s_touch[tid] = 0u;
@@ -411,7 +416,7 @@ __global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(ViewBatch vb,
             // The record carries its Gaussian's id (the same in every lane): the row address is
             // formed in scalar registers.
             const uint32_t gid = (uint32_t)__builtin_amdgcn_readfirstlane((int)__float_as_uint(r2.y));
-            AccT *dst = static_cast<AccT *>(a.acc) + (size_t)gid * GSR_ACC_STRIDE;
+            AccT *dst = acc + (size_t)gid * GSR_ACC_STRIDE;
             uint64_t red_mask = 0;
             if (BLOCK) {
                 if (__popcll(am) >= p.threshold) {
@@ -468,7 +473,7 @@ __global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(ViewBatch vb,
                 const int e = i / 9;
                 const bool f = s_touch[e] != 0u;
                 if (f) {
-                    atomic_acc(static_cast<AccT *>(a.acc) + (size_t)__float_as_uint(s2[e].y) * GSR_ACC_STRIDE +
+                    atomic_acc(acc + (size_t)__float_as_uint(s2[e].y) * GSR_ACC_STRIDE +
                                    (i - 9 * e), s_acc[i]);
                     ++issued;
                 }
