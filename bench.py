@@ -39,12 +39,14 @@ sys.path.insert(0, ROOT)
 THRESHOLDS = [1, 2, 4, 8, 16, 24, 32, 48, 64]
 PEAK_FP32_VALU_TFLOPS = 157.3     # MI355X fp32 vector peak (256 CUs x 2.4 GHz x 256 flop/clk)
 PEAK_HBM_GBS = 8000.0
-# Algorithmic fp32 work of the backward composite: per walked
-# (pixel, entry) pair the splat evaluation (offset, quadratic form, exp, alpha),
-# per contributing pair the transmittance recovery and the nine gradient values.
-FLOPS_PER_EVAL = 14
-FLOPS_PER_CONTRIB = 40
-BYTES_PER_RECORD = 40             # id + mean2d + conic + opacity + rgb, read once per tile-list entry walked
+# Algorithmic fp32 work of the backward composite: per evaluated (pixel, entry) pair the splat
+# evaluation (offset, quadratic form, exp), per contributing pair the transmittance division,
+# colour update, dL/dalpha and the nine gradient values, per reduced wave-entry the nine values'
+# six butterfly steps (12 E + 45 A + 54 W_R).
+FLOPS_PER_EVAL = 12
+FLOPS_PER_CONTRIB = 45
+FLOPS_PER_REDUCED = 54
+BYTES_PER_RECORD = 40             # id + mean2d + conic + opacity + rgb, read once per entry a tile's block walks
 BYTES_PER_PIXEL = 20              # dL/dI (12) + T_final (4) + n_contrib (4)
 BYTES_PER_VISIBLE = 72            # nine fp64 sums written back once (their clearing excluded; a7 reads them)
 
@@ -541,6 +543,7 @@ def ab_summary(res, cnt, stats, thr, sweep):
         "atomic_instrs_plain": int(cp.atomic_instrs), "atomic_instrs_reduce": int(cr.atomic_instrs),
         "evaluated_E": int(cr.evaluated), "active_A": int(cr.active), "wave_entries": int(cr.wave_entries),
         "visited_wave_entries": int(cr.visited), "longest_wave_walk": int(cr.max_wave_visits),
+        "walked_entries_P_walk": int(cr.walked),
         "reduced_W_R": int(cr.reduced), "plain_lanes_A_lt": int(cr.plain_lanes),
         "threshold_sweep_ms": sweep,
         "accumulator_note": ("fp64 accumulators (default) meet the 1e-3 gradient tolerance against the oracle; "
@@ -567,13 +570,15 @@ def rooflines(wl, stats, cr, a6_ms, a7_ms):
     hw = wl.camera.width * wl.camera.height
     n, n_vis = wl.scene.n, int(stats.n_visible)
     K3 = 3 * (wl.scene.sh_degree + 1) ** 2
-    flops = FLOPS_PER_EVAL * cr.evaluated + FLOPS_PER_CONTRIB * cr.active
+    flops = FLOPS_PER_EVAL * cr.evaluated + FLOPS_PER_CONTRIB * cr.active + FLOPS_PER_REDUCED * cr.reduced
     a6_tflops = flops / (a6_ms * 1e-3) / 1e12
     pbytes = 4 * (11 + K3)
-    a6_bytes = BYTES_PER_PIXEL * hw + BYTES_PER_VISIBLE * n_vis + BYTES_PER_RECORD * int(stats.n_pairs)
+    # records: the entries the blocks stage (P_walk: each tile's block walks to its deepest pixel's
+    # n_contrib), not all P entries of the lists
+    a6_bytes = BYTES_PER_PIXEL * hw + BYTES_PER_VISIBLE * n_vis + BYTES_PER_RECORD * int(cr.walked)
     a6 = {"bound": "alu", "achieved": round(a6_tflops, 3), "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
           "frac": round(a6_tflops / PEAK_FP32_VALU_TFLOPS, 4), "kernel": "composite_bwd_kernel<16,256,wave_reduce>",
-          "ms": round(a6_ms, 4), "algorithmic_flops": int(flops),
+          "ms": round(a6_ms, 4), "algorithmic_flops": int(flops), "algorithmic_bytes": int(a6_bytes),
           "hbm_GBs_algorithmic": round(a6_bytes / (a6_ms * 1e-3) / 1e9, 1),
           "hbm_frac_algorithmic": round(a6_bytes / (a6_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
     m6 = kernel_counters("composite_bwd", wl.name)

@@ -176,11 +176,13 @@ typedef struct {
  *  hist[c]       wave-entries with c active lanes, c = 0..64 (c = 0 not counted)
  *  visited       (wave, entry) steps the walk took: entries a wave's visit
  *                masks kept, active lanes or not (>= wave_entries)
- *  max_wave_visits  the most entries one wave visited (the longest walk) */
+ *  max_wave_visits  the most entries one wave visited (the longest walk)
+ *  walked        P_walk: list entries staged, summed over tiles (each tile's
+ *                block walks to its deepest pixel's n_contrib) */
 typedef struct {
     uint64_t evaluated, active, wave_entries, reduced, plain_lanes, lane_atomics, atomic_instrs;
     uint64_t hist[65];
-    uint64_t visited, max_wave_visits;
+    uint64_t visited, max_wave_visits, walked;
 } gsr_bwd_counters_t;
 
 /* Milliseconds of the stages of the last gsr_render / gsr_backward with

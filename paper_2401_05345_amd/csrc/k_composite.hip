@@ -292,7 +292,9 @@ __global__ __launch_bounds__(TILE *TILE) void composite_fwd_kernel(ViewBatch vb,
 enum { CNT_EVAL = 0, CNT_ACTIVE, CNT_WAVE_ENTRIES, CNT_REDUCED, CNT_PLAIN_LANES, CNT_LANE_ATOMICS, CNT_INSTRS, CNT_HIST };
 // after the 65 histogram slots: visited wave-entries (every entry a wave's visit masks keep)
 // and the most entries any one wave visited
-constexpr int CNT_VISITED = CNT_HIST + 65, CNT_MAX_WAVE_VISITS = CNT_HIST + 66, CNT_SLOTS = CNT_HIST + 67;
+// and the list entries the blocks staged (each block walks to its deepest pixel's n_contrib)
+constexpr int CNT_VISITED = CNT_HIST + 65, CNT_MAX_WAVE_VISITS = CNT_HIST + 66, CNT_WALKED = CNT_HIST + 67,
+              CNT_SLOTS = CNT_HIST + 68;
 
 template <int TILE, int BATCH, int MODE, bool COUNT, bool SPLIT, typename AccT>
 __global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(ViewBatch vb, int remap,
@@ -493,6 +495,7 @@ __global__ __launch_bounds__(TILE *TILE) void composite_bwd_kernel(ViewBatch vb,
             atomicAdd(&s_cnt[CNT_VISITED], (unsigned long long)c_visit);
             atomicMax(&s_cnt[CNT_MAX_WAVE_VISITS], (unsigned long long)c_visit);
         }
+        if (tid == 0) s_cnt[CNT_WALKED] = (unsigned long long)walk;
         __syncthreads();
         for (int i = tid; i < CNT_SLOTS; i += TILE * TILE)
             if (s_cnt[i]) {

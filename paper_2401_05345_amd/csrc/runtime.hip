@@ -1254,7 +1254,7 @@ gsr_status gsr_bwd_counters(gsr_ctx *ctx, const gsr_fwd *st, gsr_bwd_counters_t 
     if (!st->counters_valid || !st->counters)
         return fail(ctx, GSR_ESTATE, "the last backward did not run with GSR_FLAG_DEBUG_COUNTERS");
     GSR_HIP(ctx, hipSetDevice(ctx->device));
-    unsigned long long h[74];
+    unsigned long long h[75];
     GSR_HIP(ctx, hipMemcpyAsync(h, st->counters, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
     GSR_HIP(ctx, hipStreamSynchronize(ctx->stream));
     out->evaluated = h[0];
@@ -1267,6 +1267,7 @@ gsr_status gsr_bwd_counters(gsr_ctx *ctx, const gsr_fwd *st, gsr_bwd_counters_t 
     for (int i = 0; i < 65; ++i) out->hist[i] = h[7 + i];
     out->visited = h[72];
     out->max_wave_visits = h[73];
+    out->walked = h[74];
     return GSR_OK;
 }
 

@@ -74,7 +74,8 @@ class gsr_fwd_export_t(ctypes.Structure):
 class gsr_bwd_counters_t(ctypes.Structure):
     _fields_ = [("evaluated", c_uint64), ("active", c_uint64), ("wave_entries", c_uint64), ("reduced", c_uint64),
                 ("plain_lanes", c_uint64), ("lane_atomics", c_uint64), ("atomic_instrs", c_uint64),
-                ("hist", c_uint64 * 65), ("visited", c_uint64), ("max_wave_visits", c_uint64)]
+                ("hist", c_uint64 * 65), ("visited", c_uint64), ("max_wave_visits", c_uint64),
+                ("walked", c_uint64)]
 
 
 class gsr_stage_times_t(ctypes.Structure):

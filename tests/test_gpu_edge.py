@@ -180,6 +180,12 @@ def test_backward_counters_match_the_atomic_count_model(renderer):
             assert hist[0] == 0 and hist.sum() == c.wave_entries and (hist * lanes).sum() == c.active
             # every visited entry is a step of one wave's walk; the longest walk is one of them
             assert c.visited >= c.wave_entries and 0 < c.max_wave_visits <= c.visited
+            # P_walk: every tile's block stages its list up to its deepest pixel's n_contrib
+            nc = out["n_contrib"].astype(np.int64)
+            gx, gy = -(-cam.width // 16), -(-cam.height // 16)
+            pad = np.zeros((gy * 16, gx * 16), np.int64)
+            pad[:cam.height, :cam.width] = nc
+            assert c.walked == int(pad.reshape(gy, 16, gx, 16).max(axis=(1, 3)).sum())
             t = max(thr, 1)
             if mode == gsr.GSR_BWD_PLAIN_ATOMIC:
                 assert c.reduced == 0 and c.plain_lanes == c.active
