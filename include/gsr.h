@@ -566,8 +566,8 @@ gsr_status gsr_wave_reduce_selftest(gsr_ctx *ctx, const float *vals, const uint8
 
 /* Measurement utility (not part of rendering): one memory-operation
  * pattern of the backward composite, timed alone, to measure the roofs the
- * kernels are held against (the survey of the method asks for a measured
- * atomic rate, there being no published one for this GPU).
+ * kernels are held against (no atomic rate is published for this GPU, so
+ * it is measured).
  *   GSR_MB_COPY                   float4 copy of bytes/2 into the other half
  *                                 (ops = bytes read + written: HBM bandwidth)
  *   GSR_MB_ATOMIC_F32_DISTINCT    no-return fp32 adds, every lane its own
