@@ -188,9 +188,15 @@ bool run_batch(gsr_server *S, Lane &L, Batch &b, std::vector<Scene *> &sc, bool 
         if (!(sc[i]->pairs_per_px > 0.0)) capacity = false;
         caps[i] = sc[i]->capacity((double)cams[i].width * (double)cams[i].height);
     }
-    if (status == GSR_OK)
-        status = capacity ? render_batch_capacity(c, k, scenes, cams, &S->opts.config, imgs, caps, states)
-                          : gsr_render_batch(c, k, scenes, cams, &S->opts.config, imgs, states);
+    if (status == GSR_OK && capacity) {
+        status = render_batch_capacity(c, k, scenes, cams, &S->opts.config, imgs, caps, states);
+        // capacities that do not fit in device memory: the batch reads its counts back instead
+        if (status == GSR_ENOMEM) {
+            capacity = false;
+            status = GSR_OK;
+        }
+    }
+    if (status == GSR_OK && !capacity) status = gsr_render_batch(c, k, scenes, cams, &S->opts.config, imgs, states);
     for (int i = 0; i < k && status == GSR_OK; ++i) {
         const int64_t n3 = 3 * (int64_t)cams[i].width * cams[i].height;
         if (launch_l1_sum(imgs[i], tgts[i], n3, L.loss_dev + i, st) != hipSuccess) status = GSR_EHIP;
