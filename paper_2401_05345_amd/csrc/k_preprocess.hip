@@ -448,16 +448,20 @@ __device__ __forceinline__ void gaussian_grads(int64_t i, const float *__restric
 // values and its 3 clamped colour gradients in an LDS row. Then the block writes its whole
 // segment of every output array, zeros for culled Gaussians included, as consecutive 16-byte
 // non-temporal stores (one float per lane and store when unaligned); with accumulate = 1 it adds
-// to the visible rows only.
+// to the visible rows only. Culled Gaussians point at an all-zero LDS row, so every output value
+// is read the same way, without a branch per value.
 // One wave per block: at 3M Gaussians / 1080p blocks of 64 rows measured 0.212 ms, of 128 rows
 // 0.214 ms and of 256 rows 0.220 ms; more, smaller blocks overlap one block's chain rule with
 // other blocks' writes.
 constexpr int kA7Block = 64;
+constexpr int kA7ZeroRow = kA7Block; // the all-zero row culled Gaussians read
 
 template <int DEG>
 struct A7Layout {
     static constexpr int K = (DEG + 1) * (DEG + 1);
-    static constexpr int ROW = 11 + K + 3;     // gradients, basis values, colour gradients
+    static constexpr int Y = 11;                // basis values
+    static constexpr int G = 11 + K;            // colour gradients g0 g1 g2, then g0 g1 again
+    static constexpr int ROW = 11 + K + 5;
     static constexpr int PITCH = ROW | 1;       // odd: rows written by consecutive lanes hit distinct banks
 };
 
@@ -477,7 +481,7 @@ __device__ __forceinline__ void a7_write(float *__restrict__ dst, int count, boo
     const int m = count * W;
     if (mode == A7_ADD) {
         for (int e = threadIdx.x; e < m; e += kA7Block)
-            if (slot[e / W] >= 0) dst[e] += val(e);
+            if (slot[e / W] != kA7ZeroRow) dst[e] += val(e);
         return;
     }
     int e0 = 0;
@@ -493,6 +497,47 @@ __device__ __forceinline__ void a7_write(float *__restrict__ dst, int count, boo
     for (int e = e0 + threadIdx.x; e < m; e += kA7Block) dst[e] = val(e);
 }
 
+// The SH segment (rows of 3K floats, value 3k + ch = Y[k] g[ch]) as 16-byte non-temporal stores,
+// for 3K a multiple of 4, so that each store lies in one row. A store starting at value 4m of
+// its row covers k0 = floor(4m / 3) and k0 + 1 and the channels c0, c0 + 1, c0 + 2, c0 (mod 3)
+// with c0 = m mod 3; the row's colour gradients stored as g0 g1 g2 g0 g1 give the three
+// channels in that order at consecutive addresses.
+// m mod 3 and floor(m / 3) for m < 12, as 2-bit fields (field m at bit 2m)
+constexpr uint32_t a7_pack_thirds(bool quotient) {
+    uint32_t t = 0;
+    for (int m = 0; m < 12; ++m) t |= (uint32_t)(quotient ? m / 3 : m % 3) << (2 * m);
+    return t;
+}
+constexpr uint32_t kA7Mod3 = a7_pack_thirds(false), kA7Div3 = a7_pack_thirds(true);
+
+template <int DEG>
+__device__ __forceinline__ void a7_write_sh4(float *__restrict__ dst, int count, const int16_t *slot,
+                                             const float *s_row) {
+    using L = A7Layout<DEG>;
+    constexpr int F4 = 3 * L::K / 4; // stores per row
+    static_assert(F4 * 4 == 3 * L::K && F4 <= 12, "rows of whole 16-byte stores, m < 12");
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    v4f *d4 = reinterpret_cast<v4f *>(dst);
+    const int m4 = count * F4;
+    // row q and store m within it, stepped as c advances by kA7Block
+    int q = (int)threadIdx.x / F4, m = (int)threadIdx.x - q * F4;
+    for (int c = threadIdx.x; c < m4; c += kA7Block) {
+        const int c0 = (int)((kA7Mod3 >> (2 * m)) & 3u);
+        const int k0 = m + (int)((kA7Div3 >> (2 * m)) & 3u); // floor(4m / 3)
+        const float *row = s_row + slot[q] * L::PITCH;
+        const float ya = row[L::Y + k0], yb = row[L::Y + k0 + 1];
+        const float ga = row[L::G + c0], gb = row[L::G + c0 + 1], gc = row[L::G + c0 + 2];
+        const v4f v = {ya * ga, (c0 == 2 ? yb : ya) * gb, (c0 >= 1 ? yb : ya) * gc, yb * ga};
+        __builtin_nontemporal_store(v, d4 + c);
+        q += kA7Block / F4;
+        m += kA7Block % F4;
+        if (m >= F4) {
+            m -= F4;
+            ++q;
+        }
+    }
+}
+
 template <int DEG, typename AccT>
 __global__ __launch_bounds__(kA7Block) void preprocess_bwd_kernel(int n, const float *__restrict__ means,
                                                                   const float *__restrict__ log_scales,
@@ -504,8 +549,8 @@ __global__ __launch_bounds__(kA7Block) void preprocess_bwd_kernel(int n, const f
                                                                   int mode, int aligned) {
     using L = A7Layout<DEG>;
     constexpr int K = L::K, NS = 3 * K, PITCH = L::PITCH;
-    __shared__ float s_row[kA7Block * PITCH];
-    __shared__ int16_t s_slot[kA7Block];   // LDS row of each Gaussian of the block, -1 = culled
+    __shared__ float s_row[(kA7Block + 1) * PITCH];
+    __shared__ int16_t s_slot[kA7Block];   // LDS row of each Gaussian of the block, kA7ZeroRow = culled
     __shared__ int16_t s_list[kA7Block];   // block-local indices of the visible Gaussians
     __shared__ int s_wave_count[kA7Block / 64];
     const int64_t g0 = (int64_t)blockIdx.x * kA7Block;
@@ -516,6 +561,7 @@ __global__ __launch_bounds__(kA7Block) void preprocess_bwd_kernel(int n, const f
     const bool vis = t < count && radius[g0 + t] > 0;
     const uint64_t mask = __ballot(vis);
     if (lane == 0) s_wave_count[wave] = __popcll(mask);
+    for (int k = t; k < PITCH; k += kA7Block) s_row[kA7ZeroRow * PITCH + k] = 0.0f;
     __syncthreads();
     int before = 0, nv = 0;
 #pragma unroll
@@ -524,7 +570,7 @@ __global__ __launch_bounds__(kA7Block) void preprocess_bwd_kernel(int n, const f
         nv += s_wave_count[w];
     }
     const int rank = before + __popcll(mask & ((1ull << lane) - 1ull));
-    s_slot[t] = vis ? (int16_t)rank : (int16_t)-1;
+    s_slot[t] = vis ? (int16_t)rank : (int16_t)kA7ZeroRow;
     if (vis) s_list[rank] = (int16_t)t;
     __syncthreads();
     if (mode == A7_ADD && nv == 0) return;
@@ -538,28 +584,31 @@ __global__ __launch_bounds__(kA7Block) void preprocess_bwd_kernel(int n, const f
 #pragma unroll
         for (int k = 0; k < 11; ++k) row[k] = o[k];
 #pragma unroll
-        for (int k = 0; k < K; ++k) row[11 + k] = Y[k];
+        for (int k = 0; k < K; ++k) row[L::Y + k] = Y[k];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) row[11 + K + c] = g[c];
+        for (int c = 0; c < 5; ++c) row[L::G + c] = g[c % 3];
     }
     __syncthreads();
 
     // ---- the block's segment of each output array, culled rows as zeros ----
     const bool vec = aligned != 0;
     const auto field = [&](int W, int off) {
-        return [=](int e) {
-            const int s = s_slot[e / W];
-            return s >= 0 ? s_row[s * PITCH + off + e % W] : 0.0f;
-        };
+        return [=](int e) { return s_row[s_slot[e / W] * PITCH + off + e % W]; };
     };
     a7_write<3>(out.means3d + 3 * g0, count, vec, mode, s_slot, field(3, 0));
     a7_write<3>(out.log_scales + 3 * g0, count, vec, mode, s_slot, field(3, 3));
     a7_write<4>(out.quats + 4 * g0, count, vec, mode, s_slot, field(4, 6));
     a7_write<1>(out.opacity_logits + g0, count, vec, mode, s_slot, field(1, 10));
+    if constexpr (NS % 4 == 0) {
+        if (vec && mode == A7_ALL) {
+            a7_write_sh4<DEG>(out.sh + NS * g0, count, s_slot, s_row);
+            return;
+        }
+    }
     a7_write<NS>(out.sh + NS * g0, count, vec, mode, s_slot, [=](int e) {
-        const int s = s_slot[e / NS];
+        const float *row = s_row + s_slot[e / NS] * PITCH;
         const int r = e % NS;
-        return s >= 0 ? s_row[s * PITCH + 11 + r / 3] * s_row[s * PITCH + 11 + K + r % 3] : 0.0f;
+        return row[L::Y + r / 3] * row[L::G + r % 3];
     });
 }
 
