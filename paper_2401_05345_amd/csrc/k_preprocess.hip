@@ -442,7 +442,7 @@ __device__ __forceinline__ void gaussian_grads(int64_t i, const float *__restric
     o[10] = go * op * (1.0f - op);
 }
 
-// a7 over blocks of kA7Block consecutive Gaussians. The block first lists its visible Gaussians
+// a7 over blocks of kA7Rows consecutive Gaussians. The block first lists its visible Gaussians
 // (radius > 0) in LDS, so that their chain rule runs on dense lanes (a view from inside the
 // cloud keeps about a quarter of them); each computed Gaussian leaves 11 gradients, its K basis
 // values and its 3 clamped colour gradients in an LDS row. Then the block writes its whole
@@ -450,11 +450,13 @@ __device__ __forceinline__ void gaussian_grads(int64_t i, const float *__restric
 // non-temporal stores (one float per lane and store when unaligned); with accumulate = 1 it adds
 // to the visible rows only. Culled Gaussians point at an all-zero LDS row, so every output value
 // is read the same way, without a branch per value.
-// One wave per block: at 3M Gaussians / 1080p blocks of 64 rows measured 0.212 ms, of 128 rows
-// 0.214 ms and of 256 rows 0.220 ms; more, smaller blocks overlap one block's chain rule with
-// other blocks' writes.
-constexpr int kA7Block = 64;
-constexpr int kA7ZeroRow = kA7Block; // the all-zero row culled Gaussians read
+// One wave of 64 rows per block. At 3M Gaussians / 1080p, with one wave per 64 rows, blocks of
+// 128 and 256 rows measured 0.214 and 0.220 ms against 0.212 ms; with one wave for 128 or 256
+// rows (denser chain-rule lanes, each wave writing more) 0.234 and 0.232 ms against 0.204 ms.
+// More, smaller blocks overlap one block's chain rule with other blocks' writes.
+constexpr int kA7Threads = 64;
+constexpr int kA7Rows = 64;              // Gaussians per block, a multiple of kA7Threads
+constexpr int kA7ZeroRow = kA7Rows;      // the all-zero row culled Gaussians read
 
 template <int DEG>
 struct A7Layout {
@@ -480,7 +482,7 @@ __device__ __forceinline__ void a7_write(float *__restrict__ dst, int count, boo
     typedef float v4f __attribute__((ext_vector_type(4)));
     const int m = count * W;
     if (mode == A7_ADD) {
-        for (int e = threadIdx.x; e < m; e += kA7Block)
+        for (int e = threadIdx.x; e < m; e += kA7Threads)
             if (slot[e / W] != kA7ZeroRow) dst[e] += val(e);
         return;
     }
@@ -488,13 +490,13 @@ __device__ __forceinline__ void a7_write(float *__restrict__ dst, int count, boo
     if (vec) {
         v4f *d4 = reinterpret_cast<v4f *>(dst);
         const int m4 = m / 4;
-        for (int c = threadIdx.x; c < m4; c += kA7Block) {
+        for (int c = threadIdx.x; c < m4; c += kA7Threads) {
             const v4f v = {val(4 * c), val(4 * c + 1), val(4 * c + 2), val(4 * c + 3)};
             __builtin_nontemporal_store(v, d4 + c);
         }
         e0 = m4 * 4;
     }
-    for (int e = e0 + threadIdx.x; e < m; e += kA7Block) dst[e] = val(e);
+    for (int e = e0 + threadIdx.x; e < m; e += kA7Threads) dst[e] = val(e);
 }
 
 // The SH segment (rows of 3K floats, value 3k + ch = Y[k] g[ch]) as 16-byte non-temporal stores,
@@ -519,9 +521,9 @@ __device__ __forceinline__ void a7_write_sh4(float *__restrict__ dst, int count,
     typedef float v4f __attribute__((ext_vector_type(4)));
     v4f *d4 = reinterpret_cast<v4f *>(dst);
     const int m4 = count * F4;
-    // row q and store m within it, stepped as c advances by kA7Block
+    // row q and store m within it, stepped as c advances by kA7Threads
     int q = (int)threadIdx.x / F4, m = (int)threadIdx.x - q * F4;
-    for (int c = threadIdx.x; c < m4; c += kA7Block) {
+    for (int c = threadIdx.x; c < m4; c += kA7Threads) {
         const int c0 = (int)((kA7Mod3 >> (2 * m)) & 3u);
         const int k0 = m + (int)((kA7Div3 >> (2 * m)) & 3u); // floor(4m / 3)
         const float *row = s_row + slot[q] * L::PITCH;
@@ -529,8 +531,8 @@ __device__ __forceinline__ void a7_write_sh4(float *__restrict__ dst, int count,
         const float ga = row[L::G + c0], gb = row[L::G + c0 + 1], gc = row[L::G + c0 + 2];
         const v4f v = {ya * ga, (c0 == 2 ? yb : ya) * gb, (c0 >= 1 ? yb : ya) * gc, yb * ga};
         __builtin_nontemporal_store(v, d4 + c);
-        q += kA7Block / F4;
-        m += kA7Block % F4;
+        q += kA7Threads / F4;
+        m += kA7Threads % F4;
         if (m >= F4) {
             m -= F4;
             ++q;
@@ -539,7 +541,7 @@ __device__ __forceinline__ void a7_write_sh4(float *__restrict__ dst, int count,
 }
 
 template <int DEG, typename AccT>
-__global__ __launch_bounds__(kA7Block) void preprocess_bwd_kernel(int n, const float *__restrict__ means,
+__global__ __launch_bounds__(kA7Threads) void preprocess_bwd_kernel(int n, const float *__restrict__ means,
                                                                   const float *__restrict__ log_scales,
                                                                   const float *__restrict__ quats,
                                                                   const float *__restrict__ opacity_logits,
@@ -549,34 +551,31 @@ __global__ __launch_bounds__(kA7Block) void preprocess_bwd_kernel(int n, const f
                                                                   int mode, int aligned) {
     using L = A7Layout<DEG>;
     constexpr int K = L::K, NS = 3 * K, PITCH = L::PITCH;
-    __shared__ float s_row[(kA7Block + 1) * PITCH];
-    __shared__ int16_t s_slot[kA7Block];   // LDS row of each Gaussian of the block, kA7ZeroRow = culled
-    __shared__ int16_t s_list[kA7Block];   // block-local indices of the visible Gaussians
-    __shared__ int s_wave_count[kA7Block / 64];
-    const int64_t g0 = (int64_t)blockIdx.x * kA7Block;
-    const int count = (int)min<int64_t>(kA7Block, (int64_t)n - g0);
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    __shared__ float s_row[(kA7Rows + 1) * PITCH];
+    __shared__ int16_t s_slot[kA7Rows];   // LDS row of each Gaussian of the block, kA7ZeroRow = culled
+    __shared__ int16_t s_list[kA7Rows];   // block-local indices of the visible Gaussians
+    const int64_t g0 = (int64_t)blockIdx.x * kA7Rows;
+    const int count = (int)min<int64_t>(kA7Rows, (int64_t)n - g0);
+    const int lane = threadIdx.x;
 
-    // ---- list the visible Gaussians in index order (ballot ranks within each wave) ----
-    const bool vis = t < count && radius[g0 + t] > 0;
-    const uint64_t mask = __ballot(vis);
-    if (lane == 0) s_wave_count[wave] = __popcll(mask);
-    for (int k = t; k < PITCH; k += kA7Block) s_row[kA7ZeroRow * PITCH + k] = 0.0f;
-    __syncthreads();
-    int before = 0, nv = 0;
+    // ---- list the visible Gaussians in index order (ballot ranks, 64 rows at a time) ----
+    int nv = 0;
 #pragma unroll
-    for (int w = 0; w < kA7Block / 64; ++w) {
-        before += w < wave ? s_wave_count[w] : 0;
-        nv += s_wave_count[w];
+    for (int r = 0; r < kA7Rows / kA7Threads; ++r) {
+        const int row = r * kA7Threads + lane;
+        const bool vis = row < count && radius[g0 + row] > 0;
+        const uint64_t mask = __ballot(vis);
+        const int rank = nv + __popcll(mask & ((1ull << lane) - 1ull));
+        s_slot[row] = vis ? (int16_t)rank : (int16_t)kA7ZeroRow;
+        if (vis) s_list[rank] = (int16_t)row;
+        nv += __popcll(mask);
     }
-    const int rank = before + __popcll(mask & ((1ull << lane) - 1ull));
-    s_slot[t] = vis ? (int16_t)rank : (int16_t)kA7ZeroRow;
-    if (vis) s_list[rank] = (int16_t)t;
+    for (int k = lane; k < PITCH; k += kA7Threads) s_row[kA7ZeroRow * PITCH + k] = 0.0f;
     __syncthreads();
     if (mode == A7_ADD && nv == 0) return;
 
-    if (t < nv) {
-        // ---- chain rule of the visible ones on the first nv lanes ----
+    for (int t = lane; t < nv; t += kA7Threads) {
+        // ---- chain rule of the visible ones, on dense lanes ----
         const int64_t i = g0 + s_list[t];
         float o[11], Y[K], g[3];
         gaussian_grads<DEG, AccT>(i, means, log_scales, quats, opacity_logits, sh, cam, acc, o, Y, g);
@@ -635,13 +634,13 @@ hipError_t launch_preprocess_fwd(const gsr_scene &s, const DevCamera &cam, float
 hipError_t launch_preprocess_bwd(const gsr_scene &s, const DevCamera &cam, const int32_t *radius, const void *acc,
                                  bool acc_f64, const gsr_grads &out, int accumulate, hipStream_t st) {
     if (s.n <= 0) return hipSuccess;
-    const unsigned blocks = (unsigned)((s.n + kA7Block - 1) / kA7Block);
+    const unsigned blocks = (unsigned)((s.n + kA7Rows - 1) / kA7Rows);
     const auto a16 = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
     const int aligned = a16(out.means3d) && a16(out.log_scales) && a16(out.quats) && a16(out.opacity_logits) &&
                         a16(out.sh);
     const int mode = accumulate ? A7_ADD : A7_ALL;
 #define GSR_PB(D, A)                                                                                               \
-    preprocess_bwd_kernel<D, A><<<blocks, kA7Block, 0, st>>>(s.n, s.means3d, s.log_scales, s.quats,                \
+    preprocess_bwd_kernel<D, A><<<blocks, kA7Threads, 0, st>>>(s.n, s.means3d, s.log_scales, s.quats,                \
                                                               s.opacity_logits, s.sh, cam, radius,                 \
                                                               static_cast<const A *>(acc), out, mode, aligned)
     if (acc_f64) {
