@@ -94,6 +94,9 @@ hipError_t device_exclusive_scan(const uint32_t *in, const uint32_t *gather, uin
 // which sizes the launches); with range_dev = (max ~key, max key) on the device,
 // passes above the keys' highest varying bit copy instead of sorting.
 size_t radix_hist_count(int64_t n);
+// Whether a sort of n items runs without a separate scan launch per pass (few blocks, each
+// deriving its offsets from the histogram table itself).
+bool radix_sort_fused(int64_t n);
 hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n, int bits,
                             uint32_t *hist, uint32_t *partials, int *which, hipStream_t st,
                             const uint32_t *n_dev = nullptr, const uint32_t *range_dev = nullptr);

@@ -540,6 +540,8 @@ size_t radix_hist_count(int64_t n) {
     return (size_t)(b + 4) * kBins + 8; // + 4 columns: a fused table's rows are padded to a multiple of 4
 }
 
+bool radix_sort_fused(int64_t n) { return sort_blocks(n) <= kFusedScanBlocks; }
+
 hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n, int bits,
                             uint32_t *hist, uint32_t *partials, int *which, hipStream_t st, const uint32_t *n_dev,
                             const uint32_t *range_dev) {
@@ -548,12 +550,17 @@ hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *
     const int64_t blocks = sort_blocks(n);
     const bool small = sort_items(n) == 4;
     uint32_t *ks[2] = {k0, k1}, *vs[2] = {v0, v1};
-    // 8-bit digits, the remainder in the last pass, whose table has only 1 << remainder rows (12
-    // bits as 8 + 4 measured faster than as 6 + 6: the narrow last pass has a one-launch scan).
+    // As few passes as 8-bit digits allow. Sorts of 1024-item blocks take 8-bit digits and the
+    // remainder last, whose table has only 1 << remainder rows (12 bits as 8 + 4 measured faster
+    // than as 6 + 6 on 0.8M pairs: the narrow last pass has a one-launch scan). Sorts of 4096-item
+    // blocks split the bits evenly: fewer digits make longer runs per block and digit, so the
+    // scatter writes fuller lines (13 bits on 7.5M pairs: 7 + 6 took 125 us, 8 + 5 134 us).
     const int passes = (bits + 7) / 8;
+    const bool even = !small;
     int cur = 0;
     for (int p = 0, shift = 0; p < passes; ++p) {
-        const int nb = (bits - shift) < 8 ? (bits - shift) : 8;
+        const int rest = bits - shift;
+        const int nb = even ? (rest + (passes - p) - 1) / (passes - p) : (rest < 8 ? rest : 8);
         const hipError_t e =
             small ? radix_pass<4>(ks[cur], vs[cur], ks[cur ^ 1], vs[cur ^ 1], n, shift, nb, blocks, hist, partials,
                                   n_dev, range_dev, st)

@@ -505,11 +505,14 @@ gsr_status render_views(gsr_ctx *ctx, int nv, const gsr_scene *scenes, const gsr
     // a2/a3 (depth digits): stable sort of the visible Gaussians by fp32 depth (ties keep index
     // order). Bits above the highest one in which the smallest and the largest visible key differ
     // are the same in every key and need no pass (for an object seen from outside the exponent
-    // byte of every depth is the same). One view: the sort is enqueued before the host waits for
-    // the counts, launched for all n Gaussians and bounded by the visible count and key range
-    // on the device (passes above the varying bits copy), so the GPU sorts while the counts
-    // travel. Several views share one wait: each view's sort is sized by its read-back count.
-    const bool overlap = nv == 1;
+    // byte of every depth is the same). One view whose sort of all n Gaussians needs no scan
+    // launches: the sort is enqueued before the host waits for the counts, launched for all n
+    // and bounded by the visible count and key range on the device (passes above the varying
+    // bits copy), so the GPU sorts while the counts travel. Otherwise, and for several views
+    // (which share one wait), each view's sort is sized by its read-back count and key range:
+    // at 3M Gaussians / 1080p (0.7M visible) that took 115 us against 144 us for the sort of
+    // all n bounded on the device; at 100k / 800x800 the bounded sort took 61 us against 69.
+    const bool overlap = nv == 1 && radix_sort_fused(sts[0]->n);
     if (overlap) {
         gsr_fwd *st = sts[0];
         int which = 0;
