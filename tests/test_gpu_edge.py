@@ -212,11 +212,12 @@ def test_backward_counters_match_the_atomic_count_model(renderer):
             gsr.gsr_fwd_release(renderer.ctx, st)
 
 
-@pytest.mark.parametrize("degree", [0, 3])
+@pytest.mark.parametrize("degree", [0, 1, 2, 3])
 def test_gradient_outputs_unaligned_and_accumulated(renderer, degree):
     # The per-Gaussian gradients leave as 16-byte stores when every output is 16-byte aligned
-    # and a block of 256 Gaussians is full, else one float at a time: both paths, and
-    # accumulate = 1 on both, must write the same values bit for bit.
+    # (SH rows of degrees 1 and 3 are whole 16-byte groups, stored group by group; degrees 0
+    # and 2 go float by float), else one float at a time: both paths, and accumulate = 1 on
+    # both, must write the same values bit for bit. 777 Gaussians leave a ragged last block.
     import torch
     say(f"[gpu] unaligned / accumulated gradient outputs, SH degree {degree}")
     wl = sg.tiny_scene(9, 777, 48, 40, sh_degree=degree, log_scale=(-2.4, 0.4), half=0.8)
