@@ -154,7 +154,7 @@ class Bench:
 
     def backward_only(self, fr, cfg, iters, clear=None):
         """Backward repeated on one forward state; returns per-iteration (a6, a7) ms lists (and the
-        accumulator clearing's ms in `clear` when given)."""
+        ms of the accumulator clearing and tile ordering before a6 in `clear` when given)."""
         a6, a7 = [], []
         for _ in range(iters):
             self.gsr.gsr_backward(self.r.ctx, fr.state, self.dl, self.gstruct, 0, cfg)
@@ -532,7 +532,7 @@ def ab_summary(res, cnt, stats, thr, sweep):
         "plain_atomic_ms": round(pz + p6 + p7, 4),
         "plain_atomic_f64_ms": round(qz + q6 + q7, 4),
         "wave_reduce_acc_f32_ms": round(wz + w6 + w7, 4),
-        "clear_accumulators_ms": round(rz, 4),
+        "clear_and_tile_order_ms": round(rz, 4),
         "composite_bwd_wave_reduce_ms": round(r6, 4),
         "preprocess_bwd_ms": round(r7, 4),
         "composite_bwd_plain_ms": round(p6, 4),

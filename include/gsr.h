@@ -186,7 +186,9 @@ typedef struct {
 } gsr_bwd_counters_t;
 
 /* Milliseconds of the stages of the last gsr_render / gsr_backward with
- * GSR_FLAG_STAGE_TIMING (HIP events on the context stream). */
+ * GSR_FLAG_STAGE_TIMING (HIP events on the context stream). zero_acc covers
+ * the clearing of the accumulator rows and the building of the backward's
+ * tile order; composite_bwd the backward composite launch alone. */
 typedef struct {
     float preprocess, depth_sort, scan_emit, tile_sort, ranges, composite_fwd;
     float zero_acc, composite_bwd, preprocess_bwd;

@@ -245,7 +245,7 @@ struct gsr_fwd {
     uint4 *vis_part = nullptr;          // per-block statistics of the visible-Gaussian compaction
     uint2 *ranges = nullptr;
     uint32_t *tile_walk = nullptr; // deepest n_contrib per tile (ordered renders)
-    uint2 *order_bwd = nullptr;    // this view's tiles by decreasing walk (single-view backward)
+    uint2 *order_bwd = nullptr;    // table a single-view backward orders its tiles in (rebuilt by each)
     uint2 *batch_work = nullptr;   // (view, tile) table of a batched backward led by this state
     int64_t batch_work_cap = 0;
     float *T_final = nullptr;

@@ -411,8 +411,9 @@ gsr_status enqueue_project_and_depth_sort(gsr_ctx *ctx, int nv, gsr_fwd *const *
     return GSR_OK;
 }
 
-// a5 for every view in one launch (longest list first), then each view's tile_walk orders
-// its backward. work: a table of base[nv] entries for the launch (nullptr: a pool temp).
+// a5 for every view in one launch (longest list first); it records each tile's deepest
+// n_contrib (tile_walk), from which the backward orders its tiles. work: a table of base[nv]
+// entries for the launch (nullptr: a pool temp).
 gsr_status enqueue_composite_fwd(gsr_ctx *ctx, int nv, gsr_fwd *const *sts, float *const *images,
                                  const gsr_config *config, uint2 *work_buf, bool tm) {
     hipStream_t s = ctx->stream;
@@ -436,11 +437,6 @@ gsr_status enqueue_composite_fwd(gsr_ctx *ctx, int nv, gsr_fwd *const *sts, floa
         }
         const int remap = (nv == 1 && (config->flags & GSR_FLAG_XCD_REMAP)) ? 1 : 0;
         GSR_HIP(ctx, launch_composite_fwd(vb, config->tile, config->lds_batch, remap, work, s));
-    }
-    if (ordered && nv == 1) {
-        gsr_fwd *st = sts[0];
-        if (!st->order_bwd) GSR_TRY(pool_alloc(ctx, st, &st->order_bwd, st->n_tiles));
-        GSR_HIP(ctx, launch_order_tiles(vb, ORDER_BY_WALK, st->order_bwd, s));
     }
     mark(ctx, tm, EV_R6);
     return GSR_OK;
@@ -689,11 +685,9 @@ gsr_status bwd_prepare(gsr_ctx *ctx, int nv, gsr_fwd *const *sts, const float *c
     if (nv == 1) {
         if (ordered) {
             gsr_fwd *st = sts[0];
-            if (!st->order_bwd) {
-                GSR_TRY(pool_alloc(ctx, st, &st->order_bwd, st->n_tiles));
-                GSR_HIP(ctx, launch_order_tiles(vb, plan.order_mode, st->order_bwd, ctx->stream));
-            }
+            if (!st->order_bwd) GSR_TRY(pool_alloc(ctx, st, &st->order_bwd, st->n_tiles));
             plan.work = st->order_bwd;
+            plan.build_work = true;
         }
     } else {
         gsr_fwd *lead = sts[0];
@@ -725,8 +719,10 @@ gsr_status bwd_enqueue(gsr_ctx *ctx, int nv, gsr_fwd *const *sts, const gsr_conf
         if (plan.own_acc) sts[v]->acc_f64 = f64;
     }
     if (count) GSR_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t *>(sts[0]->counters), 0u, 160, s));
-    mark(ctx, tm, EV_B1);
+    // The tiles' order for this backward (longest recorded walk first), built from the walks of
+    // the render it follows; timed with the clearing, so the composite's span is its kernel alone.
     if (plan.build_work) GSR_HIP(ctx, launch_order_tiles(plan.vb, plan.order_mode, plan.work, s));
+    mark(ctx, tm, EV_B1);
     BwdParams p{};
     p.counters = count ? sts[0]->counters : nullptr;
     p.threshold = cfg->reduce_threshold < 1 ? 1 : cfg->reduce_threshold;
@@ -764,12 +760,10 @@ void bwd_plan_scratch(gsr_ctx *ctx, gsr_fwd *st, const float *dl, const gsr_conf
     plan.build_work = false;
     plan.own_acc = false;
     if (ordered) {
-        if (st->order_bwd) {
-            plan.work = st->order_bwd;
-        } else {
-            plan.work = reinterpret_cast<uint2 *>(static_cast<unsigned char *>(ctx->scratch) + kNoallocRowBytes);
-            plan.build_work = true;
-        }
+        plan.work = st->order_bwd ? st->order_bwd
+                                  : reinterpret_cast<uint2 *>(static_cast<unsigned char *>(ctx->scratch) +
+                                                              kNoallocRowBytes);
+        plan.build_work = true;
     }
 }
 
