@@ -161,6 +161,10 @@ hipError_t launch_composite_fwd(const ViewBatch &vb, int tile, int lds_batch, in
 // The batch's (view, tile) pairs, base[n] of them: in index order (ORDER_IDENTITY) or by
 // decreasing work (list length, or each view's tile_walk).
 hipError_t launch_order_tiles(const ViewBatch &vb, int mode, uint2 *work, hipStream_t st);
+// One view (vb.n == 1): the tile order as launch_order_tiles and, in the same launch, the
+// accumulator rows of the m listed Gaussians (m_dev: the count on the device, nullable) cleared.
+hipError_t launch_clear_rows_and_order(const ViewBatch &vb, int mode, uint2 *work, const uint32_t *ids, int64_t m,
+                                       const uint32_t *m_dev, void *acc, bool acc_f64, hipStream_t st);
 
 // a6: backward composite.
 struct BwdParams {

@@ -535,7 +535,7 @@ __global__ __launch_bounds__(256) void l1_grad_kernel(const float *image, const 
 // its list length. Counting sort on a log-scale bucket of the work (16
 // buckets per octave), one block.
 
-__global__ __launch_bounds__(1024) void order_tiles_kernel(ViewBatch vb, int mode, uint2 *work) {
+__device__ __forceinline__ void order_tiles_block(const ViewBatch &vb, int mode, uint2 *work) {
     __shared__ uint32_t s_count[256];
     // The views' tile bases and work arrays, copied once: indexing the by-value argument with a
     // per-item view number would reload them from memory for every item.
@@ -640,6 +640,29 @@ __global__ __launch_bounds__(1024) void order_tiles_kernel(ViewBatch vb, int mod
     }
 }
 
+__global__ __launch_bounds__(1024) void order_tiles_kernel(ViewBatch vb, int mode, uint2 *work) {
+    order_tiles_block(vb, mode, work);
+}
+
+// One view's backward set-up in one launch: block 0 builds the tile order (as
+// order_tiles_kernel), the other blocks clear the listed accumulator rows, one thread per
+// 16-byte chunk so that consecutive threads fill whole rows; the order's one-block latency
+// overlaps the clearing's writes. m_dev (nullable): the list's length on the device, at most m.
+__global__ __launch_bounds__(1024) void clear_rows_and_order_kernel(ViewBatch vb, int mode, uint2 *work,
+                                                                     const uint32_t *ids, int64_t m,
+                                                                     const uint32_t *m_dev, uint4 *acc,
+                                                                     int chunks) {
+    if (blockIdx.x == 0) {
+        order_tiles_block(vb, mode, work);
+        return;
+    }
+    const int64_t t = (int64_t)(blockIdx.x - 1) * blockDim.x + threadIdx.x;
+    const int64_t v = t / chunks;
+    if (m_dev && (int64_t)*m_dev < m) m = *m_dev;
+    if (v >= m) return;
+    acc[(int64_t)ids[v] * chunks + (t - v * chunks)] = make_uint4(0u, 0u, 0u, 0u);
+}
+
 template <int TILE, int BATCH>
 hipError_t fwd_t(const ViewBatch &vb, int remap, const uint2 *work, hipStream_t st) {
     const int n_tiles = vb.v[0].cam.grid_x * vb.v[0].cam.grid_y;
@@ -690,6 +713,17 @@ hipError_t bwd_t(const ViewBatch &vb, int remap, int mode, bool count, bool spli
 hipError_t launch_order_tiles(const ViewBatch &vb, int mode, uint2 *work, hipStream_t st) {
     if (vb.n <= 0 || vb.base[vb.n] == 0) return hipSuccess;
     order_tiles_kernel<<<1, 1024, 0, st>>>(vb, mode, work);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_rows_and_order(const ViewBatch &vb, int mode, uint2 *work, const uint32_t *ids, int64_t m,
+                                       const uint32_t *m_dev, void *acc, bool acc_f64, hipStream_t st) {
+    if (vb.n != 1) return hipErrorInvalidValue;
+    const int chunks = GSR_ACC_STRIDE * (acc_f64 ? 8 : 4) / 16;
+    const int64_t threads = (m > 0 ? m : 0) * chunks;
+    const unsigned blocks = (unsigned)(1 + (threads + 1023) / 1024);
+    clear_rows_and_order_kernel<<<blocks, 1024, 0, st>>>(vb, mode, work, ids, m > 0 ? m : 0, m_dev,
+                                                         static_cast<uint4 *>(acc), chunks);
     return hipGetLastError();
 }
 

@@ -708,20 +708,27 @@ gsr_status bwd_enqueue(gsr_ctx *ctx, int nv, gsr_fwd *const *sts, const gsr_conf
     const bool f64 = (cfg->flags & GSR_FLAG_ACC_F32) == 0;
     for (int v = 0; v < nv; ++v) sts[v]->counters_valid = false;
     mark(ctx, tm, EV_B0);
+    // The tiles' order for this backward (longest recorded walk first), built from the walks of
+    // the render it follows, is timed with the clearing, so the composite's span is its kernel
+    // alone; for one view both go in one launch.
+    const bool fused = nv == 1 && plan.build_work;
     for (int v = 0; v < nv; ++v) {
         // The depth-sorted ids start with the visible Gaussians (culled ones carry the largest
         // key): after a render that read its counts back they are exactly those; after a
         // capacity-mode render their count is on the device.
         const gsr_fwd *sv = sts[v];
-        GSR_HIP(ctx, launch_zero_visible_rows(sv->radius, sv->n, sv->sorted_ids_by_depth,
-                                              sv->p_known ? sv->n_visible : sv->n,
-                                              sv->p_known ? nullptr : sv->totals + 1, plan.vb.v[v].acc, f64, s));
+        const int64_t m = sv->p_known ? sv->n_visible : sv->n;
+        const uint32_t *m_dev = sv->p_known ? nullptr : sv->totals + 1;
+        if (fused)
+            GSR_HIP(ctx, launch_clear_rows_and_order(plan.vb, plan.order_mode, plan.work, sv->sorted_ids_by_depth, m,
+                                                     m_dev, plan.vb.v[v].acc, f64, s));
+        else
+            GSR_HIP(ctx, launch_zero_visible_rows(sv->radius, sv->n, sv->sorted_ids_by_depth, m, m_dev,
+                                                  plan.vb.v[v].acc, f64, s));
         if (plan.own_acc) sts[v]->acc_f64 = f64;
     }
     if (count) GSR_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t *>(sts[0]->counters), 0u, 160, s));
-    // The tiles' order for this backward (longest recorded walk first), built from the walks of
-    // the render it follows; timed with the clearing, so the composite's span is its kernel alone.
-    if (plan.build_work) GSR_HIP(ctx, launch_order_tiles(plan.vb, plan.order_mode, plan.work, s));
+    if (plan.build_work && !fused) GSR_HIP(ctx, launch_order_tiles(plan.vb, plan.order_mode, plan.work, s));
     mark(ctx, tm, EV_B1);
     BwdParams p{};
     p.counters = count ? sts[0]->counters : nullptr;
