@@ -367,10 +367,12 @@ __global__ __launch_bounds__(kThreads) void radix_hist_kernel(const uint32_t *ke
     // A narrow digit (the top pass of the tile sort: a few dozen values over long sorted runs)
     // puts many lanes of a wave on one LDS counter, where their atomics serialise: lanes find
     // their equal-digit peers with one ballot per bit and one lane adds the group's size. Wide
-    // digits vary from lane to lane and keep one atomic per lane (measured faster there).
+    // digits vary from lane to lane and keep one atomic per lane (measured faster there: on the
+    // 7.5M-pair tile sort at 1080p, peers up to 6 bits took 122.5 us, up to 8 bits 136 us, up
+    // to 5 bits 127 us).
     const int nbits = __popc(mask);
     const int lane = threadIdx.x & 63;
-    if (nbits <= 5) {
+    if (nbits <= 6) {
 #pragma unroll
         for (int r = 0; r < ITEMS; ++r) {
             const bool valid = pos(r) < n;
