@@ -122,12 +122,13 @@ __device__ __forceinline__ uint32_t emit9(bool active, uint64_t m, float (&v)[9]
 // can pass entry j only if the splat's quadratic form (log2(e)/2) d^T K d (K
 // the conic, d the offset from its centre; the staged units) is at most
 // log2(255 o) at that lane's sample point. The test takes the minimum of the
-// form over the square holding all
-// 8x8 sample points of the wave, widened by half a pixel: zero when the
-// centre lies inside, else the least of the four edge minima (each a clamped
-// one-dimensional quadratic). Being a minimum over a superset of the sample
-// points, with an absolute slack of 1e-3, it never drops an entry some lane
-// passes. Lane l tests entries l, l+64, ... so the walk loops need no
+// form over the square spanned by the wave's 8x8 sample points (the pixel
+// centres, qc +- 3.5 in each axis): zero when the centre lies inside, else
+// the least of the four edge minima (each a clamped one-dimensional
+// quadratic). Being a minimum over a superset of the sample points, with an
+// absolute slack of 1e-3, it never drops an entry some lane passes. (The
+// square widened by half a pixel more kept 7 % more entries that no lane
+// takes.) Lane l tests entries l, l+64, ... so the walk loops need no
 // per-entry test and skip the rest with scalar bit scans.
 __device__ __forceinline__ float edge_min(float d, float lo, float hi, float kd, float kcross, float ko) {
     // min over e in [lo, hi] of kd d^2 + 2 kcross d e + ko e^2 (ko > 0)
@@ -147,9 +148,9 @@ __device__ __forceinline__ void wave_visit_masks(const float4 *s0, const float4 
             const float4 r = s0[j];
             // the staged form is -log2(e)/2 (d^T K d): (ka, kb, kc) = its negation as (A, B, C)
             const float ka = -r.z, kb = -0.5f * r.w, kc = -s1[j].x, reach = s2[j].z;
-            // square [qc - 4, qc + 4]^2 relative to the splat centre
-            const float lx = qcx - 4.0f - r.x, hx = qcx + 4.0f - r.x;
-            const float ly = qcy - 4.0f - r.y, hy = qcy + 4.0f - r.y;
+            // square [qc - 3.5, qc + 3.5]^2 relative to the splat centre
+            const float lx = qcx - 3.5f - r.x, hx = qcx + 3.5f - r.x;
+            const float ly = qcy - 3.5f - r.y, hy = qcy + 3.5f - r.y;
             const bool inside = lx <= 0.0f && hx >= 0.0f && ly <= 0.0f && hy >= 0.0f;
             float fmin = 0.0f;
             if (!(ka > 0.0f && kc > 0.0f && ka * kc - kb * kb > 0.0f)) {
