@@ -694,7 +694,15 @@ def main():
     backward["p50_backward_ms"] = round(float(np.percentile(bwd, 50)), 4)
     backward["p99_backward_ms"] = round(float(np.percentile(bwd, 99)), 4)
     log(f"[bench] A/B a6: plain {res['plain_f32'][0]:.3f} ms, reduce {res['reduce_f64'][0]:.3f} ms")
-    roofline = rooflines(wl, fstats, cnt["reduce"], res["reduce_f64"][0], res["reduce_f64"][1])
+    # The kernels' launch times over the timed region (its steps' events), when it runs the
+    # wave-reduced backward; the A/B legs repeat the backward on one warm state and run a few
+    # per cent faster.
+    if MODES[args.mode] == gsr.GSR_BWD_WAVE_REDUCE:
+        roofline = rooflines(wl, fstats, cnt["reduce"], float(a6.mean()), float(a7.mean()))
+        roofline["timing"] = f"mean over the {args.steps} timed steps"
+    else:
+        roofline = rooflines(wl, fstats, cnt["reduce"], res["reduce_f64"][0], res["reduce_f64"][1])
+        roofline["timing"] = "median of the wave-reduce A/B leg"
 
     out = {
         "metric": "3DGS backward ms/iter + TCC atomics, wave-reduce vs plain atomics; p99 step lat",
@@ -759,7 +767,9 @@ def main():
                 per2.append(st2)
         res2, cnt2, stats2 = ab_legs(b2, thr2, 10)
         leg = ab_summary(res2, cnt2, stats2, thr2, s2)
-        leg["roofline"] = rooflines(wl2, stats2, cnt2["reduce"], res2["reduce_f64"][0], res2["reduce_f64"][1])
+        leg["roofline"] = rooflines(wl2, stats2, cnt2["reduce"], float(np.mean([s.composite_bwd for s in per2])),
+                                    float(np.mean([s.preprocess_bwd for s in per2])))
+        leg["roofline"]["timing"] = f"mean over {len(per2)} steps"
         leg["step_render_ms"] = round(float(np.mean([s.preprocess + s.depth_sort + s.scan_emit + s.tile_sort +
                                                      s.ranges + s.composite_fwd for s in per2])), 4)
         leg["forward_stages_ms"] = {k: round(float(np.mean([getattr(s, k) for s in per2])), 4)
