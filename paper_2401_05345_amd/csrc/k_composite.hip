@@ -521,14 +521,6 @@ __global__ __launch_bounds__(64) void wave_reduce_selftest_kernel(const float *v
     if (issued) atomicAdd(lane_atomics, (unsigned long long)issued);
 }
 
-__global__ __launch_bounds__(256) void l1_grad_kernel(const float *image, const float *target, int64_t count,
-                                                       float inv, float *out) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= count) return;
-    const float d = image[i] - target[i];
-    out[i] = d > 0.0f ? inv : (d < 0.0f ? -inv : 0.0f);
-}
-
 // The batch's (view, tile) pairs in index order, or ordered by decreasing
 // work (longest first, so the dispatcher's greedy assignment of workgroups to
 // free CUs approximates longest-processing-time scheduling; a batch of views
@@ -759,12 +751,6 @@ hipError_t launch_composite_bwd(const ViewBatch &vb, int t, int lds_batch, int r
     if (lds_batch == 128) GSR_B(32, 128);
     GSR_B(32, 256);
 #undef GSR_B
-}
-
-hipError_t launch_l1_grad(const float *image, const float *target, int64_t count, float *out, hipStream_t st) {
-    if (count <= 0) return hipSuccess;
-    l1_grad_kernel<<<(unsigned)((count + 255) / 256), 256, 0, st>>>(image, target, count, 1.0f / (float)count, out);
-    return hipGetLastError();
 }
 
 hipError_t launch_wave_reduce_selftest(const float *vals, const uint8_t *active, int n_waves, int mode,

@@ -194,6 +194,30 @@ __global__ __launch_bounds__(256) void ssim_finalize_kernel(const float *sums, i
         loss[0] = (float)((1.0 - (double)lambda) * red[1][0] * inv_n + (double)lambda * (1.0 - red[0][0] * inv_n));
 }
 
+// dL/dimage of the mean absolute error: sign(image - target) / count (0 where they are equal).
+__device__ __forceinline__ float l1_sign(float a, float b, float inv) {
+    const float d = a - b;
+    return d > 0.0f ? inv : (d < 0.0f ? -inv : 0.0f);
+}
+
+__global__ __launch_bounds__(256) void l1_grad_kernel(const float *image, const float *target, int64_t count,
+                                                       float inv, float *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    out[i] = l1_sign(image[i], target[i], inv);
+}
+
+// The same four values per thread as 16-byte loads and stores (16-byte aligned arrays; the
+// count's remainder below 4 goes through l1_grad_kernel).
+__global__ __launch_bounds__(256) void l1_grad4_kernel(const float4 *image, const float4 *target, int64_t count4,
+                                                        float inv, float4 *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count4) return;
+    const float4 a = image[i], b = target[i];
+    out[i] = make_float4(l1_sign(a.x, b.x, inv), l1_sign(a.y, b.y, inv), l1_sign(a.z, b.z, inv),
+                         l1_sign(a.w, b.w, inv));
+}
+
 } // namespace
 
 hipError_t launch_l1_dssim_grad(const float *img, const float *ref, int C, int W, int H, float lambda, float *dmu,
@@ -225,6 +249,28 @@ hipError_t launch_l1_dssim_grad(const float *img, const float *ref, int C, int W
 
 size_t dssim_partial_count(int C, int W, int H) {
     return 2 * (size_t)((W + TX - 1) / TX) * ((H + TY - 1) / TY) * (C > 0 ? C : 1);
+}
+
+hipError_t launch_l1_grad(const float *image, const float *target, int64_t count, float *out, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    const float inv = 1.0f / (float)count;
+    const auto a16 = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+    int64_t done = 0;
+    if (a16(image) && a16(target) && a16(out)) {
+        const int64_t count4 = count / 4;
+        if (count4 > 0) {
+            l1_grad4_kernel<<<(unsigned)((count4 + 255) / 256), 256, 0, st>>>(
+                reinterpret_cast<const float4 *>(image), reinterpret_cast<const float4 *>(target), count4, inv,
+                reinterpret_cast<float4 *>(out));
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        done = 4 * count4;
+    }
+    if (done < count)
+        l1_grad_kernel<<<(unsigned)((count - done + 255) / 256), 256, 0, st>>>(image + done, target + done,
+                                                                           count - done, inv, out + done);
+    return hipGetLastError();
 }
 
 } // namespace gsr
