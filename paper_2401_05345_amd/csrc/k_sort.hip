@@ -579,18 +579,33 @@ hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *
 // ---------------------------------------------------------------------------
 namespace {
 
+// Inclusive prefix maximum over the 64 lanes (signed), in DPP steps: row shifts by 1, 2, 4 and
+// 8 within each 16-lane row, then the row broadcasts of lanes 15 and 31 (lanes a step has no
+// source for keep their value).
+__device__ __forceinline__ int wave_prefix_max(int v) {
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x111, 0xF, 0xF, false)); // row_shr:1
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x112, 0xF, 0xF, false)); // row_shr:2
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x114, 0xF, 0xF, false)); // row_shr:4
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x118, 0xF, 0xF, false)); // row_shr:8
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x142, 0xA, 0xF, false)); // row_bcast:15
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x143, 0xC, 0xF, false)); // row_bcast:31
+    return v;
+}
+
 // A wave takes 64 consecutive depth-ordered Gaussians and writes their pairs together: the
 // wave's pairs are one contiguous run of the list (each Gaussian's rectangle row by row, the
 // Gaussians in depth order), so lane l writes entries l, l + 64, ... of that run and each
 // store instruction covers consecutive addresses. Entry k belongs to the last of the 64
-// Gaussians whose exclusive prefix count is at most k (a six-step search over the wave's
-// prefix counts in LDS).
+// Gaussians whose exclusive prefix count is at most k. For each window of 64 entries, every
+// Gaussian with pairs that starts inside the window marks its start in LDS with its index,
+// and a prefix maximum over the lanes carries each mark to the entries after it (entries
+// before the window's first mark belong to the Gaussian that ended the previous window).
 __global__ __launch_bounds__(256) void emit_pairs_kernel(int64_t n, const uint32_t *sorted_ids,
                                                           const uint32_t *offsets, const float4 *rec,
                                                           const int32_t *radius, DevCamera cam, uint32_t *pair_tile,
                                                           uint32_t *pair_id, uint32_t cap) {
     __shared__ uint32_t s_pre[4][64], s_off[4][64], s_g[4][64];
-    __shared__ int s_x0[4][64], s_y0[4][64], s_w[4][64];
+    __shared__ int s_x0[4][64], s_y0[4][64], s_w[4][64], s_mark[4][64];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int x0 = 0, x1 = 0, y0 = 0, y1 = 0;
@@ -611,7 +626,8 @@ __global__ __launch_bounds__(256) void emit_pairs_kernel(int64_t n, const uint32
         const uint32_t t = (uint32_t)__shfl_up((int)inc, d, 64);
         if (lane >= d) inc += t;
     }
-    s_pre[wave][lane] = inc - cnt;
+    const uint32_t pre = inc - cnt;
+    s_pre[wave][lane] = pre;
     s_off[wave][lane] = o;
     s_g[wave][lane] = g;
     s_x0[wave][lane] = x0;
@@ -619,16 +635,25 @@ __global__ __launch_bounds__(256) void emit_pairs_kernel(int64_t n, const uint32
     s_w[wave][lane] = x1 - x0;
     __syncthreads();
     const uint32_t total = (uint32_t)__shfl((int)inc, 63, 64);
-    for (uint32_t k = (uint32_t)lane; k < total; k += 64) {
-        int j = 0;
-#pragma unroll
-        for (int step = 32; step >= 1; step >>= 1)
-            if (s_pre[wave][j + step] <= k) j += step;
+    int carry = -1; // the Gaussian that owns the entry before the window
+    for (uint32_t w0 = 0; w0 < total; w0 += 64) {
+        s_mark[wave][lane] = -1;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (cnt > 0 && pre >= w0 && pre - w0 < 64u) s_mark[wave][pre - w0] = lane;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int j = max(wave_prefix_max(s_mark[wave][lane]), carry);
+        carry = __builtin_amdgcn_readlane(j, 63);
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t k = w0 + (uint32_t)lane;
+        if (k >= total) continue;
         const uint32_t local = k - s_pre[wave][j];
         const uint32_t w = (uint32_t)s_w[wave][j];
         const uint32_t row = local / w;
         const uint32_t oo = s_off[wave][j] + local;
-        if (oo < cap) { // pairs past the buffer's capacity are dropped (pad_pairs flags it)
+        if (oo < cap) { // pairs past the buffer's capacity are dropped (the overflow word flags it)
             pair_tile[oo] = (uint32_t)((s_y0[wave][j] + (int)row) * cam.grid_x + s_x0[wave][j] + (int)(local - row * w));
             pair_id[oo] = s_g[wave][j];
         }
